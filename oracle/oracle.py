@@ -1,0 +1,184 @@
+"""ctypes front-end of the FP64 CPU oracle in ``gevp_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The product package never imports it.
+
+Every function takes and returns numpy arrays in the mathematical sense
+(``A[i, j]`` is row i, column j); conversion to the column-major storage the C
+code reads happens here.  Only the lower triangles of A and B are read, the
+LAPACK ``uplo='L'`` convention.
+
+Functions and the parts of the paper they follow:
+
+* ``solve``            -- lowest ``nev`` eigenpairs of A x = lambda B x with
+                          B Hermitian positive definite (section 1, eq. (3);
+                          the "full data" direct iteration of section 2).
+* ``residuals``        -- ||A x_i - lambda_i B x_i||_2 and max |X^H B X - I|.
+* ``pair_residual``    -- the same for one pair, O(n^2): for sampled checks.
+* ``inertia``          -- number of eigenvalues below sigma (Sylvester).
+* ``bisect``           -- k-th eigenvalue by bisection on inertia counts.
+* ``inverse_iteration``-- eigenvector at a given eigenvalue estimate.
+* ``grad``             -- gradient of sum_i w_i lambda_i with respect to A, B.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # type: ignore
+
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        lib.oref_solve.argtypes = [I, P, I, P, I, I, P, P, I]
+        lib.oref_solve.restype = I
+        lib.oref_residuals.argtypes = [I, P, I, P, I, I, P, P, I, P, P]
+        lib.oref_residuals.restype = None
+        lib.oref_pair_residual.argtypes = [I, P, I, P, I, D, P, P, P]
+        lib.oref_pair_residual.restype = None
+        lib.oref_inertia.argtypes = [I, P, I, P, I, D]
+        lib.oref_inertia.restype = ctypes.c_long
+        lib.oref_bisect.argtypes = [I, P, I, P, I, I, D, D, D]
+        lib.oref_bisect.restype = D
+        lib.oref_inverse_iteration.argtypes = [I, P, I, P, I, D, I, P]
+        lib.oref_inverse_iteration.restype = None
+        lib.oref_grad.argtypes = [I, I, P, I, P, P, P, I, P, I]
+        lib.oref_grad.restype = None
+        lib.oref_potrf.argtypes = [I, P, I]
+        lib.oref_potrf.restype = I
+        _lib = lib
+    return _lib
+
+
+def _colmajor(M):
+    return np.asfortranarray(np.asarray(M, dtype=np.complex128))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, n):
+        self.code = code
+        if code > n:
+            msg = f"B is not positive definite (Cholesky pivot {code - n})"
+        elif code == 1:
+            msg = "tridiagonal QR did not converge"
+        else:
+            msg = f"invalid argument {-code}"
+        super().__init__(msg)
+
+
+def solve(A, B, nev):
+    """Lowest ``nev`` eigenpairs (lam ascending, X B-orthonormal, phase
+    normalised so the largest-modulus entry of each column is real > 0)."""
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    n = A.shape[0]
+    lam = np.empty(nev, dtype=np.float64)
+    X = np.empty((n, nev), dtype=np.complex128, order="F")
+    rc = lib.oref_solve(n, _ptr(A), n, _ptr(B), n, nev, _ptr(lam), _ptr(X), n)
+    if rc != 0:
+        raise OracleError(rc, n)
+    return lam, np.array(X)
+
+
+def solve_status(A, B, nev):
+    """Like ``solve`` but returns the raw status code instead of raising."""
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    n = A.shape[0]
+    lam = np.empty(max(nev, 1), dtype=np.float64)
+    X = np.empty((n, max(nev, 1)), dtype=np.complex128, order="F")
+    return lib.oref_solve(n, _ptr(A), n, _ptr(B), n, nev, _ptr(lam), _ptr(X), n)
+
+
+def residuals(A, B, lam, X):
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    X = _colmajor(X)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    n, m = X.shape
+    res = np.empty(m, dtype=np.float64)
+    orth = np.zeros(1, dtype=np.float64)
+    lib.oref_residuals(n, _ptr(A), n, _ptr(B), n, m, _ptr(lam), _ptr(X), n, _ptr(res), _ptr(orth))
+    return res, float(orth[0])
+
+
+def pair_residual(A, B, lam_i, x):
+    """(||A x - lam B x||_2, x^H B x) for one pair; A, B may be column-major
+    device-sized host arrays (only the lower triangles are read)."""
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    n = A.shape[0]
+    r = np.zeros(1)
+    q = np.zeros(1)
+    lib.oref_pair_residual(n, _ptr(A), n, _ptr(B), n, float(lam_i), _ptr(x), _ptr(r), _ptr(q))
+    return float(r[0]), float(q[0])
+
+
+def inertia(A, B, sigma):
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    n = A.shape[0]
+    return int(lib.oref_inertia(n, _ptr(A), n, _ptr(B), n, float(sigma)))
+
+
+def bisect(A, B, k, lo, hi, tol=1e-14):
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    n = A.shape[0]
+    return float(lib.oref_bisect(n, _ptr(A), n, _ptr(B), n, int(k), float(lo), float(hi), float(tol)))
+
+
+def inverse_iteration(A, B, mu, x0, iters=3):
+    lib = _load()
+    A = _colmajor(A)
+    B = _colmajor(B)
+    x = np.array(x0, dtype=np.complex128)
+    n = A.shape[0]
+    lib.oref_inverse_iteration(n, _ptr(A), n, _ptr(B), n, float(mu), int(iters), _ptr(x))
+    return x
+
+
+def grad(X, lam, w):
+    """G_A = X diag(w) X^H and G_B = -X diag(w * lam) X^H."""
+    lib = _load()
+    X = _colmajor(X)
+    n, m = X.shape
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    GA = np.empty((n, n), dtype=np.complex128, order="F")
+    GB = np.empty((n, n), dtype=np.complex128, order="F")
+    lib.oref_grad(n, m, _ptr(X), n, _ptr(lam), _ptr(w), _ptr(GA), n, _ptr(GB), n)
+    return np.array(GA), np.array(GB)
+
+
+def cholesky(B):
+    """Lower Cholesky factor of B (lower triangle read); raises if not HPD."""
+    lib = _load()
+    n = B.shape[0]
+    L = np.array(np.tril(B), dtype=np.complex128, order="F")
+    rc = lib.oref_potrf(n, _ptr(L), n)
+    if rc:
+        raise OracleError(n + rc, n)
+    return np.array(L)
