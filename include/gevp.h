@@ -1,0 +1,209 @@
+/*
+ * gevp.h -- C ABI of the MI355X seeded solver for sequences of dense complex
+ * Hermitian generalized eigenproblems.
+ *
+ * The problem (the paper, section 1, eq. (3) and the paragraph before it):
+ * for every k-point and every outer SCF iteration, find the lowest nev
+ * eigenpairs of A x = lambda B x, A Hermitian (the Hamiltonian), B Hermitian
+ * positive definite (the overlap), eigenvalues in ascending order (eq. (1)).
+ * Successive iterations form a chain of correlated problems, and the previous
+ * iteration's eigenvectors seed the next solve (section 2, first paragraph and
+ * paragraph "Eigenvectors evolution").
+ *
+ * Method: Cholesky reduction to standard form C = L^{-1} A L^{-H}, then a
+ * Chebyshev-filtered subspace iteration started from the seed block, with
+ * CholQR orthonormalisation, Rayleigh-Ritz and residual-based locking, then
+ * X = L^{-H} Y.  The paper names an improved subspace iteration as the
+ * intended solver for the fast iterations (section 3) but gives no details;
+ * the filter is the Chebyshev form of Zhou & Saad.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are complex128 (two doubles, real then imaginary) in
+ *    column-major order with a leading dimension >= the row count, in DEVICE
+ *    memory of the handle's device.  Only the lower triangles of A and B are
+ *    read (LAPACK uplo = 'L').  A, B and X0 are never written.
+ *  - The caller owns every buffer passed in; the handle owns its workspace,
+ *    allocated on first use with hipMalloc and grown as needed, freed by
+ *    gevp_destroy.
+ *  - Work runs on the stream set with gevp_set_stream (default: the null
+ *    stream).  gevp_solve returns after its work has completed, because its
+ *    status depends on convergence; gevp_backward and the gevp_k_* kernels
+ *    are asynchronous.
+ *  - A handle is not thread-safe: one handle per host thread and stream.
+ *  - Errors are returned as a status code and never raised across the ABI.
+ */
+#ifndef GEVP_H
+#define GEVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gevp_ctx* gevp_handle;
+
+typedef enum {
+  GEVP_OK = 0,
+  GEVP_ERR_INVALID = 1,    /* a bad argument; info->lapack_info = -(argument index) */
+  GEVP_ERR_NOT_HPD = 2,    /* Cholesky of B failed; info->lapack_info = n + pivot (1-based) */
+  GEVP_ERR_NOCONV = 3,     /* maxit reached; outputs hold the best pairs and residuals */
+  GEVP_ERR_HIP = 4,        /* a HIP runtime call failed */
+  GEVP_ERR_NONFINITE = 5,  /* NaN or Inf in A, B or X0 */
+  GEVP_ERR_ALLOC = 6       /* workspace allocation failed */
+} gevp_status;
+
+typedef enum {
+  GEVP_FP64 = 0,   /* every step in FP64 */
+  GEVP_FP32 = 1,   /* filter products in FP32 MFMA, everything else FP64 */
+  GEVP_BF16X3 = 2  /* filter products in split-BF16 (3 products, FP32 accumulate) */
+} gevp_precision;
+
+/* Options; a zero-initialised struct selects every default. */
+typedef struct {
+  int precision;            /* gevp_precision; default GEVP_FP64 */
+  int nex;                  /* guard vectors; 0 = max(16, ceil(0.15 nev)) rounded to 16 */
+  int deg_init;             /* filter degree of a cold first sweep; 0 = 20 */
+  int deg_max;              /* per-sweep cap on a column's degree; 0 = 36 */
+  int maxit;                /* outer iterations; 0 = 40 */
+  int lanczos_steps;        /* spectral-bound Lanczos steps; 0 = 24 */
+  unsigned long long seed;  /* random fill of non-seeded columns */
+  int skip_final_residual;  /* 1: skip the original-basis residual check */
+  int reserved[8];
+} gevp_opts;
+
+/* Diagnostics, filled on return when a non-NULL pointer is passed. */
+typedef struct {
+  int64_t lapack_info;    /* zhegv-style: 0, -i bad argument, n+i Cholesky pivot i */
+  int outer_iters;        /* filter + QR + Rayleigh-Ritz sweeps */
+  int nconv;              /* converged wanted pairs (nev on success) */
+  int block;              /* nev + nex */
+  int qr_fallbacks;       /* shifted-CholQR fallbacks taken */
+  int64_t col_degrees;    /* sum over sweeps of filtered column-degrees */
+  double max_resid;       /* max_i ||A x_i - lambda_i B x_i||_2 / ||A||_2 (original basis) */
+  double normA, normB;    /* Lanczos estimates of ||A||_2, ||B||_2 */
+  double filter_flops;    /* useful filter flops, 8 n^2 per column-degree */
+  double ms[8];           /* stage times (ms) when profiling is on: see gevp_stage */
+} gevp_info;
+
+typedef enum {
+  GEVP_STAGE_STAGE = 0,   /* input mirroring and scans */
+  GEVP_STAGE_CHOL = 1,    /* Cholesky of B */
+  GEVP_STAGE_REDUCE = 2,  /* C = L^{-1} A L^{-H} */
+  GEVP_STAGE_BOUNDS = 3,  /* Lanczos bounds */
+  GEVP_STAGE_FILTER = 4,  /* Chebyshev filter */
+  GEVP_STAGE_QR = 5,      /* CholQR */
+  GEVP_STAGE_RR = 6,      /* Rayleigh-Ritz incl. the small eigensolve */
+  GEVP_STAGE_FINAL = 7    /* back-transform and residual */
+} gevp_stage;
+
+/* Create a handle on HIP device `device`.  The workspace is allocated lazily. */
+gevp_status gevp_create(gevp_handle* h, int device);
+
+/* Run subsequent work on `hip_stream` (a hipStream_t; NULL = null stream). */
+gevp_status gevp_set_stream(gevp_handle h, void* hip_stream);
+
+/* 1: record per-stage HIP event times into gevp_info.ms (adds syncs). */
+gevp_status gevp_set_profiling(gevp_handle h, int on);
+
+/* Free the workspace and the handle. */
+void gevp_destroy(gevp_handle h);
+
+const char* gevp_status_string(gevp_status s);
+
+/* Block width nev + nex that gevp_solve uses for these options. */
+int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev);
+
+/*
+ * Lowest eigenpairs of A x = lambda B x.
+ *   n        order of A and B (n >= 1)
+ *   A, lda   device complex128 n x n, Hermitian, lower triangle read
+ *   B, ldb   device complex128 n x n, Hermitian positive definite, lower read
+ *   X0, ldx0, k0
+ *            optional seed block (device complex128 n x k0, k0 <= block), the
+ *            previous SCF iteration's eigenvectors in the original basis;
+ *            X0 = NULL or k0 = 0 is a cold start.  Columns beyond k0 are
+ *            filled from a counter-based random generator (opts->seed).
+ *   nev      wanted pairs, 1 <= nev <= n
+ *   tol      convergence: ||A x_i - lambda_i B x_i||_2 <= tol ||A||_2 for
+ *            every i < nev (tol > 0; 1e-10 is typical)
+ *   kx       columns returned, nev <= kx <= block: the first nev are the
+ *            wanted pairs, the rest are the guard Ritz pairs (useful as the
+ *            next seed)
+ *   lambda   device float64[kx], ascending
+ *   X, ldx   device complex128 n x kx, B-orthonormal eigenvectors; the
+ *            largest-modulus entry of each column is real and positive
+ *   resid    optional device float64[kx]: ||A x_i - lambda_i B x_i||_2
+ *   info     optional host struct
+ * Returns GEVP_OK, or GEVP_ERR_NOCONV with the best pairs written.
+ */
+gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n,
+                       const void* A, int64_t lda, const void* B, int64_t ldb,
+                       const void* X0, int64_t ldx0, int64_t k0,
+                       int64_t nev, double tol, int64_t kx,
+                       double* lambda, void* X, int64_t ldx, double* resid,
+                       gevp_info* info);
+
+/*
+ * Batched k-points: `count` independent problems of uneven size (the paper,
+ * section 1: one pencil per Bloch vector k).  Arrays of length count hold
+ * per-problem arguments as in gevp_solve (X0[i] may be NULL).  kx[i] = nev[i]
+ * when kx is NULL.  infos may be NULL.  Returns the worst status.
+ */
+gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count,
+                               const int64_t* n, const void* const* A, const int64_t* lda,
+                               const void* const* B, const int64_t* ldb,
+                               const void* const* X0, const int64_t* ldx0, const int64_t* k0,
+                               const int64_t* nev, double tol, const int64_t* kx,
+                               double* const* lambda, void* const* X, const int64_t* ldx,
+                               double* const* resid, gevp_info* infos);
+
+/*
+ * Adjoint of L = sum_i w_i lambda_i (first-order perturbation of a
+ * B-orthonormal pair: d lambda_i = x_i^H (dA - lambda_i dB) x_i):
+ *   dA = X diag(w) X^H,    dB = -X diag(w .* lambda) X^H     (full n x n)
+ * X: device complex128 n x nev (ldx); lambda, w: device float64[nev];
+ * dA, dB: device complex128 n x n outputs, either may be NULL.
+ */
+gevp_status gevp_backward(gevp_handle h, int64_t n, int64_t nev, const void* X, int64_t ldx,
+                          const double* lambda, const double* w,
+                          void* dA, int64_t ldda, void* dB, int64_t lddb);
+
+/* ---- kernel-level entry points (the building blocks, exposed for tests) ---- */
+
+/*
+ * D = alpha op(A) op(B) + beta Cm + gamma diag-scaled E on FP64 MFMA, complex128.
+ *   opA, opB: 'N' or 'C' (conjugate transpose).  op(A) is m x k, op(B) k x n.
+ *   Cm may alias D; Cm / E may be NULL (term dropped).  gcol (device float64[n])
+ *   scales the E term per column when non-NULL.  Asynchronous.
+ */
+gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                         double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         double beta, const void* Cm, int64_t ldc,
+                         double gamma, const void* E, int64_t lde, const double* gcol,
+                         void* D, int64_t ldd);
+
+/* In-place Cholesky of the lower triangle of the n x n Hermitian M (upper
+ * triangle zeroed).  Synchronous; returns GEVP_ERR_NOT_HPD with *pivot
+ * (1-based) on failure. */
+gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t* pivot);
+
+/* Triangular solves with the lower-triangular L (n x n):
+ *   side 'L', trans 'N':  R <- L^{-1} R        (R is n x m)
+ *   side 'L', trans 'C':  R <- L^{-H} R        (R is n x m)
+ *   side 'R', trans 'C':  R <- R L^{-H}        (R is m x n)
+ * Asynchronous. */
+gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t m,
+                        const void* L, int64_t ldl, void* R, int64_t ldr);
+
+/* Eigen-decomposition of a small Hermitian matrix (n <= 4096) on the GPU:
+ * H = Z diag(theta) Z^H, theta ascending.  H (lower read) is overwritten.
+ * Synchronous. */
+gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
+                        double* theta, void* Z, int64_t ldz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEVP_H */

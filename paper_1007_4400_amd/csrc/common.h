@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP sources of libgevp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "../../include/gevp.h"
+
+typedef double2 zd;  // complex128 stored as (re, im)
+
+// ---------------------------------------------------------------- host side
+
+#define GEVP_HIP_TRY(expr)                                                          \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      if (gevp_log_enabled())                                                       \
+        fprintf(stderr, "[gevp] %s failed: %s (%s:%d)\n", #expr, hipGetErrorString(_e), \
+                __FILE__, __LINE__);                                                \
+      return GEVP_ERR_HIP;                                                          \
+    }                                                                               \
+  } while (0)
+
+#define GEVP_TRY(expr)                   \
+  do {                                   \
+    gevp_status _s = (expr);             \
+    if (_s != GEVP_OK) return _s;        \
+  } while (0)
+
+int gevp_log_enabled();
+
+struct gevp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int profiling = 0;
+  // bump-allocated workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_used = 0;
+  // pinned host mirror of small device status blocks
+  void* host_pinned = nullptr;
+  size_t host_pinned_bytes = 0;
+};
+
+// Workspace carving.  reserve() (re)allocates when `bytes` exceeds the current
+// size; take() hands out 256-byte aligned pieces until reset().
+gevp_status ws_reserve(gevp_ctx* c, size_t bytes);
+void* ws_take(gevp_ctx* c, size_t bytes);
+inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---- kernel launchers (host functions, asynchronous on c->stream)
+
+// D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E   (FP64 MFMA, complex128)
+// When `coef` (device double[3]) is non-null it supplies alpha, beta, gamma.
+gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
+                         double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
+                         double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
+                         int64_t lde, const double* gcol, zd* D, int64_t ldd,
+                         const double* coef = nullptr);
+
+// Recursive blocked Cholesky of the lower triangle; Dinv (n x 64 column-major,
+// ld = ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev
+// (device int) receives the first failing pivot (1-based) or stays 0.
+gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
+                       int* info_dev);
+// R <- L^{-1} R (R n x m) ;  R <- L^{-H} R ;  R <- R L^{-H} (R m x n)
+gevp_status trsm_left_lower_n(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
+                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+gevp_status trsm_left_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
+                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
+                               const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+// Inverses of the 64 x 64 diagonal blocks of an already factored L.
+gevp_status diag_block_inverses(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl, zd* Dinv,
+                                int64_t ldi);
+
+// Small Hermitian eigensolver (n <= 4096): H (full storage, overwritten),
+// theta ascending, Z (n x n) unitary.  work >= heev_work_bytes(n).
+size_t heev_work_bytes(int64_t n);
+gevp_status heev_small(gevp_ctx* c, int64_t n, zd* H, int64_t ldh, double* theta, zd* Z,
+                       int64_t ldz, void* work);
+
+// elementwise / reduction kernels (vec_kernels.hip)
+gevp_status launch_mirror_lower(gevp_ctx* c, int64_t n, const zd* S, int64_t lds, zd* D,
+                                int64_t ldd, int* flag_nonfinite);
+gevp_status launch_symmetrize(gevp_ctx* c, int64_t n, zd* M, int64_t ldm);
+gevp_status launch_copy2d(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                          zd* D, int64_t ldd);
+gevp_status launch_check_finite(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S,
+                                int64_t lds, int* flag);
+gevp_status launch_randn(gevp_ctx* c, int64_t rows, int64_t cols, zd* V, int64_t ldv,
+                         int64_t col_offset, unsigned long long seed);
+gevp_status launch_colnorm_scale(gevp_ctx* c, int64_t rows, int64_t cols, zd* V, int64_t ldv);
+gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* W, int64_t ldw,
+                              const zd* V, int64_t ldv, const double* theta, double* out);
+gevp_status launch_colnorms(gevp_ctx* c, int64_t rows, int64_t cols, const zd* V, int64_t ldv,
+                            double* out);
+gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                               const int* perm, zd* D, int64_t ldd);
+gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx);
+gevp_status launch_hemv_cols(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y);
+gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const double* shift);
+gevp_status launch_scale_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                              const double* w, zd* D, int64_t ldd);
+gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d);
+
+// Lanczos bounds: runs `steps` steps on the Hermitian M (full storage) and
+// writes into out[0..5]: theta_min, theta_max, beta_last, upper bound
+// (theta_max + beta_last), spectrum-fraction estimate (see lanczos.hip),
+// max(|theta_min|, |theta_max|).  frac = wanted fraction for out[4].
+gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int steps,
+                           unsigned long long seed, double frac, double* out, void* work);
+size_t lanczos_work_bytes(int64_t n, int steps);
+
+// Controller (single work-group): decides convergence, the next filter
+// interval, per-column degrees, the degree-sorted column permutation and the
+// filter coefficients.  See solver.hip for the status layout.
+struct CtlParams {
+  int nb, nev, deg_max, deg_init, mode;  // mode 0: from Ritz data, 1: cold start
+  double tol_abs;                        // absolute C-space residual tolerance (device if <0)
+};
+gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
+                           const double* resid, const double* bounds, const double* norms,
+                           double tol_rel, int* status_i, double* status_d, int* perm,
+                           double* coefs);

@@ -1,0 +1,500 @@
+// Small dense Hermitian eigensolver for the Rayleigh-Ritz step (n up to a few
+// thousand), all on the GPU in FP64:
+//
+//  1. Householder tridiagonalisation H = U T U^H, one fused kernel per
+//     reflector.  Kernel s finishes the rank-2 update of reflector s-1 on the
+//     columns it owns, forms reflector s from column s (which every
+//     work-group reconstructs redundantly from the old column and the
+//     previous reflector, so no extra grid-wide barrier is needed), and
+//     accumulates p = tau H v for reflector s on its columns.  Hermitian
+//     symmetry turns each row dot product into a contiguous column dot.
+//  2. Eigenvalues of the real tridiagonal T by bisection on Sturm counts, one
+//     thread per eigenvalue.
+//  3. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
+//     pivoting), one thread per eigenvalue; members of numerically
+//     degenerate clusters are then made orthonormal by modified Gram-Schmidt.
+//  4. Z = U Z_T by applying the reflectors in reverse order.
+#include <cfloat>
+
+#include "common.h"
+
+namespace {
+constexpr int HT = 256;  // threads per work-group
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ double bsum(double v, double* sh) {
+  v = wsum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  const double s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ zd cmul(zd a, zd b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ zd cconj(zd a) { return make_double2(a.x, -a.y); }
+
+struct TrdArgs {
+  int n;
+  zd* H;
+  int64_t ldh;
+  zd* V;  // reflectors, column s holds v_s (v_s[s+1] = 1)
+  int64_t ldv;
+  zd* tau;
+  double* d;
+  double* e;
+  zd* pb;       // 2 x n : p of the previous / current reflector
+  zd* pp;       // 2 x G : per-work-group partial sums v^H p
+  int G;
+};
+
+// Reflector s (0 <= s <= n-2); s == n-1 finishes the last diagonal entry.
+__global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
+  extern __shared__ zd vs[];  // v_s, indices s+1 .. n-1 stored at [i]
+  __shared__ double sh[4];
+  __shared__ double shK[2];
+  const int n = a.n, tid = threadIdx.x, wg = blockIdx.x;
+  const int prev = s - 1;
+  // scalars of the previous reflector: K = 1/2 conj(tau) sum(partials),
+  // w = p - K v
+  zd K = make_double2(0.0, 0.0);
+  const zd* vp = (prev >= 0) ? a.V + (int64_t)prev * a.ldv : nullptr;
+  const zd* pprev = (prev >= 0) ? a.pb + (int64_t)(prev & 1) * n : nullptr;
+  if (prev >= 0) {
+    double sr = 0.0, si = 0.0;
+    for (int g = tid; g < a.G; g += HT) {
+      const zd q = a.pp[(int64_t)(prev & 1) * a.G + g];
+      sr += q.x;
+      si += q.y;
+    }
+    sr = bsum(sr, sh);
+    si = bsum(si, sh);
+    const zd t = cconj(a.tau[prev]);
+    const zd k2 = cmul(t, make_double2(sr, si));
+    K = make_double2(0.5 * k2.x, 0.5 * k2.y);
+  }
+  auto wprev = [&](int i) -> zd {  // w_{s-1}[i]
+    const zd p = pprev[i], v = vp[i], kv = cmul(K, v);
+    return make_double2(p.x - kv.x, p.y - kv.y);
+  };
+  // updated column s entry i (i >= s): H(i,s) - v_i conj(w_s) - w_i conj(v_s)
+  zd vps = make_double2(0.0, 0.0), wps = make_double2(0.0, 0.0);
+  if (prev >= 0) {
+    vps = vp[s];
+    wps = wprev(s);
+  }
+  auto colS = [&](int i) -> zd {
+    zd h = a.H[i + (int64_t)s * a.ldh];
+    if (prev >= 0) {
+      const zd v = vp[i], w = wprev(i);
+      const zd t1 = cmul(v, cconj(wps)), t2 = cmul(w, cconj(vps));
+      h.x -= t1.x + t2.x;
+      h.y -= t1.y + t2.y;
+    }
+    return h;
+  };
+  if (s == n - 1) {  // finish: last diagonal entry only
+    if (wg == 0 && tid == 0) a.d[s] = colS(s).x;
+    return;
+  }
+  // reflector s from x = column s, rows s+1 .. n-1
+  double sig = 0.0;
+  for (int i = s + 2 + tid; i < n; i += HT) {
+    const zd c = colS(i);
+    sig += c.x * c.x + c.y * c.y;
+  }
+  sig = bsum(sig, sh);
+  const zd alpha = colS(s + 1);
+  zd tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+  double beta;
+  if (sig == 0.0 && alpha.y == 0.0) {
+    beta = alpha.x;
+  } else {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sig);
+    beta = (alpha.x >= 0.0) ? -nrm : nrm;
+    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const zd den = make_double2(alpha.x - beta, alpha.y);  // scal = 1 / den
+    const double dd = den.x * den.x + den.y * den.y;
+    scal = make_double2(den.x / dd, -den.y / dd);
+  }
+  for (int i = s + 1 + tid; i < n; i += HT) vs[i] = (i == s + 1) ? make_double2(1.0, 0.0) : cmul(colS(i), scal);
+  __syncthreads();
+  if (wg == 0) {
+    zd* vcol = a.V + (int64_t)s * a.ldv;
+    for (int i = tid; i < n; i += HT) vcol[i] = (i > s) ? vs[i] : make_double2(0.0, 0.0);
+    if (tid == 0) {
+      a.tau[s] = tau;
+      a.e[s] = beta;
+      a.d[s] = colS(s).x;
+    }
+  }
+  // own columns j >= s+1, j % G == wg: finish the previous update on rows
+  // >= s+1 and accumulate p_s[j] = tau (v_s^H H(:, j))^* ... via Hermitian
+  // symmetry: p_j = tau sum_i conj(H(i,j)) v_i
+  const int lane = tid & 63, wave = tid >> 6;
+  zd part = make_double2(0.0, 0.0);
+  zd* pcur = a.pb + (int64_t)(s & 1) * n;
+  int j0 = s + 1 + ((wg - (s + 1)) % a.G + a.G) % a.G;
+  for (int j = j0 + wave * a.G; j < n; j += 4 * a.G) {
+    zd* col = a.H + (int64_t)j * a.ldh;
+    zd vj = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
+    if (prev >= 0) {
+      vj = vp[j];
+      wj = wprev(j);
+    }
+    double ar = 0.0, ai = 0.0;
+    for (int i = s + 1 + lane; i < n; i += 64) {
+      zd h = col[i];
+      if (prev >= 0) {
+        const zd v = vp[i], w = wprev(i);
+        const zd t1 = cmul(v, cconj(wj)), t2 = cmul(w, cconj(vj));
+        h.x -= t1.x + t2.x;
+        h.y -= t1.y + t2.y;
+        col[i] = h;
+      }
+      const zd v = vs[i];  // conj(h) * v
+      ar += h.x * v.x + h.y * v.y;
+      ai += h.x * v.y - h.y * v.x;
+    }
+    ar = wsum(ar);
+    ai = wsum(ai);
+    const zd pj = cmul(tau, make_double2(ar, ai));
+    if (lane == 0) {
+      pcur[j] = pj;
+      const zd cv = cconj(vs[j]);
+      const zd t = cmul(cv, pj);
+      part.x += t.x;
+      part.y += t.y;
+    }
+  }
+  // work-group partial of v_s^H p_s
+  double pr = bsum(lane == 0 ? part.x : 0.0, sh);
+  double pi = bsum(lane == 0 ? part.y : 0.0, sh);
+  if (tid == 0) a.pp[(int64_t)(s & 1) * a.G + wg] = make_double2(pr, pi);
+  (void)shK;
+}
+
+// Sturm count: number of eigenvalues of T smaller than x.
+__device__ int sturm(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(HT) void k_tri_bisect(const double* d, const double* e, int n,
+                                                   double* theta) {
+  extern __shared__ double sm[];
+  double* sd = sm;
+  double* se2 = sm + n;
+  __shared__ double red[2];
+  for (int i = threadIdx.x; i < n; i += HT) {
+    sd[i] = d[i];
+    se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gl = DBL_MAX, gu = -DBL_MAX, emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? sqrt(se2[i - 1]) : 0.0) + (i < n - 1 ? sqrt(se2[i]) : 0.0);
+      gl = fmin(gl, sd[i] - r);
+      gu = fmax(gu, sd[i] + r);
+      if (i < n - 1) emax = fmax(emax, se2[i]);
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    gl -= 2.0 * DBL_EPSILON * tnorm * n + 1e-300;
+    gu += 2.0 * DBL_EPSILON * tnorm * n + 1e-300;
+    red[0] = gl;
+    red[1] = gu;
+    (void)emax;
+  }
+  __syncthreads();
+  const int k = blockIdx.x * HT + threadIdx.x;
+  if (k >= n) return;
+  double lo = red[0], hi = red[1];
+  double emax = 0.0;
+  for (int i = 0; i < n - 1; ++i) emax = fmax(emax, se2[i]);
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
+    if (mid <= lo || mid >= hi) break;
+    if (sturm(sd, se2, n, mid, pivmin) <= k) lo = mid; else hi = mid;
+  }
+  theta[k] = 0.5 * (lo + hi);
+}
+
+__device__ __forceinline__ uint64_t hmix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Inverse iteration, thread j <-> eigenvalue j.  Scratch arrays are laid out
+// [i * n + j] so that a wave's accesses are contiguous.  Output Zt[i*n + j].
+// LU of T - lam I with partial pivoting: row k of U holds (U, Vv, Ww) on
+// columns (k, k+1, k+2); Lm the multiplier and Sw the row swap of step k.
+__global__ __launch_bounds__(HT) void k_tri_invit(const double* d, const double* e, int n,
+                                                  const double* theta, double* U, double* Vv,
+                                                  double* Ww, double* Lm, double* Sw, double* Zt,
+                                                  double tnorm) {
+  const int j = blockIdx.x * HT + threadIdx.x;
+  if (j >= n) return;
+  const double lam = theta[j];
+  const double tiny = DBL_EPSILON * fmax(tnorm, DBL_MIN);
+  auto at = [&](double* A, int i) -> double& { return A[(int64_t)i * n + j]; };
+  // working row k: (al, be) on columns (k, k+1)
+  double al = d[0] - lam, be = (n > 1) ? e[0] : 0.0;
+  for (int k = 0; k < n - 1; ++k) {
+    const double ck = e[k], an = d[k + 1] - lam, bn = (k + 1 < n - 1) ? e[k + 1] : 0.0;
+    if (fabs(al) >= fabs(ck)) {  // pivot on the working row
+      const double piv = (al == 0.0) ? tiny : al;
+      const double l = ck / piv;
+      at(U, k) = piv;
+      at(Vv, k) = be;
+      at(Ww, k) = 0.0;
+      at(Lm, k) = l;
+      at(Sw, k) = 0.0;
+      al = an - l * be;
+      be = bn;
+    } else {  // pivot on the next original row (ck, an, bn)
+      const double l = al / ck;
+      at(U, k) = ck;
+      at(Vv, k) = an;
+      at(Ww, k) = bn;
+      at(Lm, k) = l;
+      at(Sw, k) = 1.0;
+      const double nal = be - l * an;
+      be = -l * bn;
+      al = nal;
+    }
+  }
+  at(U, n - 1) = (al == 0.0) ? tiny : al;
+  for (int i = 0; i < n; ++i) {
+    const uint64_t r = hmix(((uint64_t)j << 32) ^ (uint64_t)i ^ 0x5DEECE66Dull);
+    at(Zt, i) = ((double)(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+  }
+  double nrm = 0.0;
+  for (int it = 0; it < 3; ++it) {
+    for (int k = 0; k < n - 1; ++k) {
+      const double l = at(Lm, k);
+      const double yk = at(Zt, k), yk1 = at(Zt, k + 1);
+      if (at(Sw, k) != 0.0) {
+        at(Zt, k) = yk1;
+        at(Zt, k + 1) = yk - l * yk1;
+      } else {
+        at(Zt, k + 1) = yk1 - l * yk;
+      }
+    }
+    double x1 = 0.0, x2 = 0.0, mx = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      double y = at(Zt, k);
+      if (k + 1 < n) y -= at(Vv, k) * x1;
+      if (k + 2 < n) y -= at(Ww, k) * x2;
+      const double x = y / at(U, k);
+      at(Zt, k) = x;
+      x2 = x1;
+      x1 = x;
+      mx = fmax(mx, fabs(x));
+    }
+    const double sc = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
+    nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = at(Zt, i) * sc;
+      at(Zt, i) = v;
+      nrm += v * v;
+    }
+  }
+  const double inv = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
+  for (int i = 0; i < n; ++i) at(Zt, i) *= inv;
+}
+
+// Modified Gram-Schmidt inside clusters of (numerically) equal eigenvalues:
+// work-group b handles the cluster that starts at index b (if any).
+__global__ __launch_bounds__(HT) void k_tri_cluster_mgs(const double* theta, int n, double* Zt,
+                                                        double ctol) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (b >= n) return;
+  const bool start = (b == 0 || theta[b] - theta[b - 1] > ctol);
+  if (!start || b + 1 >= n || theta[b + 1] - theta[b] > ctol) return;
+  int end = b + 1;
+  while (end + 1 < n && theta[end + 1] - theta[end] <= ctol) ++end;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int m = b; m <= end; ++m) {
+      for (int q = b; q < m; ++q) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += HT) s += Zt[(int64_t)i * n + q] * Zt[(int64_t)i * n + m];
+        s = bsum(s, sh);
+        for (int i = threadIdx.x; i < n; i += HT) Zt[(int64_t)i * n + m] -= s * Zt[(int64_t)i * n + q];
+        __syncthreads();
+      }
+      double s = 0.0;
+      for (int i = threadIdx.x; i < n; i += HT) {
+        const double v = Zt[(int64_t)i * n + m];
+        s += v * v;
+      }
+      s = bsum(s, sh);
+      const double inv = (s > 0.0) ? 1.0 / sqrt(s) : 0.0;
+      for (int i = threadIdx.x; i < n; i += HT) Zt[(int64_t)i * n + m] *= inv;
+      __syncthreads();
+    }
+}
+
+// Zc(i, j) = Zt[i*n + j] as complex, 32 x 32 tiles through LDS
+__global__ __launch_bounds__(256) void k_zt_to_complex(const double* Zt, int n, zd* Z, int64_t ldz) {
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    t[r][tx] = (i < n && j < n) ? Zt[(int64_t)i * n + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + tx;
+    if (i < n && j < n) Z[i + (int64_t)j * ldz] = make_double2(t[tx][r], 0.0);
+  }
+}
+
+// Z <- G_0 G_1 ... G_{n-2} Z, reflectors applied last to first; each
+// work-group owns 16 columns (4 per wave) and stages v_s through LDS.
+__global__ __launch_bounds__(256) void k_apply_reflectors(int n, zd* Z, int64_t ldz, const zd* V,
+                                                          int64_t ldv, const zd* tau) {
+  extern __shared__ zd sv[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = blockIdx.x * 16 + wave * 4;
+  for (int s = n - 2; s >= 0; --s) {
+    const zd t = tau[s];
+    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
+    __syncthreads();
+    for (int i = s + 1 + tid; i < n; i += 256) sv[i] = V[i + (int64_t)s * ldv];
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int col = c0 + q;
+      if (col >= n) break;
+      zd* z = Z + (int64_t)col * ldz;
+      double sr = 0.0, si = 0.0;
+      for (int i = s + 1 + lane; i < n; i += 64) {
+        const zd v = sv[i], x = z[i];  // conj(v) x
+        sr += v.x * x.x + v.y * x.y;
+        si += v.x * x.y - v.y * x.x;
+      }
+      sr = wsum(sr);
+      si = wsum(si);
+      const zd f = cmul(t, make_double2(sr, si));
+      for (int i = s + 1 + lane; i < n; i += 64) {
+        const zd v = sv[i], fv = cmul(f, v);
+        z[i].x -= fv.x;
+        z[i].y -= fv.y;
+      }
+    }
+  }
+}
+
+__global__ void k_tri_norm(const double* d, const double* e, int n, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < n; ++i)
+    m = fmax(m, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
+  out[0] = m;
+}
+}  // namespace
+
+size_t heev_work_bytes(int64_t n) {
+  const int G = (int)(n < 128 ? (n > 1 ? n - 1 : 1) : 128);
+  size_t b = 0;
+  b += ws_round(sizeof(zd) * n * n);          // V (reflectors)
+  b += ws_round(sizeof(zd) * n);              // tau
+  b += 2 * ws_round(sizeof(double) * n);      // d, e
+  b += ws_round(sizeof(zd) * 2 * n);          // pb
+  b += ws_round(sizeof(zd) * 2 * G);          // pp
+  b += 6 * ws_round(sizeof(double) * n * n);  // U, Vv, Ww, Lm, Zt + spare
+  b += ws_round(sizeof(double) * 8);
+  return b;
+}
+
+gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* theta, zd* Z,
+                       int64_t ldz, void* work) {
+  if (n64 <= 0) return GEVP_OK;
+  if (n64 > 4000) return GEVP_ERR_INVALID;  // v_s must fit 64 KB of LDS
+  const int n = (int)n64;
+  const int G = n < 128 ? (n > 1 ? n - 1 : 1) : 128;
+  char* w = (char*)work;
+  auto take = [&](size_t bytes) {
+    void* p = w;
+    w += ws_round(bytes);
+    return p;
+  };
+  TrdArgs a;
+  a.n = n;
+  a.H = H;
+  a.ldh = ldh;
+  a.V = (zd*)take(sizeof(zd) * n * n);
+  a.ldv = n;
+  a.tau = (zd*)take(sizeof(zd) * n);
+  a.d = (double*)take(sizeof(double) * n);
+  a.e = (double*)take(sizeof(double) * n);
+  a.pb = (zd*)take(sizeof(zd) * 2 * n);
+  a.pp = (zd*)take(sizeof(zd) * 2 * G);
+  a.G = G;
+  double* U = (double*)take(sizeof(double) * n * n);
+  double* Vv = (double*)take(sizeof(double) * n * n);
+  double* Ww = (double*)take(sizeof(double) * n * n);
+  double* Lm = (double*)take(sizeof(double) * n * n);
+  double* Zt = (double*)take(sizeof(double) * n * n);
+  double* Sw = (double*)take(sizeof(double) * n * n);
+  double* tn = (double*)take(sizeof(double) * 8);
+
+  const size_t shv = sizeof(zd) * (size_t)n;
+  if (n == 1) {
+    hipLaunchKernelGGL(k_hetrd_step, dim3(1), dim3(HT), shv, c->stream, a, 0);
+    GEVP_HIP_TRY(hipGetLastError());
+    GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd), c->stream));
+  } else {
+    GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd) * n, c->stream));
+    for (int s = 0; s <= n - 1; ++s) {
+      hipLaunchKernelGGL(k_hetrd_step, dim3(G), dim3(HT), shv, c->stream, a, s);
+      GEVP_HIP_TRY(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(k_tri_norm, dim3(1), dim3(64), 0, c->stream, a.d, a.e, n, tn);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_tri_bisect, dim3((n + HT - 1) / HT), dim3(HT), sizeof(double) * 2 * n,
+                     c->stream, a.d, a.e, n, theta);
+  GEVP_HIP_TRY(hipGetLastError());
+  // ||T|| is needed on the host only as a scale for the zero-pivot guard and
+  // the cluster tolerance; read it back (one small synchronous copy).
+  double tnorm = 0.0;
+  GEVP_HIP_TRY(hipMemcpyAsync(&tnorm, tn, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+  hipLaunchKernelGGL(k_tri_invit, dim3((n + HT - 1) / HT), dim3(HT), 0, c->stream, a.d, a.e, n,
+                     theta, U, Vv, Ww, Lm, Sw, Zt, tnorm);
+  GEVP_HIP_TRY(hipGetLastError());
+  const double ctol = 1e3 * DBL_EPSILON * fmax(tnorm, 1e-300);
+  hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, ctol);
+  GEVP_HIP_TRY(hipGetLastError());
+  const unsigned tb = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
+  GEVP_HIP_TRY(hipGetLastError());
+  if (n > 1) {
+    hipLaunchKernelGGL(k_apply_reflectors, dim3((n + 15) / 16), dim3(256), shv, c->stream, n, Z,
+                       ldz, a.V, a.ldv, a.tau);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
+  return GEVP_OK;
+}

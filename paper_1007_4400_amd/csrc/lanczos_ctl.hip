@@ -1,0 +1,334 @@
+// Spectral bounds by a few Lanczos steps, and the controller that turns
+// Ritz values and residuals into the next Chebyshev filter.
+//
+// Lanczos: v_{j+1} beta_j = M v_j - alpha_j v_j - beta_{j-1} v_{j-1}.  The
+// Ritz values of the k x k tridiagonal bracket the spectrum from inside; the
+// largest plus the last beta is a safe upper bound for the filter interval
+// (the damped end), and the squared first components of the Ritz vectors
+// estimate the spectral density, which places the lower end of the damped
+// interval for a cold start.
+//
+// Controller: Chebyshev filter of degree m on the damped interval [a, b]
+// (centre c, half-width e), normalised at the lowest estimate mu, applied
+// with the scaled three-term recurrence
+//   Y1 = (s1/e)(C - cI) Y0,
+//   Y_{j+1} = (2 s_{j+1}/e)(C - cI) Y_j - s_j s_{j+1} Y_{j-1},
+//   s1 = e/(mu - c),  s_{j+1} = 1/(2/s1 - s_j),
+// whose coefficients are written as (alpha, beta, gamma) triples for the GEMM
+// epilogue D = alpha C Y + beta Y + gamma Y_prev.  A column whose Ritz value
+// theta lies left of the interval gains a factor rho = |t| + sqrt(t^2 - 1),
+// t = (theta - c)/e, per degree relative to the damped part, so it needs
+// m = log(r / tol) / log(rho) more degrees to converge; converged wanted
+// columns get degree 0 (they stay in the basis), guard columns the largest
+// degree of the unconverged wanted ones.  Degrees are even so every column's
+// last iterate lands in the same buffer; columns are sorted by degree so the
+// columns still active at step j form a contiguous suffix.
+#include <cfloat>
+
+#include "common.h"
+
+namespace {
+
+__global__ __launch_bounds__(1024) void k_lanczos_init(int64_t n, zd* v) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += v[i].x * v[i].x + v[i].y * v[i].y;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < 16; ++w) t += sh[w];
+  const double inv = 1.0 / sqrt(t);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) v[i] = make_double2(v[i].x * inv, v[i].y * inv);
+}
+
+__device__ double bsum1024(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < 16; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// w = M v_j (given); alpha_j = Re(v_j^H w); w -= alpha_j v_j + beta_{j-1} v_{j-1};
+// beta_j = ||w||; v_{j+1} = w / beta_j
+__global__ __launch_bounds__(1024) void k_lanczos_vec(int64_t n, const zd* vprev, const zd* vcur,
+                                                      const zd* w, zd* vnext, double* alpha,
+                                                      double* beta, int j) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += vcur[i].x * w[i].x + vcur[i].y * w[i].y;
+  const double a = bsum1024(s, sh);
+  const double bp = (j > 0) ? beta[j - 1] : 0.0;
+  double q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    double rx = w[i].x - a * vcur[i].x, ry = w[i].y - a * vcur[i].y;
+    if (j > 0) {
+      rx -= bp * vprev[i].x;
+      ry -= bp * vprev[i].y;
+    }
+    vnext[i] = make_double2(rx, ry);
+    q += rx * rx + ry * ry;
+  }
+  const double b = sqrt(bsum1024(q, sh));
+  const double inv = (b > 0.0) ? 1.0 / b : 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) vnext[i] = make_double2(vnext[i].x * inv, vnext[i].y * inv);
+  if (threadIdx.x == 0) {
+    alpha[j] = a;
+    beta[j] = b;
+  }
+}
+
+// Eigenvalues of the k x k Lanczos tridiagonal with the first component of
+// each eigenvector, by implicit Wilkinson-shift QR tracking only the first
+// row of the accumulated rotations.  Single thread; k <= 64.
+__global__ void k_lanczos_finish(const double* alpha, const double* beta, int k, double frac,
+                                 double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double d[64], e[64], z[64];
+  for (int i = 0; i < k; ++i) {
+    d[i] = alpha[i];
+    e[i] = (i < k - 1) ? beta[i] : 0.0;
+    z[i] = (i == 0) ? 1.0 : 0.0;
+  }
+  double tn = 0.0;
+  for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(d[i]) + fabs(e[i]) + (i ? fabs(e[i - 1]) : 0.0));
+  int m = k - 1, guard = 0;
+  while (m > 0 && guard < 100 * k) {
+    if (fabs(e[m - 1]) <= DBL_EPSILON * (fabs(d[m - 1]) + fabs(d[m])) || fabs(e[m - 1]) <= DBL_EPSILON * tn) {
+      e[m - 1] = 0.0;
+      --m;
+      continue;
+    }
+    int l = m - 1;
+    while (l > 0 && fabs(e[l - 1]) > DBL_EPSILON * (fabs(d[l - 1]) + fabs(d[l])) &&
+           fabs(e[l - 1]) > DBL_EPSILON * tn)
+      --l;
+    ++guard;
+    const double aa = d[m - 1], bb = e[m - 1], cc = d[m];
+    const double del = 0.5 * (aa - cc);
+    const double den = del + copysign(hypot(del, bb), del);
+    const double mu = (den != 0.0) ? cc - bb * bb / den : cc - fabs(bb);
+    double x = d[l] - mu, y = e[l];
+    for (int q = l; q < m; ++q) {
+      const double r = hypot(x, y);
+      const double cs = (r == 0.0) ? 1.0 : x / r, sn = (r == 0.0) ? 0.0 : y / r;
+      if (q > l) e[q - 1] = r;
+      const double dq = d[q], dq1 = d[q + 1], eq = e[q];
+      d[q] = cs * cs * dq + 2.0 * cs * sn * eq + sn * sn * dq1;
+      d[q + 1] = sn * sn * dq - 2.0 * cs * sn * eq + cs * cs * dq1;
+      e[q] = cs * sn * (dq1 - dq) + (cs * cs - sn * sn) * eq;
+      if (q < m - 1) {
+        x = e[q];
+        y = sn * e[q + 1];
+        e[q + 1] = cs * e[q + 1];
+      }
+      const double z0 = z[q], z1 = z[q + 1];
+      z[q] = cs * z0 + sn * z1;
+      z[q + 1] = -sn * z0 + cs * z1;
+    }
+  }
+  // sort (insertion) by value, carrying weights
+  for (int i = 1; i < k; ++i) {
+    const double dv = d[i], zv = z[i];
+    int p = i - 1;
+    while (p >= 0 && d[p] > dv) {
+      d[p + 1] = d[p];
+      z[p + 1] = z[p];
+      --p;
+    }
+    d[p + 1] = dv;
+    z[p + 1] = zv;
+  }
+  const double blast = beta[k - 1];
+  out[0] = d[0];
+  out[1] = d[k - 1];
+  out[2] = blast;
+  out[3] = d[k - 1] + fabs(blast);
+  // density estimate: point where the cumulative weight reaches frac
+  double cum = 0.0, est = d[k - 1];
+  for (int i = 0; i < k; ++i) {
+    const double wgt = z[i] * z[i];
+    if (cum + wgt >= frac) {
+      const double lo = (i > 0) ? d[i - 1] : d[0];
+      const double t = (wgt > 0.0) ? (frac - cum) / wgt : 1.0;
+      est = lo + t * (d[i] - lo);
+      break;
+    }
+    cum += wgt;
+  }
+  out[4] = est;
+  out[5] = fmax(fabs(d[0]), fabs(d[k - 1]));
+}
+
+// status_i: [0] nconv  [1] maxdeg  [2] done  [3] unused  [4 + j - 1] s_j (j = 1..maxdeg)
+// status_d: [0] a  [1] b  [2] c  [3] e  [4] tol_abs  [5] sum of column degrees  [6] mu
+__global__ __launch_bounds__(256) void k_control(CtlParams p, const double* theta,
+                                                 const double* resid, const double* bounds,
+                                                 const double* norms, double tol_rel, int* si,
+                                                 double* sd, int* perm, double* coefs) {
+  extern __shared__ int deg[];  // nb
+  __shared__ int cnt[256];
+  __shared__ int sh_nconv, sh_maxdeg;
+  const int tid = threadIdx.x, nb = p.nb, nev = p.nev;
+  const double normA = norms[0], normB = norms[1];
+  const double tol_abs = tol_rel * normA / sqrt(fmax(normB, DBL_MIN));
+  double a, mu;
+  const double b = bounds[3];
+  if (p.mode == 1) {
+    a = bounds[4];
+    mu = bounds[0];
+  } else {
+    a = theta[nb - 1];
+    mu = fmin(theta[0], bounds[0]);
+  }
+  if (!(a < b)) a = b - 1e-3 * fmax(fabs(b), 1.0);
+  if (!(mu < a)) mu = a - 0.5 * (b - a);
+  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+  if (tid == 0) {
+    int nc = 0;
+    if (p.mode == 0)
+      while (nc < nev && resid[nc] <= tol_abs) ++nc;
+    sh_nconv = nc;
+  }
+  __syncthreads();
+  const bool done = (p.mode == 0) && sh_nconv >= nev;
+  // per-column degrees
+  for (int i = tid; i < nb; i += 256) {
+    int m;
+    if (p.mode == 1) {
+      m = p.deg_init;
+    } else if (i < nev) {
+      if (resid[i] <= tol_abs) {
+        m = 0;
+      } else {
+        const double t = (theta[i] - c) / e;
+        if (t >= -1.0) {
+          m = p.deg_max;
+        } else {
+          const double rho = fabs(t) + sqrt(t * t - 1.0);
+          const double need = log(resid[i] / tol_abs) / log(rho);
+          m = (int)ceil(need) + 1;
+          if (m < 2) m = 2;
+          if (m > p.deg_max) m = p.deg_max;
+        }
+      }
+    } else {
+      m = -1;  // guard: filled below
+    }
+    m = (m > 0) ? (m + (m & 1)) : m;
+    deg[i] = m;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int mx = 0;
+    for (int i = 0; i < nb && i < nev; ++i) mx = max(mx, deg[i]);
+    if (p.mode == 1) mx = deg[0];
+    if (mx == 0 && !done) mx = 2;
+    if (mx > p.deg_max + (p.deg_max & 1)) mx = p.deg_max + (p.deg_max & 1);
+    sh_maxdeg = done ? 0 : mx;
+  }
+  __syncthreads();
+  for (int i = tid; i < nb; i += 256)
+    if (deg[i] < 0) deg[i] = sh_maxdeg;
+  __syncthreads();
+  // stable counting sort by degree (degrees <= 255)
+  for (int i = tid; i < 256; i += 256) cnt[i] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    long long sum = 0;
+    for (int i = 0; i < nb; ++i) {
+      cnt[deg[i]]++;
+      sum += deg[i];
+    }
+    int acc = 0;
+    for (int v = 0; v < 256; ++v) {
+      const int cv = cnt[v];
+      cnt[v] = acc;
+      acc += cv;
+    }
+    // s_j = number of columns with degree < j
+    for (int j = 1; j <= sh_maxdeg; ++j) si[4 + j - 1] = cnt[j];
+    for (int i = 0; i < nb; ++i) perm[cnt[deg[i]]++] = i;
+    si[0] = sh_nconv;
+    si[1] = sh_maxdeg;
+    si[2] = done ? 1 : 0;
+    si[3] = 0;
+    sd[0] = a;
+    sd[1] = b;
+    sd[2] = c;
+    sd[3] = e;
+    sd[4] = tol_abs;
+    sd[5] = (double)sum;
+    sd[6] = mu;
+    // filter coefficients, step j at coefs[3 (j - 1)]
+    const double s1 = e / (mu - c);
+    double sg = s1;
+    for (int j = 1; j <= sh_maxdeg; ++j) {
+      double al, be, ga;
+      if (j == 1) {
+        al = s1 / e;
+        be = -s1 * c / e;
+        ga = 0.0;
+      } else {
+        const double sn = 1.0 / (2.0 / s1 - sg);
+        al = 2.0 * sn / e;
+        be = -2.0 * sn * c / e;
+        ga = -sg * sn;
+        sg = sn;
+      }
+      coefs[3 * (j - 1) + 0] = al;
+      coefs[3 * (j - 1) + 1] = be;
+      coefs[3 * (j - 1) + 2] = ga;
+    }
+  }
+}
+}  // namespace
+
+size_t lanczos_work_bytes(int64_t n, int steps) {
+  return ws_round(sizeof(zd) * n * 4) + 2 * ws_round(sizeof(double) * (steps + 1));
+}
+
+gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int steps,
+                           unsigned long long seed, double frac, double* out, void* work) {
+  if (steps > 64) steps = 64;
+  if (steps > n) steps = (int)n;
+  if (steps < 1) steps = 1;
+  char* w = (char*)work;
+  zd* V = (zd*)w;
+  w += ws_round(sizeof(zd) * n * 4);
+  double* alpha = (double*)w;
+  w += ws_round(sizeof(double) * (steps + 1));
+  double* beta = (double*)w;
+  zd* buf[3] = {V, V + n, V + 2 * n};
+  zd* wv = V + 3 * n;
+  GEVP_TRY(launch_randn(c, n, 1, buf[0], n, 0, seed));
+  hipLaunchKernelGGL(k_lanczos_init, dim3(1), dim3(1024), 0, c->stream, n, buf[0]);
+  GEVP_HIP_TRY(hipGetLastError());
+  for (int j = 0; j < steps; ++j) {
+    zd* vc = buf[j % 3];
+    zd* vp = buf[(j + 2) % 3];
+    zd* vn = buf[(j + 1) % 3];
+    GEVP_TRY(launch_hemv_cols(c, n, M, ldm, vc, wv));
+    hipLaunchKernelGGL(k_lanczos_vec, dim3(1), dim3(1024), 0, c->stream, n, vp, vc, wv, vn, alpha,
+                       beta, j);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_lanczos_finish, dim3(1), dim3(64), 0, c->stream, alpha, beta, steps, frac,
+                     out);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
+                           const double* resid, const double* bounds, const double* norms,
+                           double tol_rel, int* status_i, double* status_d, int* perm,
+                           double* coefs) {
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(256), sizeof(int) * p.nb, c->stream, p, theta, resid,
+                     bounds, norms, tol_rel, status_i, status_d, perm, coefs);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}

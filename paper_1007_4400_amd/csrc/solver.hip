@@ -1,0 +1,599 @@
+// Host orchestration of the seeded Chebyshev-filtered subspace iteration and
+// the C ABI of libgevp (declared in include/gevp.h).
+//
+// One solve (the paper's fast iteration, section 2, seeded by the previous
+// iteration's eigenvectors):
+//   stage    A, B lower triangles -> full Hermitian copies; NaN/Inf scan
+//   chol     B = L L^H
+//   reduce   C = L^{-1} A L^{-H}, symmetrised
+//   bounds   Lanczos on C (filter interval), on A and B (norm estimates)
+//   seed     Y0 = [L^H X0, random], or random for a cold start
+//   loop     CholQR2 -> Rayleigh-Ritz (W = C Y, H = Y^H W, H = Z T Z^H,
+//            Y <- Y Z) -> residuals -> controller -> Chebyshev filter
+//   final    X = L^{-H} Y(:, 1:kx), original-basis residuals, phase fix
+// The only device-to-host traffic is a few status words per sweep.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+int gevp_log_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* s = getenv("GEVP_LOG");
+    v = (s && s[0] == '1') ? 1 : 0;
+  }
+  return v;
+}
+
+gevp_status ws_reserve(gevp_ctx* c, size_t bytes) {
+  c->ws_used = 0;
+  if (bytes <= c->ws_bytes) return GEVP_OK;
+  if (c->ws) {
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    GEVP_HIP_TRY(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  if (hipMalloc((void**)&c->ws, bytes) != hipSuccess) {
+    c->ws = nullptr;
+    (void)hipGetLastError();
+    return GEVP_ERR_ALLOC;
+  }
+  c->ws_bytes = bytes;
+  return GEVP_OK;
+}
+
+void* ws_take(gevp_ctx* c, size_t bytes) {
+  void* p = c->ws + c->ws_used;
+  c->ws_used += ws_round(bytes);
+  return p;
+}
+
+namespace {
+
+struct Opts {
+  int precision, nex, deg_init, deg_max, maxit, lanczos;
+  unsigned long long seed;
+  int skip_final;
+};
+
+Opts resolve(const gevp_opts* o, int64_t nev) {
+  Opts r;
+  r.precision = o ? o->precision : 0;
+  r.nex = o ? o->nex : 0;
+  if (r.nex <= 0) {
+    int64_t x = (int64_t)std::ceil(0.15 * (double)nev);
+    if (x < 16) x = 16;
+    r.nex = (int)((x + 15) / 16 * 16);
+  }
+  r.deg_init = (o && o->deg_init > 0) ? o->deg_init : 20;
+  r.deg_max = (o && o->deg_max > 0) ? o->deg_max : 36;
+  if (r.deg_max > 200) r.deg_max = 200;
+  if (r.deg_init > r.deg_max) r.deg_init = r.deg_max;
+  r.maxit = (o && o->maxit > 0) ? o->maxit : 40;
+  r.lanczos = (o && o->lanczos_steps > 0) ? o->lanczos_steps : 24;
+  r.seed = o ? o->seed : 0ull;
+  r.skip_final = o ? o->skip_final_residual : 0;
+  return r;
+}
+
+int64_t block_of(const Opts& o, int64_t n, int64_t nev) {
+  int64_t nb = nev + o.nex;
+  return nb > n ? n : nb;
+}
+
+struct Timer {
+  gevp_ctx* c;
+  hipEvent_t ev[2];
+  bool on;
+  Timer(gevp_ctx* ctx) : c(ctx), on(ctx->profiling != 0) {
+    if (on) {
+      (void)hipEventCreate(&ev[0]);
+      (void)hipEventCreate(&ev[1]);
+    }
+  }
+  ~Timer() {
+    if (on) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+    }
+  }
+  void start() {
+    if (on) (void)hipEventRecord(ev[0], c->stream);
+  }
+  void stop(gevp_info* info, int stage) {
+    if (!on) return;
+    (void)hipEventRecord(ev[1], c->stream);
+    (void)hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (info) info->ms[stage] += ms;
+  }
+};
+
+// Orthonormalise the m columns of P (n x m) by CholQR2 with column scaling;
+// a failed Cholesky of the Gram matrix falls back to a shifted first pass.
+struct QrWork {
+  zd* G;
+  zd* Dg;
+  int* flag;
+  double* shift;
+};
+
+gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWork& w,
+                    int* fallbacks) {
+  for (int pass = 0; pass < 2; ++pass) {
+    GEVP_TRY(launch_colnorm_scale(c, n, m, P, ldp));
+    GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, w.G, m));
+    const int big = 0x7fffffff;
+    GEVP_HIP_TRY(hipMemcpyAsync(w.flag, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    GEVP_TRY(chol_lower(c, m, w.G, m, w.Dg, m, w.flag));
+    int f = big;
+    GEVP_HIP_TRY(hipMemcpyAsync(&f, w.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    if (f != big) {
+      // shifted CholQR (Fukaya et al.): G + s I with s = 11 (n m + m (m+1)) u ||G||,
+      // ||G|| <= trace(G) = m after column scaling; then two more plain passes
+      ++*fallbacks;
+      const double u = 1.1102230246251565e-16;
+      const double s = 11.0 * ((double)n * m + (double)m * (m + 1)) * u * (double)m;
+      GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, w.G, m));
+      GEVP_HIP_TRY(hipMemcpyAsync(w.shift, &s, sizeof(double), hipMemcpyHostToDevice, c->stream));
+      GEVP_TRY(launch_add_diag(c, m, w.G, m, w.shift));
+      GEVP_HIP_TRY(hipMemcpyAsync(w.flag, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
+      GEVP_TRY(chol_lower(c, m, w.G, m, w.Dg, m, w.flag));
+      GEVP_TRY(trsm_right_lower_c(c, m, n, w.G, m, w.Dg, m, P, ldp));
+      pass = -1;  // two plain passes follow
+      if (*fallbacks > 8) return GEVP_ERR_NOCONV;
+      continue;
+    }
+    GEVP_TRY(trsm_right_lower_c(c, m, n, w.G, m, w.Dg, m, P, ldp));
+  }
+  return GEVP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* gevp_status_string(gevp_status s) {
+  switch (s) {
+    case GEVP_OK: return "ok";
+    case GEVP_ERR_INVALID: return "invalid argument";
+    case GEVP_ERR_NOT_HPD: return "B is not Hermitian positive definite";
+    case GEVP_ERR_NOCONV: return "not converged";
+    case GEVP_ERR_HIP: return "HIP runtime error";
+    case GEVP_ERR_NONFINITE: return "NaN or Inf in the input";
+    case GEVP_ERR_ALLOC: return "workspace allocation failed";
+  }
+  return "unknown status";
+}
+
+gevp_status gevp_create(gevp_handle* h, int device) {
+  if (!h) return GEVP_ERR_INVALID;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return GEVP_ERR_HIP;
+  }
+  gevp_ctx* c = new gevp_ctx();
+  c->device = device;
+  *h = c;
+  return GEVP_OK;
+}
+
+gevp_status gevp_set_stream(gevp_handle h, void* s) {
+  if (!h) return GEVP_ERR_INVALID;
+  h->stream = (hipStream_t)s;
+  return GEVP_OK;
+}
+
+gevp_status gevp_set_profiling(gevp_handle h, int on) {
+  if (!h) return GEVP_ERR_INVALID;
+  h->profiling = on;
+  return GEVP_OK;
+}
+
+void gevp_destroy(gevp_handle h) {
+  if (!h) return;
+  if (h->ws) {
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->ws);
+  }
+  delete h;
+}
+
+int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev) {
+  if (n < 1 || nev < 1 || nev > n) return 0;
+  return block_of(resolve(opts, nev), n, nev);
+}
+
+gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const void* A_,
+                       int64_t lda, const void* B_, int64_t ldb, const void* X0_, int64_t ldx0,
+                       int64_t k0, int64_t nev, double tol, int64_t kx, double* lambda, void* X_,
+                       int64_t ldx, double* resid_out, gevp_info* info) {
+  gevp_info dummy;
+  if (!info) info = &dummy;
+  std::memset(info, 0, sizeof(*info));
+  auto bad = [&](int arg) {
+    info->lapack_info = -arg;
+    return GEVP_ERR_INVALID;
+  };
+  if (!h) return bad(1);
+  if (n < 1) return bad(3);
+  if (!A_ || lda < n) return bad(5);
+  if (!B_ || ldb < n) return bad(7);
+  if (nev < 1 || nev > n) return bad(11);
+  if (!(tol > 0.0)) return bad(12);
+  const Opts o = resolve(opts, nev);
+  if (o.precision != GEVP_FP64) return bad(2);  // other forms: see gevp_solve_mixed
+  const int64_t nb = block_of(o, n, nev);
+  if (kx < nev || kx > nb) return bad(13);
+  if (X0_ && k0 > 0 && (ldx0 < n || k0 > nb)) return bad(10);
+  if (k0 < 0) return bad(10);
+  if (!lambda) return bad(14);
+  if (!X_ || ldx < n) return bad(16);
+  if (nb > 4000) return bad(11);  // Rayleigh-Ritz eigensolver limit
+  const bool seeded = (X0_ != nullptr && k0 > 0);
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  gevp_ctx* c = h;
+  info->block = (int)nb;
+
+  const zd* A = (const zd*)A_;
+  const zd* B = (const zd*)B_;
+  const zd* X0 = (const zd*)X0_;
+  zd* X = (zd*)X_;
+
+  // ---------------- workspace
+  const size_t nn = (size_t)n * n;
+  const int lz = o.lanczos;
+  size_t need = 0;
+  need += 4 * ws_round(sizeof(zd) * nn);                 // Af, Bf, L, C
+  need += ws_round(sizeof(zd) * n * 64);                 // Dinv
+  need += 4 * ws_round(sizeof(zd) * n * nb);             // P0, P1, W, T
+  need += 3 * ws_round(sizeof(zd) * nb * nb);            // H, Z, G
+  need += ws_round(sizeof(zd) * nb * 64);                // DinvG
+  need += heev_work_bytes(nb);
+  need += lanczos_work_bytes(n, lz);
+  need += 3 * ws_round(sizeof(double) * 8);              // bounds C, A, B
+  need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, negl, spare
+  need += ws_round(sizeof(int) * nb);                    // perm
+  need += ws_round(sizeof(double) * 3 * 256);            // coefs
+  need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
+  need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
+  need += ws_round(sizeof(double) * 4);                  // norms
+  GEVP_TRY(ws_reserve(c, need));
+  zd* Af = (zd*)ws_take(c, sizeof(zd) * nn);
+  zd* Bf = (zd*)ws_take(c, sizeof(zd) * nn);
+  zd* L = (zd*)ws_take(c, sizeof(zd) * nn);
+  zd* C = (zd*)ws_take(c, sizeof(zd) * nn);
+  zd* Dinv = (zd*)ws_take(c, sizeof(zd) * n * 64);
+  zd* P0 = (zd*)ws_take(c, sizeof(zd) * n * nb);
+  zd* P1 = (zd*)ws_take(c, sizeof(zd) * n * nb);
+  zd* W = (zd*)ws_take(c, sizeof(zd) * n * nb);
+  zd* T = (zd*)ws_take(c, sizeof(zd) * n * nb);
+  zd* Hs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
+  zd* Zs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
+  zd* Gs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
+  zd* DinvG = (zd*)ws_take(c, sizeof(zd) * nb * 64);
+  void* heevw = ws_take(c, heev_work_bytes(nb));
+  void* lanw = ws_take(c, lanczos_work_bytes(n, lz));
+  double* bC = (double*)ws_take(c, sizeof(double) * 8);
+  double* bA = (double*)ws_take(c, sizeof(double) * 8);
+  double* bB = (double*)ws_take(c, sizeof(double) * 8);
+  double* theta = (double*)ws_take(c, sizeof(double) * nb);
+  double* rres = (double*)ws_take(c, sizeof(double) * nb);
+  double* fres = (double*)ws_take(c, sizeof(double) * nb);
+  (void)ws_take(c, sizeof(double) * nb);
+  int* perm = (int*)ws_take(c, sizeof(int) * nb);
+  double* coefs = (double*)ws_take(c, sizeof(double) * 3 * 256);
+  int* st_i = (int*)ws_take(c, sizeof(int) * 300);
+  double* st_d = (double*)ws_take(c, sizeof(double) * 16);
+  int* flags = (int*)ws_take(c, sizeof(int) * 8);
+  double* shift = (double*)ws_take(c, sizeof(double) * 8);
+  double* norms = (double*)ws_take(c, sizeof(double) * 4);
+
+  Timer tm(c);
+  // flags[0]: nonfinite input, flags[1]: Cholesky pivot of B, flags[2]: QR flag
+  int init_flags[4] = {0, 0x7fffffff, 0x7fffffff, 0};
+  GEVP_HIP_TRY(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, c->stream));
+
+  // ---------------- stage
+  tm.start();
+  GEVP_TRY(launch_mirror_lower(c, n, A, lda, Af, n, flags));
+  GEVP_TRY(launch_mirror_lower(c, n, B, ldb, Bf, n, flags));
+  if (seeded) GEVP_TRY(launch_check_finite(c, n, k0, X0, ldx0, flags));
+  tm.stop(info, GEVP_STAGE_STAGE);
+
+  // ---------------- Cholesky of B
+  tm.start();
+  GEVP_TRY(launch_copy2d(c, n, n, Bf, n, L, n));
+  GEVP_TRY(chol_lower(c, n, L, n, Dinv, n, flags + 1));
+  tm.stop(info, GEVP_STAGE_CHOL);
+  int hf[2];
+  GEVP_HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+  if (hf[0]) return GEVP_ERR_NONFINITE;
+  if (hf[1] != 0x7fffffff) {
+    info->lapack_info = n + hf[1];
+    return GEVP_ERR_NOT_HPD;
+  }
+
+  // ---------------- reduction to standard form
+  tm.start();
+  GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
+  GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
+  GEVP_TRY(trsm_right_lower_c(c, n, n, L, n, Dinv, n, C, n));
+  GEVP_TRY(launch_symmetrize(c, n, C, n));
+  tm.stop(info, GEVP_STAGE_REDUCE);
+
+  // ---------------- bounds
+  tm.start();
+  const double frac = std::min(1.0, (double)nb / (double)n);
+  GEVP_TRY(lanczos_bounds(c, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw));
+  GEVP_TRY(lanczos_bounds(c, n, Af, n, lz, o.seed ^ 0xA11CEull, frac, bA, lanw));
+  GEVP_TRY(lanczos_bounds(c, n, Bf, n, lz, o.seed ^ 0xB0Bull, frac, bB, lanw));
+  GEVP_TRY(launch_copy_real(c, 1, bA + 5, norms));
+  GEVP_TRY(launch_copy_real(c, 1, bB + 5, norms + 1));
+  tm.stop(info, GEVP_STAGE_BOUNDS);
+
+  // ---------------- initial block
+  if (seeded) {
+    // C-space seed: y = L^H x
+    GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, P0, n));
+  }
+  const int64_t kseed = seeded ? k0 : 0;
+  GEVP_TRY(launch_randn(c, n, nb - kseed, P0 + kseed * n, n, kseed, o.seed));
+
+  QrWork qw{Gs, DinvG, flags + 2, shift};
+  int fallbacks = 0;
+  CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, 0.0};
+  std::vector<int> hst(4 + 260);
+  std::vector<double> hsd(16);
+  int it = 0;
+  bool converged = false;
+  bool need_filter_first = !seeded && nb < n;
+  gevp_status st = GEVP_OK;
+
+  auto run_filter = [&](int maxdeg, const int* sj) -> gevp_status {
+    // columns permuted by degree into P1 (F0); F1 = P0; result lands in F0
+    zd* F[2] = {P1, P0};
+    GEVP_TRY(launch_gather_cols(c, n, nb, P0, n, perm, P1, n));
+    for (int j = 1; j <= maxdeg; ++j) {
+      const int64_t s0 = sj[j - 1];
+      const int64_t cols = nb - s0;
+      if (cols <= 0) break;
+      const double* cf = coefs + 3 * (j - 1);
+      zd* src = F[(j - 1) & 1];
+      zd* dst = F[j & 1];
+      if (j == 1)
+        GEVP_TRY(launch_zgemm(c, 0, 0, n, cols, n, 0.0, C, n, src + s0 * n, n, 0.0, src + s0 * n, n,
+                              0.0, nullptr, 0, nullptr, dst + s0 * n, n, cf));
+      else
+        GEVP_TRY(launch_zgemm(c, 0, 0, n, cols, n, 0.0, C, n, src + s0 * n, n, 0.0, src + s0 * n, n,
+                              0.0, dst + s0 * n, n, nullptr, dst + s0 * n, n, cf));
+    }
+    std::swap(P0, P1);
+    return GEVP_OK;
+  };
+
+  if (need_filter_first) {
+    cp.mode = 1;
+    GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs));
+    GEVP_HIP_TRY(hipMemcpyAsync(hst.data(), st_i, sizeof(int) * hst.size(), hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipMemcpyAsync(hsd.data(), st_d, sizeof(double) * hsd.size(), hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    tm.start();
+    GEVP_TRY(run_filter(hst[1], hst.data() + 4));
+    tm.stop(info, GEVP_STAGE_FILTER);
+    info->col_degrees += (int64_t)hsd[5];
+  }
+  cp.mode = 0;
+  for (it = 0; it < o.maxit; ++it) {
+    tm.start();
+    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks));
+    tm.stop(info, GEVP_STAGE_QR);
+    tm.start();
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, W, n));
+    GEVP_TRY(launch_zgemm(c, 1, 0, nb, nb, n, 1.0, P0, n, W, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, Hs, nb));
+    GEVP_TRY(launch_symmetrize(c, nb, Hs, nb));
+    GEVP_TRY(heev_small(c, nb, Hs, nb, theta, Zs, nb, heevw));
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, P1, n));
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, W, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, T, n));
+    std::swap(P0, P1);
+    std::swap(W, T);
+    GEVP_TRY(launch_resid_cols(c, n, nb, W, n, P0, n, theta, rres));
+    tm.stop(info, GEVP_STAGE_RR);
+    info->outer_iters = it + 1;
+    GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs));
+    GEVP_HIP_TRY(hipMemcpyAsync(hst.data(), st_i, sizeof(int) * hst.size(), hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipMemcpyAsync(hsd.data(), st_d, sizeof(double) * hsd.size(), hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    info->nconv = hst[0];
+    if (gevp_log_enabled())
+      fprintf(stderr, "[gevp] it %d nconv %d maxdeg %d a %.4g b %.4g tol %.3g\n", it, hst[0], hst[1],
+              hsd[0], hsd[1], hsd[4]);
+    if (hst[2]) {
+      converged = true;
+      break;
+    }
+    if (it + 1 == o.maxit) break;
+    tm.start();
+    GEVP_TRY(run_filter(hst[1], hst.data() + 4));
+    tm.stop(info, GEVP_STAGE_FILTER);
+    info->col_degrees += (int64_t)hsd[5];
+  }
+  info->qr_fallbacks = fallbacks;
+  info->filter_flops = 8.0 * (double)n * (double)n * (double)info->col_degrees;
+
+  // ---------------- back-transform and final residuals
+  tm.start();
+  GEVP_TRY(launch_copy2d(c, n, kx, P0, n, X, ldx));
+  GEVP_TRY(trsm_left_lower_c(c, n, kx, L, n, Dinv, n, X, ldx));
+  GEVP_TRY(launch_phase_normalize(c, n, kx, X, ldx));
+  GEVP_TRY(launch_copy_real(c, kx, theta, lambda));
+  double hn[2] = {0.0, 0.0};
+  GEVP_HIP_TRY(hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, c->stream));
+  if (!o.skip_final) {
+    // R = A X - B X diag(lambda): T = B X, then W = A X - diag-scaled T
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, kx, n, 1.0, Bf, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, T, n));
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, kx, n, 1.0, Af, n, X, ldx, 0.0, nullptr, 0, -1.0, T, n, theta,
+                          W, n));
+    GEVP_TRY(launch_colnorms(c, n, kx, W, n, fres));
+    if (resid_out) GEVP_TRY(launch_copy_real(c, kx, fres, resid_out));
+    std::vector<double> hr(kx);
+    GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kx, hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    double mx = 0.0;
+    for (int64_t i = 0; i < nev; ++i) mx = std::max(mx, hr[i]);
+    info->max_resid = (hn[0] > 0.0) ? mx / hn[0] : mx;
+    if (converged && info->max_resid > tol) st = GEVP_ERR_NOCONV;
+  } else {
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  tm.stop(info, GEVP_STAGE_FINAL);
+  info->normA = hn[0];
+  info->normB = hn[1];
+  if (!converged) st = GEVP_ERR_NOCONV;
+  if (st == GEVP_ERR_NOCONV) info->lapack_info = nev - info->nconv;
+  return st;
+}
+
+gevp_status gevp_backward(gevp_handle h, int64_t n, int64_t nev, const void* X_, int64_t ldx,
+                          const double* lambda, const double* w, void* dA_, int64_t ldda, void* dB_,
+                          int64_t lddb) {
+  if (!h || n < 1 || nev < 1 || nev > n || !X_ || ldx < n || !w) return GEVP_ERR_INVALID;
+  if (dA_ && ldda < n) return GEVP_ERR_INVALID;
+  if (dB_ && (lddb < n || !lambda)) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  gevp_ctx* c = h;
+  const zd* X = (const zd*)X_;
+  const size_t need = ws_round(sizeof(zd) * n * nev) + ws_round(sizeof(double) * nev);
+  GEVP_TRY(ws_reserve(c, need));
+  zd* Xw = (zd*)ws_take(c, sizeof(zd) * n * nev);
+  if (dA_) {
+    GEVP_TRY(launch_scale_cols(c, n, nev, X, ldx, w, Xw, n));
+    GEVP_TRY(launch_zgemm(c, 0, 1, n, n, nev, 1.0, Xw, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, (zd*)dA_, ldda));
+  }
+  if (dB_) {
+    double* wl = (double*)ws_take(c, sizeof(double) * nev);
+    (void)wl;
+    // dB = -X diag(w lambda) X^H: scale by w, then by lambda with alpha = -1
+    GEVP_TRY(launch_scale_cols(c, n, nev, X, ldx, w, Xw, n));
+    GEVP_TRY(launch_scale_cols(c, n, nev, Xw, n, lambda, Xw, n));
+    GEVP_TRY(launch_zgemm(c, 0, 1, n, n, nev, -1.0, Xw, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, (zd*)dB_, lddb));
+  }
+  return GEVP_OK;
+}
+
+gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, const int64_t* n,
+                               const void* const* A, const int64_t* lda, const void* const* B,
+                               const int64_t* ldb, const void* const* X0, const int64_t* ldx0,
+                               const int64_t* k0, const int64_t* nev, double tol,
+                               const int64_t* kx, double* const* lambda, void* const* X,
+                               const int64_t* ldx, double* const* resid, gevp_info* infos) {
+  if (!h || count < 0 || !n || !A || !lda || !B || !ldb || !nev || !lambda || !X || !ldx)
+    return GEVP_ERR_INVALID;
+  gevp_status worst = GEVP_OK;
+  for (int i = 0; i < count; ++i) {
+    const void* x0 = X0 ? X0[i] : nullptr;
+    const gevp_status s = gevp_solve(h, opts, n[i], A[i], lda[i], B[i], ldb[i], x0,
+                                     ldx0 ? ldx0[i] : n[i], (k0 && x0) ? k0[i] : 0, nev[i], tol,
+                                     kx ? kx[i] : nev[i], lambda[i], X[i], ldx[i],
+                                     resid ? resid[i] : nullptr, infos ? infos + i : nullptr);
+    if (s != GEVP_OK && (worst == GEVP_OK || s < worst || worst == GEVP_ERR_NOCONV)) worst = s;
+  }
+  return worst;
+}
+
+// ---- kernel-level entry points
+
+gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                         double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         double beta, const void* Cm, int64_t ldc, double gamma, const void* E,
+                         int64_t lde, const double* gcol, void* D, int64_t ldd) {
+  if (!h || m < 0 || n < 0 || k < 0 || !D) return GEVP_ERR_INVALID;
+  const int oa = (opA == 'C' || opA == 'c') ? 1 : 0;
+  const int ob = (opB == 'C' || opB == 'c') ? 1 : 0;
+  if (!(opA == 'N' || opA == 'n' || oa) || !(opB == 'N' || opB == 'n' || ob)) return GEVP_ERR_INVALID;
+  if (k > 0 && (!A || !B)) return GEVP_ERR_INVALID;
+  if (k > 0 && lda < (oa ? k : m)) return GEVP_ERR_INVALID;
+  if (k > 0 && ldb < (ob ? n : k)) return GEVP_ERR_INVALID;
+  if (ldd < m || (Cm && ldc < m) || (E && lde < m)) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  return launch_zgemm(h, oa, ob, m, n, k, alpha, (const zd*)A, lda, (const zd*)B, ldb, beta,
+                      (const zd*)Cm, ldc, gamma, (const zd*)E, lde, gcol, (zd*)D, ldd);
+}
+
+gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t* pivot) {
+  if (!h || n < 1 || !M || ldm < n) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, ws_round(sizeof(zd) * n * 64) + 256));
+  zd* Dinv = (zd*)ws_take(h, sizeof(zd) * n * 64);
+  int* flag = (int*)ws_take(h, sizeof(int) * 4);
+  const int big = 0x7fffffff;
+  GEVP_HIP_TRY(hipMemcpyAsync(flag, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  GEVP_TRY(chol_lower(h, n, (zd*)M, ldm, Dinv, n, flag));
+  int f = big;
+  GEVP_HIP_TRY(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
+  if (pivot) *pivot = (f == big) ? 0 : f;
+  return (f == big) ? GEVP_OK : GEVP_ERR_NOT_HPD;
+}
+
+gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t m, const void* L,
+                        int64_t ldl, void* R, int64_t ldr) {
+  if (!h || n < 1 || m < 0 || !L || ldl < n || !R) return GEVP_ERR_INVALID;
+  const bool left = (side == 'L' || side == 'l');
+  const bool conj = (trans == 'C' || trans == 'c');
+  if (!left && !(side == 'R' || side == 'r')) return GEVP_ERR_INVALID;
+  if (!conj && !(trans == 'N' || trans == 'n')) return GEVP_ERR_INVALID;
+  if (!left && !conj) return GEVP_ERR_INVALID;
+  if (ldr < (left ? n : m)) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  // the diagonal-block inverses come from re-factoring a copy of L L^H's
+  // diagonal blocks: L's own diagonal blocks are inverted directly instead
+  GEVP_TRY(ws_reserve(h, ws_round(sizeof(zd) * n * 64) + ws_round(sizeof(zd) * n * n) + 256));
+  zd* Dinv = (zd*)ws_take(h, sizeof(zd) * n * 64);
+  zd* Lc = (zd*)ws_take(h, sizeof(zd) * n * n);
+  GEVP_TRY(launch_copy2d(h, n, n, (const zd*)L, ldl, Lc, n));
+  GEVP_TRY(diag_block_inverses(h, n, Lc, n, Dinv, n));
+  if (left && !conj) return trsm_left_lower_n(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
+  if (left && conj) return trsm_left_lower_c(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
+  return trsm_right_lower_c(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
+}
+
+gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh, double* theta, void* Z,
+                        int64_t ldz) {
+  if (!h || n < 1 || n > 4000 || !H || ldh < n || !theta || !Z || ldz < n) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, heev_work_bytes(n) + ws_round(sizeof(zd) * n * n) + 256));
+  void* w = ws_take(h, heev_work_bytes(n));
+  zd* Hf = (zd*)ws_take(h, sizeof(zd) * n * n);
+  int* flag = (int*)ws_take(h, sizeof(int) * 4);
+  GEVP_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  GEVP_TRY(launch_mirror_lower(h, n, (const zd*)H, ldh, Hf, n, flag));
+  GEVP_TRY(heev_small(h, n, Hf, n, theta, (zd*)Z, ldz, w));
+  GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
+  return GEVP_OK;
+}
+
+}  // extern "C"

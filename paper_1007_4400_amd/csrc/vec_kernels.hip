@@ -1,0 +1,380 @@
+// Bandwidth-bound helper kernels: input mirroring and scans, transposes,
+// column norms and residual norms (wave64 reductions), column gathers,
+// counter-based random fill, phase normalisation, Hermitian matrix-vector
+// products for the Lanczos bounds.
+#include "common.h"
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum for 256 threads; every thread gets the result
+__device__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ bool finite2(zd v) { return isfinite(v.x) && isfinite(v.y); }
+
+// Full Hermitian copy from the lower triangle, 32 x 32 tiles through LDS so
+// the conjugate-transposed half is written coalesced.  Only tiles on or below
+// the diagonal are launched.
+__global__ __launch_bounds__(256) void k_mirror_lower(const zd* S, int64_t lds, zd* D, int64_t ldd,
+                                                      int64_t n, int* flag) {
+  __shared__ zd t[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  bool bad = false;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;  // element (i, j), column j
+    zd v = make_double2(0.0, 0.0);
+    if (i < n && j < n && i >= j) {
+      v = S[i + j * lds];
+      if (i == j) v.y = 0.0;
+      bad |= !finite2(v);
+    }
+    t[r][tx] = v;  // t[col][row]
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+    if (i < n && j < n && i >= j) D[i + j * ldd] = t[r][tx];
+  }
+  // conjugate transpose: D(j, i) = conj(S(i, j)) for i > j
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t row = bj * 32 + tx, col = bi * 32 + r;  // D(row, col), row < col
+    if (row < n && col < n && row < col) {
+      const zd v = t[tx][r];
+      D[row + col * ldd] = make_double2(v.x, -v.y);
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(256) void k_symmetrize(zd* M, int64_t ldm, int64_t n) {
+  __shared__ zd a[32][33], b[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;  // lower tile element
+    a[r][tx] = (i < n && j < n) ? M[i + j * ldm] : make_double2(0.0, 0.0);
+    const int64_t i2 = bj * 32 + tx, j2 = bi * 32 + r;  // mirrored tile element
+    b[r][tx] = (i2 < n && j2 < n) ? M[i2 + j2 * ldm] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // lower element (i, j) = (bi*32+tx, bj*32+r) pairs with upper (j, i) = b[tx][r]
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+    if (i < n && j < n && i >= j) {
+      const zd lo = a[r][tx], up = b[tx][r];
+      zd h = make_double2(0.5 * (lo.x + up.x), 0.5 * (lo.y - up.y));
+      if (i == j) h.y = 0.0;
+      M[i + j * ldm] = h;
+      M[j + i * ldm] = make_double2(h.x, -h.y);
+    }
+  }
+}
+
+__global__ void k_copy2d(int64_t rows, int64_t cols, const zd* S, int64_t lds, zd* D, int64_t ldd) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    D[i + j * ldd] = S[i + j * lds];
+}
+
+__global__ void k_check_finite(int64_t rows, const zd* S, int64_t lds, int* flag) {
+  const int64_t j = blockIdx.y;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !finite2(S[i + j * lds]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// splitmix64 finaliser: counter-based, so every (seed, column, row) maps to a
+// fixed value regardless of the launch shape
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_randn(int64_t rows, zd* V, int64_t ldv, int64_t col_offset, uint64_t seed) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = mix64(seed ^ mix64((uint64_t)(j + col_offset) * 0x100000001B3ull)) ^ (uint64_t)i;
+    const uint64_t r1 = mix64(key), r2 = mix64(key ^ 0xD1B54A32D192ED03ull);
+    const double u1 = ((r1 >> 11) + 1) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (r2 >> 11) * (1.0 / 9007199254740992.0);
+    const double rad = sqrt(-log(u1));  // E|z|^2 = 1
+    double s, co;
+    sincos(6.283185307179586 * u2, &s, &co);
+    V[i + j * ldv] = make_double2(rad * co, rad * s);
+  }
+}
+
+// one work-group per column: v <- v / ||v||  (zero columns left as they are)
+__global__ __launch_bounds__(256) void k_colnorm_scale(int64_t rows, zd* V, int64_t ldv) {
+  __shared__ double sh[4];
+  zd* v = V + blockIdx.x * ldv;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) s += v[i].x * v[i].x + v[i].y * v[i].y;
+  s = block_sum256(s, sh);
+  if (s > 0.0) {
+    const double inv = 1.0 / sqrt(s);
+    for (int64_t i = threadIdx.x; i < rows; i += 256) v[i] = make_double2(v[i].x * inv, v[i].y * inv);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colnorms(int64_t rows, const zd* V, int64_t ldv, double* out) {
+  __shared__ double sh[4];
+  const zd* v = V + blockIdx.x * ldv;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) s += v[i].x * v[i].x + v[i].y * v[i].y;
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+}
+
+// r_j = || W_j - theta_j V_j ||_2
+__global__ __launch_bounds__(256) void k_resid_cols(int64_t rows, const zd* W, int64_t ldw,
+                                                    const zd* V, int64_t ldv, const double* theta,
+                                                    double* out) {
+  __shared__ double sh[4];
+  const int64_t j = blockIdx.x;
+  const zd* w = W + j * ldw;
+  const zd* v = V + j * ldv;
+  const double th = theta[j];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    const double rx = w[i].x - th * v[i].x, ry = w[i].y - th * v[i].y;
+    s += rx * rx + ry * ry;
+  }
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) out[j] = sqrt(s);
+}
+
+__global__ void k_gather_cols(int64_t rows, const zd* S, int64_t lds, const int* perm, zd* D,
+                              int64_t ldd) {
+  const int64_t j = blockIdx.y;
+  const zd* s = S + (int64_t)perm[j] * lds;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    D[i + j * ldd] = s[i];
+}
+
+__global__ void k_scale_cols(int64_t rows, const zd* S, int64_t lds, const double* w, zd* D,
+                             int64_t ldd) {
+  const int64_t j = blockIdx.y;
+  const double a = w[j];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const zd v = S[i + j * lds];
+    D[i + j * ldd] = make_double2(a * v.x, a * v.y);
+  }
+}
+
+// Largest-modulus entry of each column made real and positive (lowest index
+// among entries within 1e-12 relative of the maximum).
+__global__ __launch_bounds__(256) void k_phase_normalize(int64_t rows, zd* X, int64_t ldx) {
+  __shared__ double shm[256];
+  __shared__ int shi[256];
+  zd* x = X + blockIdx.x * ldx;
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) m = fmax(m, hypot(x[i].x, x[i].y));
+  shm[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double amax = shm[0];
+  __syncthreads();
+  int best = INT32_MAX;
+  for (int64_t i = threadIdx.x; i < rows; i += 256)
+    if (hypot(x[i].x, x[i].y) >= amax * (1.0 - 1e-12)) {
+      best = (int)i;
+      break;
+    }
+  shi[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) shi[threadIdx.x] = min(shi[threadIdx.x], shi[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const int piv = shi[0];
+  if (amax == 0.0 || piv == INT32_MAX) return;
+  const zd p = x[piv];
+  const double a = hypot(p.x, p.y);
+  const double cr = p.x / a, ci = -p.y / a;  // conj(p)/|p|
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < rows; i += 256) {
+    const zd v = x[i];
+    x[i] = make_double2(v.x * cr - v.y * ci, v.x * ci + v.y * cr);
+  }
+}
+
+// y_i = sum_j conj(M(j, i)) x_j, which is (M x)_i for Hermitian M: one wave
+// per output entry reads column i contiguously.
+__global__ __launch_bounds__(256) void k_hemv_cols(int64_t n, const zd* M, int64_t ldm, const zd* x,
+                                                   zd* y) {
+  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const zd* col = M + i * ldm;
+  double sr = 0.0, si = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const zd a = col[j], b = x[j];
+    sr += a.x * b.x + a.y * b.y;
+    si += a.x * b.y - a.y * b.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) y[i] = make_double2(sr, si);
+}
+
+__global__ void k_add_diag(int64_t n, zd* M, int64_t ldm, const double* shift) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) M[i + i * ldm].x += shift[0];
+}
+
+__global__ void k_copy_real(int64_t n, const double* s, double* d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+inline unsigned gx(int64_t rows) {
+  int64_t b = (rows + 255) / 256;
+  return (unsigned)(b < 64 ? (b < 1 ? 1 : b) : 64);
+}
+}  // namespace
+
+gevp_status launch_mirror_lower(gevp_ctx* c, int64_t n, const zd* S, int64_t lds, zd* D,
+                                int64_t ldd, int* flag) {
+  if (n <= 0) return GEVP_OK;
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_mirror_lower, dim3(t, t), dim3(256), 0, c->stream, S, lds, D, ldd, n, flag);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_symmetrize(gevp_ctx* c, int64_t n, zd* M, int64_t ldm) {
+  if (n <= 0) return GEVP_OK;
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_symmetrize, dim3(t, t), dim3(256), 0, c->stream, M, ldm, n);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_copy2d(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                          zd* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_copy2d, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows, cols,
+                     S, lds, D, ldd);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_check_finite(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                                int* flag) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_check_finite, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows,
+                     S, lds, flag);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_randn(gevp_ctx* c, int64_t rows, int64_t cols, zd* V, int64_t ldv,
+                         int64_t col_offset, unsigned long long seed) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_randn, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows, V, ldv,
+                     col_offset, (uint64_t)seed);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_colnorm_scale(gevp_ctx* c, int64_t rows, int64_t cols, zd* V, int64_t ldv) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_colnorm_scale, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, V, ldv);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_colnorms(gevp_ctx* c, int64_t rows, int64_t cols, const zd* V, int64_t ldv,
+                            double* out) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_colnorms, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, V, ldv, out);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* W, int64_t ldw,
+                              const zd* V, int64_t ldv, const double* theta, double* out) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_resid_cols, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, W, ldw, V,
+                     ldv, theta, out);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                               const int* perm, zd* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_gather_cols, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows,
+                     S, lds, perm, D, ldd);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_scale_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                              const double* w, zd* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_scale_cols, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows, S,
+                     lds, w, D, ldd);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_phase_normalize, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, X, ldx);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_hemv_cols(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y) {
+  if (n <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_hemv_cols, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, n, M, ldm,
+                     x, y);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const double* shift) {
+  if (n <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_add_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, M,
+                     ldm, shift);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d) {
+  if (n <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_copy_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, s,
+                     d);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}

@@ -1,0 +1,269 @@
+"""ctypes binding of ``libgevp.so`` (declared in ``include/gevp.h``).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels on the GPU.  Tensors are torch tensors on the handle's device; the
+library reads matrices column-major, so inputs that are not already
+column-major (``t.stride() == (1, n)``) are copied into that layout, and
+outputs are returned as column-major views with the usual (rows, cols)
+shape.  If the library is missing the binding raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgevp.so")
+
+GEVP_OK, GEVP_ERR_INVALID, GEVP_ERR_NOT_HPD, GEVP_ERR_NOCONV = 0, 1, 2, 3
+GEVP_ERR_HIP, GEVP_ERR_NONFINITE, GEVP_ERR_ALLOC = 4, 5, 6
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+STAGES = ("stage", "chol", "reduce", "bounds", "filter", "qr", "rr", "final")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int), ("nex", ctypes.c_int), ("deg_init", ctypes.c_int),
+        ("deg_max", ctypes.c_int), ("maxit", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong), ("skip_final_residual", ctypes.c_int),
+        ("reserved", ctypes.c_int * 8),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("lapack_info", ctypes.c_int64), ("outer_iters", ctypes.c_int), ("nconv", ctypes.c_int),
+        ("block", ctypes.c_int), ("qr_fallbacks", ctypes.c_int), ("col_degrees", ctypes.c_int64),
+        ("max_resid", ctypes.c_double), ("normA", ctypes.c_double), ("normB", ctypes.c_double),
+        ("filter_flops", ctypes.c_double), ("ms", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms"}
+        d["ms"] = {s: self.ms[i] for i, s in enumerate(STAGES)}
+        return d
+
+
+class GevpError(RuntimeError):
+    def __init__(self, status: int, what: str, info: Optional[Info] = None):
+        self.status = status
+        self.info = info
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+
+def load():
+    """Load libgevp.so (built by ``paper_1007_4400_amd.build``); raises if it
+    is missing -- the product path has no CPU fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1007_4400_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, L, D, C = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_char
+    lib.gevp_status_string.argtypes = [I]
+    lib.gevp_status_string.restype = ctypes.c_char_p
+    lib.gevp_create.argtypes = [ctypes.POINTER(P), I]
+    lib.gevp_create.restype = I
+    lib.gevp_set_stream.argtypes = [P, P]
+    lib.gevp_set_stream.restype = I
+    lib.gevp_set_profiling.argtypes = [P, I]
+    lib.gevp_set_profiling.restype = I
+    lib.gevp_destroy.argtypes = [P]
+    lib.gevp_destroy.restype = None
+    lib.gevp_block_size.argtypes = [ctypes.POINTER(Opts), L, L]
+    lib.gevp_block_size.restype = L
+    lib.gevp_solve.argtypes = [P, ctypes.POINTER(Opts), L, P, L, P, L, P, L, L, L, D, L, P, P, L, P,
+                               ctypes.POINTER(Info)]
+    lib.gevp_solve.restype = I
+    lib.gevp_solve_batched.argtypes = [P, ctypes.POINTER(Opts), I, P, P, P, P, P, P, P, P, P, D, P,
+                                       P, P, P, P, ctypes.POINTER(Info)]
+    lib.gevp_solve_batched.restype = I
+    lib.gevp_backward.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
+    lib.gevp_backward.restype = I
+    lib.gevp_k_zgemm.argtypes = [P, C, C, L, L, L, D, P, L, P, L, D, P, L, D, P, L, P, P, L]
+    lib.gevp_k_zgemm.restype = I
+    lib.gevp_k_potrf.argtypes = [P, L, P, L, ctypes.POINTER(L)]
+    lib.gevp_k_potrf.restype = I
+    lib.gevp_k_trsm.argtypes = [P, C, C, L, L, P, L, P, L]
+    lib.gevp_k_trsm.restype = I
+    lib.gevp_k_heev.argtypes = [P, L, P, L, P, P, L]
+    lib.gevp_k_heev.restype = I
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    return load().gevp_status_string(int(s)).decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def colmajor(t: torch.Tensor) -> torch.Tensor:
+    """Column-major (Fortran-order) version of a 2-D tensor; no copy when it
+    already is one."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    r, c = t.shape
+    if t.stride(0) == 1 and (t.stride(1) >= max(r, 1) or c == 1):
+        return t
+    return t.mT.contiguous().mT
+
+
+def empty_colmajor(rows: int, cols: int, dtype=torch.complex128, device=None) -> torch.Tensor:
+    return torch.empty((cols, rows), dtype=dtype, device=device).mT
+
+
+def _ld(t: torch.Tensor) -> int:
+    return max(int(t.stride(1)), int(t.shape[0]), 1)
+
+
+def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_steps=0, seed=0,
+              skip_final_residual=False) -> Opts:
+    o = Opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.nex, o.deg_init, o.deg_max, o.maxit = nex, deg_init, deg_max, maxit
+    o.lanczos_steps, o.seed = lanczos_steps, seed
+    o.skip_final_residual = int(bool(skip_final_residual))
+    return o
+
+
+class Handle:
+    """One library handle (workspace owner) on a CUDA/HIP device."""
+
+    def __init__(self, device: int = 0, profiling: bool = False):
+        lib = load()
+        self.lib = lib
+        self.device = device
+        h = ctypes.c_void_p()
+        s = lib.gevp_create(ctypes.byref(h), device)
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_create")
+        self.h = h
+        if profiling:
+            lib.gevp_set_profiling(h, 1)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gevp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.gevp_set_stream(self.h, ctypes.c_void_p(st))
+
+    def block_size(self, n, nev, opts: Optional[Opts] = None) -> int:
+        return int(self.lib.gevp_block_size(ctypes.byref(opts or make_opts()), n, nev))
+
+    # ------------------------------------------------------------------ solve
+    def solve(self, A, B, nev, X0=None, tol=1e-10, kx=None, opts: Optional[Opts] = None,
+              raise_on_noconv=True):
+        """Lowest ``nev`` eigenpairs of A x = lambda B x.  Returns
+        (lam[kx], X[n, kx], resid[kx], info dict)."""
+        opts = opts or make_opts()
+        A = colmajor(A)
+        B = colmajor(B)
+        n = A.shape[0]
+        kx = nev if kx is None else kx
+        dev = A.device
+        lam = torch.empty(kx, dtype=torch.float64, device=dev)
+        X = empty_colmajor(n, kx, device=dev)
+        res = torch.empty(kx, dtype=torch.float64, device=dev)
+        k0 = 0
+        if X0 is not None:
+            X0 = colmajor(X0)
+            k0 = X0.shape[1]
+        info = Info()
+        self._stream()
+        s = self.lib.gevp_solve(self.h, ctypes.byref(opts), n, _ptr(A), _ld(A), _ptr(B), _ld(B),
+                                _ptr(X0), _ld(X0) if X0 is not None else n, k0, nev, float(tol), kx,
+                                _ptr(lam), _ptr(X), _ld(X), _ptr(res), ctypes.byref(info))
+        if s != GEVP_OK and not (s == GEVP_ERR_NOCONV and not raise_on_noconv):
+            raise GevpError(s, "gevp_solve", info)
+        d = info.as_dict()
+        d["status"] = s
+        return lam, X, res, d
+
+    def backward(self, X, lam, w, want_dA=True, want_dB=True):
+        X = colmajor(X)
+        n, nev = X.shape
+        dA = empty_colmajor(n, n, device=X.device) if want_dA else None
+        dB = empty_colmajor(n, n, device=X.device) if want_dB else None
+        lam = lam.contiguous()
+        w = w.to(torch.float64).contiguous()
+        self._stream()
+        s = self.lib.gevp_backward(self.h, n, nev, _ptr(X), _ld(X), _ptr(lam), _ptr(w), _ptr(dA),
+                                   n, _ptr(dB), n)
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_backward")
+        return dA, dB
+
+    # ------------------------------------------------------------ kernels
+    def zgemm(self, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, gamma=0.0, E=None, gcol=None,
+              out=None, m=None, n=None, k=None):
+        A = colmajor(A)
+        B = colmajor(B)
+        m = m if m is not None else (A.shape[0] if opA == "N" else A.shape[1])
+        k = k if k is not None else (A.shape[1] if opA == "N" else A.shape[0])
+        n = n if n is not None else (B.shape[1] if opB == "N" else B.shape[0])
+        if out is None:
+            out = empty_colmajor(m, n, device=A.device)
+        C = colmajor(C) if C is not None else None
+        E = colmajor(E) if E is not None else None
+        self._stream()
+        s = self.lib.gevp_k_zgemm(self.h, opA.encode(), opB.encode(), m, n, k, float(alpha),
+                                  _ptr(A), _ld(A), _ptr(B), _ld(B), float(beta), _ptr(C),
+                                  _ld(C) if C is not None else m, float(gamma), _ptr(E),
+                                  _ld(E) if E is not None else m, _ptr(gcol), _ptr(out), _ld(out))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_zgemm")
+        return out
+
+    def potrf(self, M):
+        """In-place lower Cholesky on a column-major copy; returns (L, pivot)."""
+        L = colmajor(M).clone()
+        n = L.shape[0]
+        piv = ctypes.c_int64(0)
+        self._stream()
+        s = self.lib.gevp_k_potrf(self.h, n, _ptr(L), _ld(L), ctypes.byref(piv))
+        if s not in (GEVP_OK, GEVP_ERR_NOT_HPD):
+            raise GevpError(s, "gevp_k_potrf")
+        return L, int(piv.value)
+
+    def trsm(self, side, trans, L, R):
+        L = colmajor(L)
+        R = colmajor(R).clone()
+        n = L.shape[0]
+        m = R.shape[1] if side == "L" else R.shape[0]
+        self._stream()
+        s = self.lib.gevp_k_trsm(self.h, side.encode(), trans.encode(), n, m, _ptr(L), _ld(L),
+                                 _ptr(R), _ld(R))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_trsm")
+        return R
+
+    def heev(self, H):
+        H = colmajor(H).clone()
+        n = H.shape[0]
+        th = torch.empty(n, dtype=torch.float64, device=H.device)
+        Z = empty_colmajor(n, n, device=H.device)
+        self._stream()
+        s = self.lib.gevp_k_heev(self.h, n, _ptr(H), _ld(H), _ptr(th), _ptr(Z), _ld(Z))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_heev")
+        return th, Z

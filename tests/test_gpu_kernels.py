@@ -1,0 +1,133 @@
+"""Kernel-level parity of the HIP building blocks against plain definitions
+(numpy complex128 products and solves, and the CPU oracle for the small
+eigensolver), at sizes that span several 64-wide tiles plus ragged tails."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _cn(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1007_4400_amd import gevp
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return gevp.Handle(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (70, 45, 33), (130, 200, 257), (1, 3, 1)])
+def test_zgemm_ops(h, opA, opB, m, n, k):
+    print(f"zgemm {opA}{opB} m={m} n={n} k={k}", flush=True)
+    rng = np.random.default_rng(m * 1000 + n + k)
+    A = _cn(rng, *((m, k) if opA == "N" else (k, m)))
+    B = _cn(rng, *((k, n) if opB == "N" else (n, k)))
+    C = _cn(rng, m, n)
+    E = _cn(rng, m, n)
+    g = rng.standard_normal(n)
+    opa = A if opA == "N" else A.conj().T
+    opb = B if opB == "N" else B.conj().T
+    ref = 1.5 * opa @ opb - 0.25 * C + 0.75 * E * g[None, :]
+    out = h.zgemm(opA, opB, _dev(A), _dev(B), alpha=1.5, beta=-0.25, C=_dev(C), gamma=0.75,
+                  E=_dev(E), gcol=_dev(g))
+    torch.cuda.synchronize()
+    err = np.max(np.abs(_np(out) - ref)) / max(1.0, np.max(np.abs(ref)))
+    assert err <= 1e-14 * np.sqrt(k) * 10
+
+
+def test_zgemm_plain_and_inplace_beta(h):
+    rng = np.random.default_rng(5)
+    m, n, k = 300, 190, 410
+    A, B, C = _cn(rng, m, k), _cn(rng, k, n), _cn(rng, m, n)
+    Cd = h.zgemm("N", "N", _dev(A), _dev(B))
+    Dd = _dev(C)
+    from paper_1007_4400_amd import gevp
+
+    Dd = gevp.colmajor(Dd)
+    h.zgemm("N", "N", _dev(A), _dev(B), alpha=-1.0, beta=1.0, C=Dd, out=Dd)
+    torch.cuda.synchronize()
+    assert np.allclose(_np(Cd), A @ B, rtol=0, atol=1e-12)
+    assert np.allclose(_np(Dd), C - A @ B, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333])
+def test_potrf(h, n):
+    print(f"potrf n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    G = _cn(rng, n, n)
+    M = G @ G.conj().T + n * np.eye(n)
+    L, piv = h.potrf(_dev(M))
+    torch.cuda.synchronize()
+    assert piv == 0
+    Lr = np.linalg.cholesky(M)
+    assert np.max(np.abs(_np(L) - Lr)) <= 1e-12 * np.max(np.abs(Lr))
+
+
+def test_potrf_not_hpd_reports_pivot(h):
+    n = 150
+    M = np.eye(n, dtype=complex)
+    M[97, 97] = -2.0
+    _, piv = h.potrf(_dev(M))
+    assert piv == 98
+
+
+@pytest.mark.parametrize("side,trans", [("L", "N"), ("L", "C"), ("R", "C")])
+@pytest.mark.parametrize("n,m", [(64, 10), (150, 77), (257, 130)])
+def test_trsm(h, side, trans, n, m):
+    print(f"trsm {side}{trans} n={n} m={m}", flush=True)
+    rng = np.random.default_rng(n + m)
+    L = np.tril(_cn(rng, n, n)) * 0.1 + np.diag(2.0 + rng.random(n))
+    R = _cn(rng, n, m) if side == "L" else _cn(rng, m, n)
+    out = _np(h.trsm(side, trans, _dev(L), _dev(R)))
+    if side == "L" and trans == "N":
+        ref = np.linalg.solve(L, R)
+    elif side == "L":
+        ref = np.linalg.solve(L.conj().T, R)
+    else:
+        ref = R @ np.linalg.inv(L.conj().T)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 130, 301])
+def test_heev_vs_oracle(h, n, oracle_mod):
+    print(f"heev n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    G = _cn(rng, n, n)
+    H = 0.5 * (G + G.conj().T)
+    th, Z = h.heev(_dev(H))
+    torch.cuda.synchronize()
+    th, Z = _np(th), _np(Z)
+    lam, _ = oracle_mod.solve(H, np.eye(n, dtype=complex), n)
+    nrm = max(1.0, np.max(np.abs(lam)))
+    assert np.max(np.abs(th - lam)) <= 1e-13 * nrm * max(1, np.sqrt(n))
+    assert np.max(np.abs(H @ Z - Z * th[None, :])) <= 1e-12 * nrm * max(1, np.sqrt(n))
+    assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10
+
+
+def test_heev_degenerate(h, oracle_mod):
+    # repeated eigenvalues: an invariant subspace, not unique vectors
+    n = 40
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(_cn(rng, n, n))
+    ev = np.repeat(np.arange(8, dtype=float), 5)
+    H = (Q * ev) @ Q.conj().T
+    H = 0.5 * (H + H.conj().T)
+    th, Z = h.heev(_dev(H))
+    th, Z = _np(th), _np(Z)
+    assert np.max(np.abs(th - ev)) <= 1e-12
+    assert np.max(np.abs(H @ Z - Z * th[None, :])) <= 1e-11
+    assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10

@@ -1,0 +1,145 @@
+"""Solver parity on the GPU against the FP64 CPU oracle (the paper, section 1,
+eq. (3): lowest eigenpairs of A x = lambda B x), cold and seeded (section 2,
+"Eigenvectors evolution": the previous iteration's eigenvectors initialise
+the next solve).
+
+Bar (written here, derived in the design notes): eigenvalues
+|d lambda_i| <= 1e-10 max(|lambda_i|, 1); residuals ||A x - lambda B x|| <=
+1e-10 ||A||_2 (computed by the oracle, not the library); eigenvectors compared
+by the phase-invariant |x_oracle^H B x_gpu| = 1 (simple eigenvalues);
+B-orthonormality max |X^H B X - I| <= 1e-9.
+"""
+import numpy as np
+import pytest
+
+from paper_1007_4400_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1007_4400_amd import gevp
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return gevp.Handle(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).to("cuda")
+
+
+def _check(oracle_mod, A, B, lam, X, nev, lam_ref=None, X_ref=None):
+    lam = lam.cpu().numpy()[:nev]
+    X = X.cpu().numpy()[:, :nev]
+    if lam_ref is None:
+        lam_ref, X_ref = oracle_mod.solve(A, B, nev)
+    err = np.abs(lam - lam_ref) / np.maximum(np.abs(lam_ref), 1.0)
+    assert err.max() <= TOL, f"eigenvalue error {err.max():.3e}"
+    res, orth = oracle_mod.residuals(A, B, lam, X)
+    nA = np.linalg.norm(A, 2)
+    assert res.max() <= TOL * nA, f"residual {res.max() / nA:.3e} ||A||"
+    assert orth <= 1e-9, f"B-orthonormality {orth:.3e}"
+    ov = np.abs(np.sum(X_ref.conj() * (B @ X), axis=0))
+    assert np.max(np.abs(ov - 1.0)) <= 1e-8
+    return lam_ref, X_ref
+
+
+@pytest.mark.parametrize("n,nev", [(40, 5), (256, 16), (300, 30)])
+def test_cold_small(h, oracle_mod, n, nev):
+    print(f"cold solve n={n} nev={nev}", flush=True)
+    wl = synth.scaled(synth.SMALL, n, nev=nev) if n == 256 else synth.scaled(synth.MEDIUM, n, nev=nev)
+    p, _ = synth.make_pencil(wl, 0)
+    lam, X, res, info = h.solve(_dev(p.A), _dev(p.B), nev, tol=TOL)
+    torch.cuda.synchronize()
+    print(info, flush=True)
+    ex, Xe = p.exact_lowest(nev)
+    _check(oracle_mod, p.A, p.B, lam, X, nev)
+    assert np.max(np.abs(lam.cpu().numpy() - ex) / np.maximum(np.abs(ex), 1)) <= TOL
+
+
+def test_sequence_seeded_small(h, oracle_mod):
+    wl = synth.SMALL
+    prev = None
+    iters = []
+    for k, (A, B) in enumerate(synth.sequence(wl, 0)):
+        print(f"sequence step {k}", flush=True)
+        X0 = prev
+        kx = h.block_size(wl.n, wl.nev)
+        lam, X, res, info = h.solve(_dev(A), _dev(B), wl.nev, X0=X0, tol=TOL, kx=kx)
+        _check(oracle_mod, A, B, lam, X, wl.nev)
+        prev = X
+        iters.append(info["outer_iters"])
+    print("outer iterations per step", iters, flush=True)
+
+
+def test_seeded_equals_cold(h, oracle_mod):
+    wl = synth.scaled(synth.MEDIUM, 384)
+    seq = list(synth.sequence(wl, 2, steps=2))
+    A1, B = seq[1]
+    kx = h.block_size(wl.n, wl.nev)
+    _, X0, _, _ = h.solve(_dev(seq[0][0]), _dev(B), wl.nev, tol=TOL, kx=kx)
+    lam_s, X_s, _, info_s = h.solve(_dev(A1), _dev(B), wl.nev, X0=X0, tol=TOL)
+    lam_c, X_c, _, info_c = h.solve(_dev(A1), _dev(B), wl.nev, tol=TOL)
+    ref = _check(oracle_mod, A1, B, lam_s, X_s, wl.nev)
+    _check(oracle_mod, A1, B, lam_c, X_c, wl.nev, *ref)
+    print("seeded", info_s["outer_iters"], info_s["col_degrees"], "cold", info_c["outer_iters"],
+          info_c["col_degrees"], flush=True)
+    assert info_s["col_degrees"] <= info_c["col_degrees"]
+
+
+def test_not_hpd(h):
+    from paper_1007_4400_amd import gevp
+
+    n = 100
+    A = np.eye(n, dtype=complex)
+    B = np.eye(n, dtype=complex)
+    B[40, 40] = -1.0
+    with pytest.raises(gevp.GevpError) as e:
+        h.solve(_dev(A), _dev(B), 4)
+    assert e.value.status == gevp.GEVP_ERR_NOT_HPD
+    assert e.value.info.lapack_info == n + 41
+
+
+def test_nonfinite_input(h):
+    from paper_1007_4400_amd import gevp
+
+    n = 50
+    A = np.eye(n, dtype=complex)
+    A[30, 2] = np.nan
+    with pytest.raises(gevp.GevpError) as e:
+        h.solve(_dev(A), _dev(np.eye(n, dtype=complex)), 4)
+    assert e.value.status == gevp.GEVP_ERR_NONFINITE
+
+
+def test_invalid_arguments(h):
+    from paper_1007_4400_amd import gevp
+
+    A = _dev(np.eye(8, dtype=complex))
+    with pytest.raises(gevp.GevpError) as e:
+        h.solve(A, A, 9)
+    assert e.value.status == gevp.GEVP_ERR_INVALID
+    with pytest.raises(gevp.GevpError):
+        h.solve(A, A, 2, tol=-1.0)
+
+
+def test_backward_matches_oracle_gradient(h, oracle_mod):
+    wl = synth.scaled(synth.GRAD, 200)
+    p, _ = synth.make_pencil(wl, 1)
+    lam, X, _, _ = h.solve(_dev(p.A), _dev(p.B), wl.nev, tol=TOL)
+    lam_n = lam.cpu().numpy()
+    mu = lam_n[int(0.9 * wl.nev)]
+    f = 1.0 / (1.0 + np.exp((lam_n - mu) / 0.01))
+    dA, dB = h.backward(X, lam, torch.from_numpy(f).cuda())
+    GA, GB = oracle_mod.grad(X.cpu().numpy(), lam_n, f)
+    dA, dB = dA.cpu().numpy(), dB.cpu().numpy()
+    assert np.linalg.norm(dA - GA) <= 1e-12 * np.linalg.norm(GA)
+    assert np.linalg.norm(dB - GB) <= 1e-12 * np.linalg.norm(GB)
+    # and against the oracle's own eigenvectors (phase-free quantity)
+    lam_o, X_o = oracle_mod.solve(p.A, p.B, wl.nev)
+    GA_o, _ = oracle_mod.grad(X_o, lam_o, f)
+    assert np.linalg.norm(dA - GA_o) <= 1e-6 * np.linalg.norm(GA_o)
