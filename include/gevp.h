@@ -80,11 +80,13 @@ typedef struct {
   int nconv;              /* converged wanted pairs (nev on success) */
   int block;              /* nev + nex */
   int qr_fallbacks;       /* shifted-CholQR fallbacks taken */
-  int64_t col_degrees;    /* sum over sweeps of filtered column-degrees */
+  int64_t col_degrees;    /* filter GEMM column-steps summed over sweeps (8 n^2 flops each) */
   double max_resid;       /* max_i ||A x_i - lambda_i B x_i||_2 / ||A||_2 (original basis) */
   double normA, normB;    /* Lanczos estimates of ||A||_2, ||B||_2 */
   double filter_flops;    /* useful filter flops, 8 n^2 per column-degree */
-  double ms[8];           /* stage times (ms) when profiling is on: see gevp_stage */
+  double ms[8];           /* stage times (ms), profiling bit 0: see gevp_stage */
+  double filter_kernel_ms;  /* summed duration of the filter GEMM launches, profiling bit 1 */
+  int64_t filter_launches;  /* number of those launches */
 } gevp_info;
 
 typedef enum {
@@ -104,8 +106,10 @@ gevp_status gevp_create(gevp_handle* h, int device);
 /* Run subsequent work on `hip_stream` (a hipStream_t; NULL = null stream). */
 gevp_status gevp_set_stream(gevp_handle h, void* hip_stream);
 
-/* 1: record per-stage HIP event times into gevp_info.ms (adds syncs). */
-gevp_status gevp_set_profiling(gevp_handle h, int on);
+/* Profiling bits: 1 = per-stage HIP event times into gevp_info.ms (adds a
+ * synchronisation per stage); 2 = HIP events around every filter GEMM launch,
+ * summed into gevp_info.filter_kernel_ms (no added synchronisation). */
+gevp_status gevp_set_profiling(gevp_handle h, int flags);
 
 /* Free the workspace and the handle. */
 void gevp_destroy(gevp_handle h);
@@ -197,7 +201,7 @@ gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t
 gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t m,
                         const void* L, int64_t ldl, void* R, int64_t ldr);
 
-/* Eigen-decomposition of a small Hermitian matrix (n <= 4096) on the GPU:
+/* Eigen-decomposition of a small Hermitian matrix (n <= 2048) on the GPU:
  * H = Z diag(theta) Z^H, theta ascending.  H (lower read) is overwritten.
  * Synchronous. */
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,

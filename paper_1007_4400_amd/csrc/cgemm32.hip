@@ -1,0 +1,265 @@
+// Complex64 filter GEMM on the FP32 matrix cores (v_mfma_f32_16x16x4f32)
+// for the mixed-precision Chebyshev filter:
+//
+//   D(:, j) = alpha_j C G(:, j) + beta_j G(:, j) + gamma_j P(:, j) + delta_j R(:, j)
+//
+// with per-column coefficients (device float64 arrays, one entry per active
+// column).  C is the FP32 copy of the reduced matrix, G the current iterate,
+// P the previous one (D may alias P) and R the FP32 residual block.  Same
+// tiling, LDS staging and XCD-aware tile order as the FP64 kernel; the
+// accumulators are FP32.
+#include "common.h"
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float2 zf;
+
+namespace {
+constexpr int BM = 64, BN = 64, KT = 16, NTHR = 256;
+constexpr int PADA = BM + 1, PADB = BN + 1;
+
+struct CgemmParams {
+  int M, N, K;
+  const zf* A;
+  int64_t lda;
+  const zf* B;
+  int64_t ldb;
+  const zf* P;
+  int64_t ldp;
+  const zf* R;
+  int64_t ldr;
+  zf* D;
+  int64_t ldd;
+  const double* alpha;  // per column
+  const double* beta;
+  const double* gamma;
+  const double* delta;
+  int tiles_n, total, remap;
+};
+
+__global__ __launch_bounds__(NTHR, 2) void k_cgemm32_filter(CgemmParams p) {
+  __shared__ zf As[2][KT][PADA];
+  __shared__ zf Bs[2][KT][PADB];
+  const int tid = threadIdx.x;
+  int L = blockIdx.x;
+  if (p.remap) {
+    const int per = p.total >> 3;
+    L = (L & 7) * per + (L >> 3);
+  }
+  const int tm = L / p.tiles_n, tn = L - tm * p.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  f4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = f4{0, 0, 0, 0};
+      accI[i][j] = f4{0, 0, 0, 0};
+    }
+  zf ra[4], rb[4];
+  const zf zero = make_float2(0.f, 0.f);
+  auto load = [&](int k0) {
+    const int m = tid & 63, gm = row0 + m;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gk = k0 + (tid >> 6) + 4 * i;
+      ra[i] = (gm < p.M && gk < p.K) ? p.A[gm + (int64_t)gk * p.lda] : zero;
+    }
+    const int k = tid & 15, gk = k0 + k;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gn = col0 + (tid >> 4) + 16 * i;
+      rb[i] = (gn < p.N && gk < p.K) ? p.B[gk + (int64_t)gn * p.ldb] : zero;
+    }
+  };
+  auto store = [&](int buf) {
+    const int m = tid & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) As[buf][(tid >> 6) + 4 * i][m] = ra[i];
+    const int k = tid & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Bs[buf][k][(tid >> 4) + 16 * i] = rb[i];
+  };
+  const int nk = (p.K + KT - 1) / KT;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) load((t + 1) * KT);
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      const int kk = ks * 4 + lg;
+      zf a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk][wr * 32 + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk][wc * 32 + j * 16 + l16];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, accR[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].y, accI[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i].y, b[j].y, accR[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
+    }
+    if (t + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  // D layout of v_mfma_f32_16x16x4f32: lane l, register r -> row 4 (l/16) + r, col l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = col0 + wc * 32 + j * 16 + l16;
+      if (col >= p.N) continue;
+      const float al = (float)p.alpha[col], be = (float)p.beta[col];
+      const float ga = (float)p.gamma[col], de = (float)p.delta[col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + i * 16 + 4 * lg + r;
+        if (row >= p.M) continue;
+        const zf g = p.B[row + (int64_t)col * p.ldb];
+        float vr = al * accR[i][j][r] + be * g.x, vi = al * accI[i][j][r] + be * g.y;
+        if (ga != 0.f) {
+          const zf q = p.P[row + (int64_t)col * p.ldp];
+          vr += ga * q.x;
+          vi += ga * q.y;
+        }
+        if (de != 0.f) {
+          const zf q = p.R[row + (int64_t)col * p.ldr];
+          vr += de * q.x;
+          vi += de * q.y;
+        }
+        p.D[row + (int64_t)col * p.ldd] = make_float2(vr, vi);
+      }
+    }
+}
+
+// FP64 complex -> FP32 complex copy of an n x n matrix (column-major)
+__global__ void k_to_c32(int64_t rows, const zd* S, int64_t lds, zf* D, int64_t ldd) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const zd v = S[i + j * lds];
+    D[i + j * ldd] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// R(:, j) = (W(:, pj) - theta_pj Q(:, pj)) * sc,  G1(:, j) = rho0_j * R(:, j),
+// G0(:, j) = 0, with pj = perm[j] (degree-sorted order), sc = 1/e
+__global__ void k_resid_start32(int64_t rows, const zd* W, const zd* Q, int64_t ld,
+                                const double* theta, const int* perm, const double* rho0,
+                                double sc, zf* R, zf* G1, zf* G0, int64_t ldl) {
+  const int64_t j = blockIdx.y;
+  const int pj = perm[j];
+  const double th = theta[pj], r0 = rho0[j];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const zd w = W[i + (int64_t)pj * ld], q = Q[i + (int64_t)pj * ld];
+    const double rx = (w.x - th * q.x) * sc, ry = (w.y - th * q.y) * sc;
+    R[i + j * ldl] = make_float2((float)rx, (float)ry);
+    G1[i + j * ldl] = make_float2((float)(r0 * rx), (float)(r0 * ry));
+    G0[i + j * ldl] = make_float2(0.f, 0.f);
+  }
+}
+
+// Y(:, j) = Q(:, perm[j]) + G(:, j)  (FP64 result)
+__global__ void k_add_correction32(int64_t rows, const zd* Q, int64_t ldq, const int* perm,
+                                   const zf* G, int64_t ldg, zd* Y, int64_t ldy) {
+  const int64_t j = blockIdx.y;
+  const int pj = perm[j];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const zd q = Q[i + (int64_t)pj * ldq];
+    const zf g = G[i + j * ldg];
+    Y[i + j * ldy] = make_double2(q.x + (double)g.x, q.y + (double)g.y);
+  }
+}
+
+inline unsigned gx(int64_t rows) {
+  int64_t b = (rows + 255) / 256;
+  return (unsigned)(b < 64 ? (b < 1 ? 1 : b) : 64);
+}
+}  // namespace
+
+gevp_status launch_cgemm32_filter(gevp_ctx* c, int64_t m, int64_t n, int64_t k, const void* A,
+                                  int64_t lda, const void* G, int64_t ldg, const void* P,
+                                  int64_t ldp, const void* R, int64_t ldr, void* D, int64_t ldd,
+                                  const double* al, const double* be, const double* ga,
+                                  const double* de) {
+  if (m <= 0 || n <= 0) return GEVP_OK;
+  CgemmParams p;
+  p.M = (int)m;
+  p.N = (int)n;
+  p.K = (int)k;
+  p.A = (const zf*)A;
+  p.lda = lda;
+  p.B = (const zf*)G;
+  p.ldb = ldg;
+  p.P = (const zf*)P;
+  p.ldp = ldp;
+  p.R = (const zf*)R;
+  p.ldr = ldr;
+  p.D = (zf*)D;
+  p.ldd = ldd;
+  p.alpha = al;
+  p.beta = be;
+  p.gamma = ga;
+  p.delta = de;
+  p.tiles_n = (int)((n + BN - 1) / BN);
+  const int64_t total = ((m + BM - 1) / BM) * p.tiles_n;
+  p.total = (int)total;
+  p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
+  hipLaunchKernelGGL(k_cgemm32_filter, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_to_c32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                          void* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_to_c32, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows, S, lds,
+                     (zf*)D, ldd);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_resid_start32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* W,
+                                 const zd* Q, int64_t ld, const double* theta, const int* perm,
+                                 const double* rho0, double sc, void* R, void* G1, void* G0,
+                                 int64_t ldl) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_resid_start32, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream, rows,
+                     W, Q, ld, theta, perm, rho0, sc, (zf*)R, (zf*)G1, (zf*)G0, ldl);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_add_correction32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* Q,
+                                    int64_t ldq, const int* perm, const void* G, int64_t ldg,
+                                    zd* Y, int64_t ldy) {
+  if (rows <= 0 || cols <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_add_correction32, dim3(gx(rows), (unsigned)cols), dim3(256), 0, c->stream,
+                     rows, Q, ldq, perm, (const zf*)G, ldg, Y, ldy);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}

@@ -14,14 +14,67 @@
 namespace {
 constexpr int NB = 64;
 
+// Inverse of the lower-triangular n x n (n <= 64) factor held in S[col][row]
+// (strict upper part free), by column-parallel forward substitution: a group
+// of four lanes owns column c of X = inv(L) and walks rows i = c..n-1,
+// x_i = -(sum_{c<=k<i} L(i,k) x_k) / L(i,i); lane q sums the k with
+// (k - c) % 4 == q and keeps exactly those x_k (strict part stored
+// transposed in S's upper triangle, S[i][c] = X(i,c); diagonal in dg), so
+// no lane reads another lane's LDS writes.  Result written to Dinv.
+__device__ void lds_inverse_to(zd (*S)[NB], zd* dg, int n, zd* Dinv, int64_t ldi) {
+  const int tid = threadIdx.x;
+  const int c = tid >> 2, q = tid & 3;
+  if (c < n) {
+    for (int i = c; i < n; ++i) {
+      zd xi;
+      if (i == c) {
+        const zd d = S[c][c];
+        const double dd = d.x * d.x + d.y * d.y;
+        xi = make_double2(d.x / dd, -d.y / dd);
+      } else {
+        double sr = 0.0, si = 0.0;
+        for (int k = c + q; k < i; k += 4) {
+          const zd l = S[k][i];
+          const zd x = (k == c) ? dg[c] : S[k][c];
+          sr += l.x * x.x - l.y * x.y;
+          si += l.x * x.y + l.y * x.x;
+        }
+        sr += __shfl_xor(sr, 1, 64);
+        si += __shfl_xor(si, 1, 64);
+        sr += __shfl_xor(sr, 2, 64);
+        si += __shfl_xor(si, 2, 64);
+        const zd d = S[i][i];
+        const double dd = d.x * d.x + d.y * d.y;
+        // xi = -(s) / d
+        xi = make_double2(-(sr * d.x + si * d.y) / dd, -(si * d.x - sr * d.y) / dd);
+      }
+      if (((i - c) & 3) == q) {
+        if (i == c) dg[c] = xi; else S[i][c] = xi;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e % n, j = e / n;
+    zd v = make_double2(0.0, 0.0);
+    if (i == j) v = dg[i];
+    else if (i > j) v = S[i][j];
+    Dinv[i + (int64_t)j * ldi] = v;
+  }
+}
+
 // Factor the n x n (n <= 64) diagonal block at M (lower triangle read) and
 // write L (upper part of the block zeroed) back, then write inv(L) to Dinv.
-// A non-positive or non-finite pivot is recorded in *info (atomic min of the
-// 1-based global index) and replaced by 1 so the kernel always finishes.
+// Right-looking, one barrier per column: the update of step j reads the
+// unscaled column j (scaling by 1/l_jj is folded into the update and applied
+// to the stored column at the end).  A non-positive or non-finite pivot is
+// recorded in *info (atomic min of the 1-based global index) and replaced by
+// 1 so the kernel always finishes.
 __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, zd* Dinv,
                                                      int64_t ldi, int* info, int goff) {
   __shared__ zd S[NB][NB];  // S[col][row]
-  __shared__ zd tmp[NB];
+  __shared__ zd dg[NB];
+  __shared__ double piv[NB];
   const int tid = threadIdx.x;
   for (int e = tid; e < NB * NB; e += 256) {
     const int i = e & (NB - 1), j = e >> 6;
@@ -30,74 +83,50 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
     S[j][i] = v;
   }
   __syncthreads();
+  const int i = tid & 63, kq = tid >> 6;
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double dv = S[j][j].x;
-      if (!(dv > 0.0) || !isfinite(dv)) {
-        atomicMin(info, goff + j + 1);
-        dv = 1.0;
-      }
-      S[j][j] = make_double2(sqrt(dv), 0.0);
-    }
-    __syncthreads();
-    const double piv = S[j][j].x;
-    for (int i = j + 1 + tid; i < n; i += 256) {
-      zd v = S[j][i];
-      S[j][i] = make_double2(v.x / piv, v.y / piv);
-    }
-    __syncthreads();
-    const int r = n - j - 1;
-    for (int e = tid; e < r * r; e += 256) {
-      const int i = j + 1 + e % r, k = j + 1 + e / r;
-      if (i >= k) {
-        const zd a = S[j][i], b = S[j][k];  // S[k][i] -= a conj(b)
-        zd s = S[k][i];
-        s.x -= a.x * b.x + a.y * b.y;
-        s.y -= a.y * b.x - a.x * b.y;
+    double d = S[j][j].x;
+    const bool badp = !(d > 0.0) || !isfinite(d);
+    if (badp) d = 1.0;
+    if (badp && tid == 0) atomicMin(info, goff + j + 1);
+    const double id = 1.0 / d;  // 1 / l_jj^2
+    if (tid == 0) piv[j] = d;
+    if (i > j && i < n) {
+      const zd ci = S[j][i];
+      for (int k = j + 1 + kq; k <= i; k += 4) {
+        const zd ck = S[j][k];
+        zd s = S[k][i];  // s -= ci conj(ck) / l_jj^2
+        s.x -= (ci.x * ck.x + ci.y * ck.y) * id;
+        s.y -= (ci.y * ck.x - ci.x * ck.y) * id;
         S[k][i] = s;
       }
     }
     __syncthreads();
   }
-  // write L (zeros above the diagonal inside the block)
-  for (int e = tid; e < n * n; e += 256) {
-    const int i = e % n, j = e / n;
-    M[i + (int64_t)j * ldm] = (i >= j) ? S[j][i] : make_double2(0.0, 0.0);
+  // scale the columns: l_jj = sqrt(d_j), l_ij = s_ij / l_jj
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & (NB - 1), j = e >> 6;
+    if (j < n && r >= j && r < n) {
+      const double lj = sqrt(piv[j]);
+      if (r == j) S[j][j] = make_double2(lj, 0.0);
+      else S[j][r] = make_double2(S[j][r].x / lj, S[j][r].y / lj);
+    }
   }
   __syncthreads();
-  // in-place inverse, columns from last to first:
-  // inv(L)(j+1:, j) = -inv(L)(j+1:, j+1:) L(j+1:, j) / L(j, j)
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid == 0) S[j][j] = make_double2(1.0 / S[j][j].x, 0.0);
-    for (int i = j + 1 + tid; i < n; i += 256) tmp[i] = S[j][i];
-    __syncthreads();
-    zd acc = make_double2(0.0, 0.0);
-    const int i = j + 1 + tid;
-    if (i < n) {
-      for (int k = j + 1; k <= i; ++k) {
-        const zd a = S[k][i], b = tmp[k];
-        acc.x += a.x * b.x - a.y * b.y;
-        acc.y += a.x * b.y + a.y * b.x;
-      }
-    }
-    __syncthreads();
-    if (i < n) {
-      const double dj = S[j][j].x;
-      S[j][i] = make_double2(-dj * acc.x, -dj * acc.y);
-    }
-    __syncthreads();
-  }
   for (int e = tid; e < n * n; e += 256) {
-    const int i = e % n, j = e / n;
-    Dinv[i + (int64_t)j * ldi] = (i >= j) ? S[j][i] : make_double2(0.0, 0.0);
+    const int r = e % n, j = e / n;
+    M[r + (int64_t)j * ldm] = (r >= j) ? S[j][r] : make_double2(0.0, 0.0);
   }
+  // the strict upper triangle of S is zero; it now receives inv(L)
+  __syncthreads();
+  lds_inverse_to(S, dg, n, Dinv, ldi);
 }
 
 // inverse of the n x n (n <= 64) lower-triangular block at L into Dinv
 __global__ __launch_bounds__(256) void k_trtri_block(const zd* L, int64_t ldl, int64_t ntot, zd* Dinv,
                                                      int64_t ldi) {
   __shared__ zd S[NB][NB];
-  __shared__ zd tmp[NB];
+  __shared__ zd dg[NB];
   const int tid = threadIdx.x;
   const int64_t off = (int64_t)blockIdx.x * NB;
   const int n = (int)((ntot - off) < NB ? (ntot - off) : NB);
@@ -107,35 +136,7 @@ __global__ __launch_bounds__(256) void k_trtri_block(const zd* L, int64_t ldl, i
     S[j][i] = (i < n && j < n && i >= j) ? Lb[i + (int64_t)j * ldl] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    if (tid == 0) {
-      const zd d = S[j][j];
-      const double dd = d.x * d.x + d.y * d.y;
-      S[j][j] = make_double2(d.x / dd, -d.y / dd);
-    }
-    for (int i = j + 1 + tid; i < n; i += 256) tmp[i] = S[j][i];
-    __syncthreads();
-    zd acc = make_double2(0.0, 0.0);
-    const int i = j + 1 + tid;
-    if (i < n) {
-      for (int k = j + 1; k <= i; ++k) {
-        const zd a = S[k][i], b = tmp[k];
-        acc.x += a.x * b.x - a.y * b.y;
-        acc.y += a.x * b.y + a.y * b.x;
-      }
-    }
-    __syncthreads();
-    if (i < n) {
-      const zd dj = S[j][j];  // -acc * inv(L_jj)
-      S[j][i] = make_double2(-(acc.x * dj.x - acc.y * dj.y), -(acc.x * dj.y + acc.y * dj.x));
-    }
-    __syncthreads();
-  }
-  zd* Db = Dinv + off;
-  for (int e = tid; e < n * n; e += 256) {
-    const int i = e % n, j = e / n;
-    Db[i + (int64_t)j * ldi] = (i >= j) ? S[j][i] : make_double2(0.0, 0.0);
-  }
+  lds_inverse_to(S, dg, n, Dinv + off, ldi);
 }
 
 __global__ void k_zero_upper(zd* M, int64_t ldm, int64_t n) {

@@ -38,9 +38,10 @@ struct gevp_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_used = 0;
-  // pinned host mirror of small device status blocks
-  void* host_pinned = nullptr;
-  size_t host_pinned_bytes = 0;
+  // event pairs around filter GEMM launches (profiling bit 1)
+  hipEvent_t* fev = nullptr;
+  int fev_cap = 0;
+  int fev_used = 0;
 };
 
 // Workspace carving.  reserve() (re)allocates when `bytes` exceeds the current
@@ -75,7 +76,7 @@ gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, i
 gevp_status diag_block_inverses(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl, zd* Dinv,
                                 int64_t ldi);
 
-// Small Hermitian eigensolver (n <= 4096): H (full storage, overwritten),
+// Small Hermitian eigensolver (n <= 2048): H (full storage, overwritten),
 // theta ascending, Z (n x n) unitary.  work >= heev_work_bytes(n).
 size_t heev_work_bytes(int64_t n);
 gevp_status heev_small(gevp_ctx* c, int64_t n, zd* H, int64_t ldh, double* theta, zd* Z,
@@ -117,10 +118,27 @@ size_t lanczos_work_bytes(int64_t n, int steps);
 // interval, per-column degrees, the degree-sorted column permutation and the
 // filter coefficients.  See solver.hip for the status layout.
 struct CtlParams {
-  int nb, nev, deg_max, deg_init, mode;  // mode 0: from Ritz data, 1: cold start
-  double tol_abs;                        // absolute C-space residual tolerance (device if <0)
+  int nb, nev, deg_max, deg_init;
+  int mode;         // 0: from Ritz data, 1: cold start, 2: Ritz data, residual-correction filter
+  double u_target;  // mode 2: smallest per-sweep residual reduction worth aiming for
 };
 gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
                            const double* resid, const double* bounds, const double* norms,
                            double tol_rel, int* status_i, double* status_d, int* perm,
-                           double* coefs);
+                           double* coefs, double* rho0 = nullptr, double* coef2 = nullptr);
+
+// mixed-precision filter pieces (cgemm32.hip)
+gevp_status launch_cgemm32_filter(gevp_ctx* c, int64_t m, int64_t n, int64_t k, const void* A,
+                                  int64_t lda, const void* G, int64_t ldg, const void* P,
+                                  int64_t ldp, const void* R, int64_t ldr, void* D, int64_t ldd,
+                                  const double* al, const double* be, const double* ga,
+                                  const double* de);
+gevp_status launch_to_c32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
+                          void* D, int64_t ldd);
+gevp_status launch_resid_start32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* W,
+                                 const zd* Q, int64_t ld, const double* theta, const int* perm,
+                                 const double* rho0, double sc, void* R, void* G1, void* G0,
+                                 int64_t ldl);
+gevp_status launch_add_correction32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* Q,
+                                    int64_t ldq, const int* perm, const void* G, int64_t ldg,
+                                    zd* Y, int64_t ldy);

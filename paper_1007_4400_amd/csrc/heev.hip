@@ -195,12 +195,15 @@ __device__ int sturm(const double* d, const double* e2, int n, double x, double 
   return cnt;
 }
 
+// One wave per eigenvalue k: every round the 64 lanes evaluate Sturm counts
+// at 64 interior points of [lo, hi] and the bracket shrinks to the
+// sub-interval where the count passes k (65x per round).
 __global__ __launch_bounds__(HT) void k_tri_bisect(const double* d, const double* e, int n,
                                                    double* theta) {
   extern __shared__ double sm[];
   double* sd = sm;
   double* se2 = sm + n;
-  __shared__ double red[2];
+  __shared__ double red[3];
   for (int i = threadIdx.x; i < n; i += HT) {
     sd[i] = d[i];
     se2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
@@ -215,26 +218,34 @@ __global__ __launch_bounds__(HT) void k_tri_bisect(const double* d, const double
       if (i < n - 1) emax = fmax(emax, se2[i]);
     }
     const double tnorm = fmax(fabs(gl), fabs(gu));
-    gl -= 2.0 * DBL_EPSILON * tnorm * n + 1e-300;
-    gu += 2.0 * DBL_EPSILON * tnorm * n + 1e-300;
-    red[0] = gl;
-    red[1] = gu;
-    (void)emax;
+    red[0] = gl - 2.0 * DBL_EPSILON * tnorm * n - 1e-300;
+    red[1] = gu + 2.0 * DBL_EPSILON * tnorm * n + 1e-300;
+    red[2] = DBL_MIN * fmax(1.0, emax);
   }
   __syncthreads();
-  const int k = blockIdx.x * HT + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (HT / 64) + (threadIdx.x >> 6);
   if (k >= n) return;
   double lo = red[0], hi = red[1];
-  double emax = 0.0;
-  for (int i = 0; i < n - 1; ++i) emax = fmax(emax, se2[i]);
-  const double pivmin = DBL_MIN * fmax(1.0, emax);
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
+  const double pivmin = red[2];
+  for (int round = 0; round < 40; ++round) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-    if (mid <= lo || mid >= hi) break;
-    if (sturm(sd, se2, n, mid, pivmin) <= k) lo = mid; else hi = mid;
+    const double w = (hi - lo) / 65.0;
+    const double x = lo + w * (lane + 1);
+    const int cnt = sturm(sd, se2, n, x, pivmin);
+    const unsigned long long m = __ballot(cnt > k);
+    const double xs = x;
+    if (m == 0ull) {
+      lo = __shfl(xs, 63, 64);
+    } else {
+      const int q = __ffsll((long long)m) - 1;
+      const double nh = __shfl(xs, q, 64);
+      const double nl = (q > 0) ? __shfl(xs, q - 1 < 0 ? 0 : q - 1, 64) : lo;
+      hi = nh;
+      lo = nl;
+    }
   }
-  theta[k] = 0.5 * (lo + hi);
+  if (lane == 0) theta[k] = 0.5 * (lo + hi);
 }
 
 __device__ __forceinline__ uint64_t hmix(uint64_t z) {
@@ -248,11 +259,19 @@ __device__ __forceinline__ uint64_t hmix(uint64_t z) {
 // [i * n + j] so that a wave's accesses are contiguous.  Output Zt[i*n + j].
 // LU of T - lam I with partial pivoting: row k of U holds (U, Vv, Ww) on
 // columns (k, k+1, k+2); Lm the multiplier and Sw the row swap of step k.
-__global__ __launch_bounds__(HT) void k_tri_invit(const double* d, const double* e, int n,
+__global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double* eg, int n,
                                                   const double* theta, double* U, double* Vv,
                                                   double* Ww, double* Lm, double* Sw, double* Zt,
                                                   double tnorm) {
-  const int j = blockIdx.x * HT + threadIdx.x;
+  extern __shared__ double sm[];
+  double* d = sm;
+  double* e = sm + n;
+  for (int i = threadIdx.x; i < n; i += 64) {
+    d[i] = dg[i];
+    e[i] = (i < n - 1) ? eg[i] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * 64 + threadIdx.x;
   if (j >= n) return;
   const double lam = theta[j];
   const double tiny = DBL_EPSILON * fmax(tnorm, DBL_MIN);
@@ -289,7 +308,7 @@ __global__ __launch_bounds__(HT) void k_tri_invit(const double* d, const double*
     at(Zt, i) = ((double)(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
   }
   double nrm = 0.0;
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < 2; ++it) {
     for (int k = 0; k < n - 1; ++k) {
       const double l = at(Lm, k);
       const double yk = at(Zt, k), yk1 = at(Zt, k + 1);
@@ -371,23 +390,30 @@ __global__ __launch_bounds__(256) void k_zt_to_complex(const double* Zt, int n, 
   }
 }
 
-// Z <- G_0 G_1 ... G_{n-2} Z, reflectors applied last to first; each
-// work-group owns 16 columns (4 per wave) and stages v_s through LDS.
-__global__ __launch_bounds__(256) void k_apply_reflectors(int n, zd* Z, int64_t ldz, const zd* V,
-                                                          int64_t ldv, const zd* tau) {
-  extern __shared__ zd sv[];
+// Z <- G_0 G_1 ... G_{n-2} Z, reflectors applied last to first.  Each
+// work-group owns `cols` columns of Z (one per wave) held in LDS for the whole
+// sweep and stages each reflector through LDS, so Z never leaves the CU.
+__global__ __launch_bounds__(256) void k_apply_reflectors(int n, int cols, zd* Z, int64_t ldz,
+                                                          const zd* V, int64_t ldv, const zd* tau) {
+  extern __shared__ zd sm2[];
+  zd* sv = sm2;          // n
+  zd* sz = sm2 + n;      // cols x n
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = blockIdx.x * 16 + wave * 4;
+  const int c0 = blockIdx.x * cols;
+  for (int q = 0; q < cols; ++q) {
+    const int col = c0 + q;
+    for (int i = tid; i < n; i += 256)
+      sz[q * n + i] = (col < n) ? Z[i + (int64_t)col * ldz] : make_double2(0.0, 0.0);
+  }
+  const bool active = wave < cols && (c0 + wave) < n;
+  zd* z = sz + wave * n;
   for (int s = n - 2; s >= 0; --s) {
     const zd t = tau[s];
     if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
     __syncthreads();
     for (int i = s + 1 + tid; i < n; i += 256) sv[i] = V[i + (int64_t)s * ldv];
     __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      const int col = c0 + q;
-      if (col >= n) break;
-      zd* z = Z + (int64_t)col * ldz;
+    if (active) {
       double sr = 0.0, si = 0.0;
       for (int i = s + 1 + lane; i < n; i += 64) {
         const zd v = sv[i], x = z[i];  // conj(v) x
@@ -398,11 +424,17 @@ __global__ __launch_bounds__(256) void k_apply_reflectors(int n, zd* Z, int64_t 
       si = wsum(si);
       const zd f = cmul(t, make_double2(sr, si));
       for (int i = s + 1 + lane; i < n; i += 64) {
-        const zd v = sv[i], fv = cmul(f, v);
+        const zd fv = cmul(f, sv[i]);
         z[i].x -= fv.x;
         z[i].y -= fv.y;
       }
     }
+  }
+  __syncthreads();
+  for (int q = 0; q < cols; ++q) {
+    const int col = c0 + q;
+    if (col >= n) break;
+    for (int i = tid; i < n; i += 256) Z[i + (int64_t)col * ldz] = sz[q * n + i];
   }
 }
 
@@ -431,7 +463,7 @@ size_t heev_work_bytes(int64_t n) {
 gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* theta, zd* Z,
                        int64_t ldz, void* work) {
   if (n64 <= 0) return GEVP_OK;
-  if (n64 > 4000) return GEVP_ERR_INVALID;  // v_s must fit 64 KB of LDS
+  if (n64 > 2048) return GEVP_ERR_INVALID;  // v_s and one column of Z must fit 64 KB of LDS
   const int n = (int)n64;
   const int G = n < 128 ? (n > 1 ? n - 1 : 1) : 128;
   char* w = (char*)work;
@@ -474,16 +506,16 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   }
   hipLaunchKernelGGL(k_tri_norm, dim3(1), dim3(64), 0, c->stream, a.d, a.e, n, tn);
   GEVP_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_tri_bisect, dim3((n + HT - 1) / HT), dim3(HT), sizeof(double) * 2 * n,
-                     c->stream, a.d, a.e, n, theta);
+  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 3) / 4), dim3(HT), sizeof(double) * 2 * n, c->stream,
+                     a.d, a.e, n, theta);
   GEVP_HIP_TRY(hipGetLastError());
   // ||T|| is needed on the host only as a scale for the zero-pivot guard and
   // the cluster tolerance; read it back (one small synchronous copy).
   double tnorm = 0.0;
   GEVP_HIP_TRY(hipMemcpyAsync(&tnorm, tn, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
-  hipLaunchKernelGGL(k_tri_invit, dim3((n + HT - 1) / HT), dim3(HT), 0, c->stream, a.d, a.e, n,
-                     theta, U, Vv, Ww, Lm, Sw, Zt, tnorm);
+  hipLaunchKernelGGL(k_tri_invit, dim3((n + 63) / 64), dim3(64), sizeof(double) * 2 * n, c->stream,
+                     a.d, a.e, n, theta, U, Vv, Ww, Lm, Sw, Zt, tnorm);
   GEVP_HIP_TRY(hipGetLastError());
   const double ctol = 1e3 * DBL_EPSILON * fmax(tnorm, 1e-300);
   hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, ctol);
@@ -492,8 +524,12 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
   GEVP_HIP_TRY(hipGetLastError());
   if (n > 1) {
-    hipLaunchKernelGGL(k_apply_reflectors, dim3((n + 15) / 16), dim3(256), shv, c->stream, n, Z,
-                       ldz, a.V, a.ldv, a.tau);
+    // columns per work-group so that v_s plus the columns fit 64 KB of LDS
+    int cols = (int)((65536 - (int64_t)shv) / (int64_t)shv);
+    if (cols > 4) cols = 4;
+    if (cols < 1) return GEVP_ERR_INVALID;  // n > 2048 is not supported here
+    hipLaunchKernelGGL(k_apply_reflectors, dim3((n + cols - 1) / cols), dim3(256),
+                       shv * (1 + cols), c->stream, n, cols, Z, ldz, a.V, a.ldv, a.tau);
     GEVP_HIP_TRY(hipGetLastError());
   }
   return GEVP_OK;

@@ -169,7 +169,8 @@ __global__ void k_lanczos_finish(const double* alpha, const double* beta, int k,
 __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* theta,
                                                  const double* resid, const double* bounds,
                                                  const double* norms, double tol_rel, int* si,
-                                                 double* sd, int* perm, double* coefs) {
+                                                 double* sd, int* perm, double* coefs,
+                                                 double* rho0, double* coef2) {
   extern __shared__ int deg[];  // nb
   __shared__ int cnt[256];
   __shared__ int sh_nconv, sh_maxdeg;
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
   if (p.mode == 1) {
     a = bounds[4];
     mu = bounds[0];
-  } else {
+  } else {  // modes 0 and 2: from the Ritz values
     a = theta[nb - 1];
     mu = fmin(theta[0], bounds[0]);
   }
@@ -190,12 +191,12 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
   const double e = 0.5 * (b - a), c = 0.5 * (b + a);
   if (tid == 0) {
     int nc = 0;
-    if (p.mode == 0)
+    if (p.mode != 1)
       while (nc < nev && resid[nc] <= tol_abs) ++nc;
     sh_nconv = nc;
   }
   __syncthreads();
-  const bool done = (p.mode == 0) && sh_nconv >= nev;
+  const bool done = (p.mode != 1) && sh_nconv >= nev;
   // per-column degrees
   for (int i = tid; i < nb; i += 256) {
     int m;
@@ -210,7 +211,11 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
           m = p.deg_max;
         } else {
           const double rho = fabs(t) + sqrt(t * t - 1.0);
-          const double need = log(resid[i] / tol_abs) / log(rho);
+          // reduction wanted this sweep; a low-precision filter (mode 2) cannot
+          // beat its rounding floor, so it aims no further than u_target
+          double red = resid[i] / tol_abs;
+          if (p.mode == 2 && red * p.u_target > 1.0) red = 1.0 / p.u_target;
+          const double need = log(red) / log(rho);
           m = (int)ceil(need) + 1;
           if (m < 2) m = 2;
           if (m > p.deg_max) m = p.deg_max;
@@ -285,6 +290,32 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
       coefs[3 * (j - 1) + 2] = ga;
     }
   }
+  if (p.mode != 2) return;
+  __syncthreads();
+  // Residual-correction filter, per column in degree-sorted order: with
+  // theta' = (theta - c)/e and T_j the Chebyshev polynomials,
+  // g_{j+1} = a_j (C' g_j + r') - b_j g_{j-1},  a_j = 2 T_j/T_{j+1},
+  // b_j = T_{j-1}/T_{j+1}, g_1 = r'/theta'; with rho_j = T_j/T_{j+1}:
+  // rho_0 = 1/theta', rho_j = 1/(2 theta' - rho_{j-1}).  Step s (computing
+  // g_{s+1}) stores alpha = a_s/e, beta = -a_s c/e, gamma = -b_s, delta = a_s.
+  const int md = sh_maxdeg;
+  for (int j = tid; j < nb; j += 256) {
+    const int col = perm[j];
+    double tp = (theta[col] - c) / e;
+    if (tp > -1.0) tp = -1.0;
+    double rprev = 1.0 / tp;
+    rho0[j] = rprev;
+    for (int st = 1; st < md; ++st) {
+      const double r = 1.0 / (2.0 * tp - rprev);
+      const double a = 2.0 * r, bb = rprev * r;
+      double* row = coef2 + (size_t)(st - 1) * 4 * nb;
+      row[j] = a / e;
+      row[nb + j] = -a * c / e;
+      row[2 * nb + j] = -bb;
+      row[3 * nb + j] = a;
+      rprev = r;
+    }
+  }
 }
 }  // namespace
 
@@ -326,9 +357,10 @@ gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int
 gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
                            const double* resid, const double* bounds, const double* norms,
                            double tol_rel, int* status_i, double* status_d, int* perm,
-                           double* coefs) {
+                           double* coefs, double* rho0, double* coef2) {
+  if (p.mode == 2 && (!rho0 || !coef2)) return GEVP_ERR_INVALID;
   hipLaunchKernelGGL(k_control, dim3(1), dim3(256), sizeof(int) * p.nb, c->stream, p, theta, resid,
-                     bounds, norms, tol_rel, status_i, status_d, perm, coefs);
+                     bounds, norms, tol_rel, status_i, status_d, perm, coefs, rho0, coef2);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

@@ -90,7 +90,7 @@ struct Timer {
   gevp_ctx* c;
   hipEvent_t ev[2];
   bool on;
-  Timer(gevp_ctx* ctx) : c(ctx), on(ctx->profiling != 0) {
+  Timer(gevp_ctx* ctx) : c(ctx), on((ctx->profiling & 1) != 0) {
     if (on) {
       (void)hipEventCreate(&ev[0]);
       (void)hipEventCreate(&ev[1]);
@@ -158,6 +158,37 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
   return GEVP_OK;
 }
 
+// Event pair around one filter launch (profiling bit 1); the pool grows on
+// demand and is summed after the solve's final synchronisation.
+gevp_status fev_mark(gevp_ctx* c) {
+  if (!(c->profiling & 2)) return GEVP_OK;
+  if (c->fev_used == c->fev_cap) {
+    const int cap = c->fev_cap ? 2 * c->fev_cap : 512;
+    hipEvent_t* nv = new hipEvent_t[cap];
+    for (int i = 0; i < c->fev_cap; ++i) nv[i] = c->fev[i];
+    for (int i = c->fev_cap; i < cap; ++i) GEVP_HIP_TRY(hipEventCreate(&nv[i]));
+    delete[] c->fev;
+    c->fev = nv;
+    c->fev_cap = cap;
+  }
+  GEVP_HIP_TRY(hipEventRecord(c->fev[c->fev_used++], c->stream));
+  return GEVP_OK;
+}
+
+gevp_status fev_collect(gevp_ctx* c, gevp_info* info) {
+  if (!(c->profiling & 2)) return GEVP_OK;
+  double tot = 0.0;
+  for (int i = 0; i + 1 < c->fev_used; i += 2) {
+    float ms = 0.f;
+    GEVP_HIP_TRY(hipEventElapsedTime(&ms, c->fev[i], c->fev[i + 1]));
+    tot += ms;
+  }
+  info->filter_kernel_ms += tot;
+  info->filter_launches += c->fev_used / 2;
+  c->fev_used = 0;
+  return GEVP_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -205,11 +236,11 @@ gevp_status gevp_set_profiling(gevp_handle h, int on) {
 
 void gevp_destroy(gevp_handle h) {
   if (!h) return;
-  if (h->ws) {
-    (void)hipSetDevice(h->device);
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->ws);
-  }
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  for (int i = 0; i < h->fev_cap; ++i) (void)hipEventDestroy(h->fev[i]);
+  delete[] h->fev;
   delete h;
 }
 
@@ -236,17 +267,19 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (nev < 1 || nev > n) return bad(11);
   if (!(tol > 0.0)) return bad(12);
   const Opts o = resolve(opts, nev);
-  if (o.precision != GEVP_FP64) return bad(2);  // other forms: see gevp_solve_mixed
+  if (o.precision != GEVP_FP64 && o.precision != GEVP_FP32) return bad(2);
+  const bool mixed = (o.precision != GEVP_FP64);
   const int64_t nb = block_of(o, n, nev);
   if (kx < nev || kx > nb) return bad(13);
   if (X0_ && k0 > 0 && (ldx0 < n || k0 > nb)) return bad(10);
   if (k0 < 0) return bad(10);
   if (!lambda) return bad(14);
   if (!X_ || ldx < n) return bad(16);
-  if (nb > 4000) return bad(11);  // Rayleigh-Ritz eigensolver limit
+  if (nb > 2048) return bad(11);  // Rayleigh-Ritz eigensolver limit
   const bool seeded = (X0_ != nullptr && k0 > 0);
   GEVP_HIP_TRY(hipSetDevice(h->device));
   gevp_ctx* c = h;
+  c->fev_used = 0;
   info->block = (int)nb;
 
   const zd* A = (const zd*)A_;
@@ -272,6 +305,13 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
   need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
   need += ws_round(sizeof(double) * 4);                  // norms
+  const size_t lp_elem = 8;                              // complex64
+  if (mixed) {
+    need += ws_round(lp_elem * nn);                      // low-precision copy of C
+    need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
+    need += ws_round(sizeof(double) * nb);               // rho0
+    need += ws_round(sizeof(double) * 4 * nb * (o.deg_max + 2));  // per-column coefficients
+  }
   GEVP_TRY(ws_reserve(c, need));
   zd* Af = (zd*)ws_take(c, sizeof(zd) * nn);
   zd* Bf = (zd*)ws_take(c, sizeof(zd) * nn);
@@ -302,6 +342,20 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   int* flags = (int*)ws_take(c, sizeof(int) * 8);
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
+  void* Clp = nullptr;
+  void* G0 = nullptr;
+  void* G1 = nullptr;
+  void* Rlp = nullptr;
+  double* rho0 = nullptr;
+  double* coef2 = nullptr;
+  if (mixed) {
+    Clp = ws_take(c, lp_elem * nn);
+    G0 = ws_take(c, lp_elem * n * nb);
+    G1 = ws_take(c, lp_elem * n * nb);
+    Rlp = ws_take(c, lp_elem * n * nb);
+    rho0 = (double*)ws_take(c, sizeof(double) * nb);
+    coef2 = (double*)ws_take(c, sizeof(double) * 4 * nb * (o.deg_max + 2));
+  }
 
   Timer tm(c);
   // flags[0]: nonfinite input, flags[1]: Cholesky pivot of B, flags[2]: QR flag
@@ -335,6 +389,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
   GEVP_TRY(trsm_right_lower_c(c, n, n, L, n, Dinv, n, C, n));
   GEVP_TRY(launch_symmetrize(c, n, C, n));
+  if (mixed) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
   tm.stop(info, GEVP_STAGE_REDUCE);
 
   // ---------------- bounds
@@ -358,7 +413,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   QrWork qw{Gs, DinvG, flags + 2, shift};
   int fallbacks = 0;
-  CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, 0.0};
+  // rounding floor of the FP32 filter products (K = n terms, FP32 accumulation)
+  const double u_target = 1e-6;
+  CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, u_target};
   std::vector<int> hst(4 + 260);
   std::vector<double> hsd(16);
   int it = 0;
@@ -374,16 +431,48 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       const int64_t s0 = sj[j - 1];
       const int64_t cols = nb - s0;
       if (cols <= 0) break;
+      info->col_degrees += cols;
       const double* cf = coefs + 3 * (j - 1);
       zd* src = F[(j - 1) & 1];
       zd* dst = F[j & 1];
+      GEVP_TRY(fev_mark(c));
       if (j == 1)
         GEVP_TRY(launch_zgemm(c, 0, 0, n, cols, n, 0.0, C, n, src + s0 * n, n, 0.0, src + s0 * n, n,
                               0.0, nullptr, 0, nullptr, dst + s0 * n, n, cf));
       else
         GEVP_TRY(launch_zgemm(c, 0, 0, n, cols, n, 0.0, C, n, src + s0 * n, n, 0.0, src + s0 * n, n,
                               0.0, dst + s0 * n, n, nullptr, dst + s0 * n, n, cf));
+      GEVP_TRY(fev_mark(c));
     }
+    std::swap(P0, P1);
+    return GEVP_OK;
+  };
+
+  // Residual-correction filter in low precision (see lanczos_ctl.hip): from
+  // the FP64 Ritz pairs (Q = P0, W = C Q, theta) build r' = (W - Q theta)/e and
+  // g_1 = r'/theta', run g_{s+1} = a_s (C' g_s + r') - b_s g_{s-1} on the low-
+  // precision copy of C, and return Y = Q + g_m in FP64.  Rounding errors are
+  // relative to |g|, which shrinks with the residual, so the sweep can reach
+  // FP64-level residuals while every filter product is low precision.
+  auto run_filter_r2 = [&](int maxdeg, const int* sj, double e_half) -> gevp_status {
+    void* F[2] = {G0, G1};
+    GEVP_TRY(launch_resid_start32(c, n, nb, W, P0, n, theta, perm, rho0, 1.0 / e_half, Rlp, G1, G0,
+                                  n));
+    for (int st = 1; st < maxdeg; ++st) {
+      const int64_t s0 = sj[st];  // columns with degree >= st + 1
+      const int64_t cols = nb - s0;
+      if (cols <= 0) break;
+      info->col_degrees += cols;
+      const double* row = coef2 + (size_t)(st - 1) * 4 * nb;
+      char* src = (char*)F[st & 1] + lp_elem * s0 * n;
+      char* dst = (char*)F[(st + 1) & 1] + lp_elem * s0 * n;
+      char* rr = (char*)Rlp + lp_elem * s0 * n;
+      GEVP_TRY(fev_mark(c));
+      GEVP_TRY(launch_cgemm32_filter(c, n, cols, n, Clp, n, src, n, dst, n, rr, n, dst, n, row + s0,
+                                     row + nb + s0, row + 2 * nb + s0, row + 3 * nb + s0));
+      GEVP_TRY(fev_mark(c));
+    }
+    GEVP_TRY(launch_add_correction32(c, n, nb, P0, n, perm, G0, n, P1, n));
     std::swap(P0, P1);
     return GEVP_OK;
   };
@@ -397,9 +486,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     tm.start();
     GEVP_TRY(run_filter(hst[1], hst.data() + 4));
     tm.stop(info, GEVP_STAGE_FILTER);
-    info->col_degrees += (int64_t)hsd[5];
   }
-  cp.mode = 0;
+  cp.mode = mixed ? 2 : 0;
   for (it = 0; it < o.maxit; ++it) {
     tm.start();
     GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks));
@@ -420,7 +508,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_TRY(launch_resid_cols(c, n, nb, W, n, P0, n, theta, rres));
     tm.stop(info, GEVP_STAGE_RR);
     info->outer_iters = it + 1;
-    GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs));
+    GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs, rho0,
+                            coef2));
     GEVP_HIP_TRY(hipMemcpyAsync(hst.data(), st_i, sizeof(int) * hst.size(), hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipMemcpyAsync(hsd.data(), st_d, sizeof(double) * hsd.size(), hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
@@ -434,9 +523,11 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     }
     if (it + 1 == o.maxit) break;
     tm.start();
-    GEVP_TRY(run_filter(hst[1], hst.data() + 4));
+    if (mixed)
+      GEVP_TRY(run_filter_r2(hst[1], hst.data() + 4, hsd[3]));
+    else
+      GEVP_TRY(run_filter(hst[1], hst.data() + 4));
     tm.stop(info, GEVP_STAGE_FILTER);
-    info->col_degrees += (int64_t)hsd[5];
   }
   info->qr_fallbacks = fallbacks;
   info->filter_flops = 8.0 * (double)n * (double)n * (double)info->col_degrees;
@@ -468,6 +559,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
   }
   tm.stop(info, GEVP_STAGE_FINAL);
+  GEVP_TRY(fev_collect(c, info));
   info->normA = hn[0];
   info->normB = hn[1];
   if (!converged) st = GEVP_ERR_NOCONV;
@@ -583,7 +675,7 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
 
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh, double* theta, void* Z,
                         int64_t ldz) {
-  if (!h || n < 1 || n > 4000 || !H || ldh < n || !theta || !Z || ldz < n) return GEVP_ERR_INVALID;
+  if (!h || n < 1 || n > 2048 || !H || ldh < n || !theta || !Z || ldz < n) return GEVP_ERR_INVALID;
   GEVP_HIP_TRY(hipSetDevice(h->device));
   GEVP_TRY(ws_reserve(h, heev_work_bytes(n) + ws_round(sizeof(zd) * n * n) + 256));
   void* w = ws_take(h, heev_work_bytes(n));

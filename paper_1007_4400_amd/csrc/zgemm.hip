@@ -55,6 +55,9 @@ struct ZgemmParams {
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
 
+// FILTER only names the kernel differently for the Chebyshev filter launches
+// (coefficients from device memory), so profiles separate them.
+template <int FILTER>
 __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
   __shared__ zd As[2][KT][PADA];
   __shared__ zd Bs[2][KT][PADB];
@@ -251,7 +254,10 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   if (total > INT32_MAX) return GEVP_ERR_INVALID;
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
-  hipLaunchKernelGGL(k_zgemm, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
+  if (coef)
+    hipLaunchKernelGGL(k_zgemm<1>, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
+  else
+    hipLaunchKernelGGL(k_zgemm<0>, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

@@ -40,6 +40,7 @@ class Info(ctypes.Structure):
         ("block", ctypes.c_int), ("qr_fallbacks", ctypes.c_int), ("col_degrees", ctypes.c_int64),
         ("max_resid", ctypes.c_double), ("normA", ctypes.c_double), ("normB", ctypes.c_double),
         ("filter_flops", ctypes.c_double), ("ms", ctypes.c_double * 8),
+        ("filter_kernel_ms", ctypes.c_double), ("filter_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -140,7 +141,7 @@ def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_s
 class Handle:
     """One library handle (workspace owner) on a CUDA/HIP device."""
 
-    def __init__(self, device: int = 0, profiling: bool = False):
+    def __init__(self, device: int = 0, profiling: int = 0):
         lib = load()
         self.lib = lib
         self.device = device
@@ -150,7 +151,10 @@ class Handle:
             raise GevpError(s, "gevp_create")
         self.h = h
         if profiling:
-            lib.gevp_set_profiling(h, 1)
+            lib.gevp_set_profiling(h, int(profiling))
+
+    def set_profiling(self, flags: int):
+        self.lib.gevp_set_profiling(self.h, int(flags))
 
     def close(self):
         if getattr(self, "h", None):
