@@ -78,39 +78,66 @@ def _mark_pop():
         pass
 
 
-def rocprof_summary(db_path, kernel_substr="k_zgemm<1>", region="timed"):
-    """Text summary of a rocprofv3 --kernel-trace [--marker-trace] database:
-    per-kernel totals, and the filter kernel's launches inside the marked
-    timed region (the same launches bench.py times with HIP events)."""
+FILTER_KERNELS = {"fp64": "k_zgemm<1>", "fp32": "k_cgemm32_filter", "bf16x3": "k_cgemm_bf16x3_filter"}
+
+
+def _regions(cur):
+    """{message: (start, end)} of the roctx ranges in a rocprofv3 database."""
+    out = {}
+    try:
+        for extdata, st, en in cur.execute("select extdata, start, end from regions"):
+            try:
+                msg = json.loads(extdata or "{}").get("message")
+            except ValueError:
+                msg = None
+            if msg:
+                out[msg] = (st, en)
+    except Exception:
+        pass
+    return out
+
+
+def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="timed"):
+    """Text summary of a rocprofv3 database: per-kernel totals from a
+    --kernel-trace run, the filter kernel's launches inside the roctx range
+    'timed' (the launches bench.py times with HIP events), and, for a --pmc
+    run, the per-dispatch FETCH_SIZE / WRITE_SIZE of that kernel next to the
+    calibration copy's (1 GiB read + 1 GiB written)."""
     import sqlite3
 
     con = sqlite3.connect(db_path)
     cur = con.cursor()
+    lines = []
     rows = cur.execute("select name, count(*), sum(end-start), avg(end-start) from kernels "
                        "group by name order by sum(end-start) desc").fetchall()
-    total = sum(r[2] for r in rows)
-    lines = [f"kernels: {sum(r[1] for r in rows)} dispatches, {total / 1e6:.1f} ms total", "",
-             f"{'total ms':>10} {'calls':>7} {'avg ms':>9}  kernel"]
-    for name, cnt, tot, avg in rows[:30]:
-        lines.append(f"{tot / 1e6:10.2f} {cnt:7d} {avg / 1e6:9.4f}  {name[:110]}")
-    win = None
-    try:
-        reg = cur.execute("select start, end from regions where name = ?", (region,)).fetchall()
-        if reg:
-            win = (min(r[0] for r in reg), max(r[1] for r in reg))
-    except Exception:
-        win = None
+    if rows:
+        total = sum(r[2] for r in rows)
+        lines += [f"kernels: {sum(r[1] for r in rows)} dispatches, {total / 1e6:.1f} ms total", "",
+                  f"{'total ms':>10} {'calls':>7} {'avg ms':>9}  kernel"]
+        for name, cnt, tot, avg in rows[:30]:
+            lines.append(f"{tot / 1e6:10.2f} {cnt:7d} {avg / 1e6:9.4f}  {name[:110]}")
+    reg = _regions(cur)
     sel = cur.execute("select start, end from kernels where name like ?",
                       ("%" + kernel_substr + "%",)).fetchall()
     lines.append("")
     if sel:
         d = [e - s for s, e in sel]
         lines.append(f"{kernel_substr}: all launches {len(d)}, avg {sum(d) / len(d) / 1e6:.4f} ms")
-        if win:
-            dw = [e - s for s, e in sel if s >= win[0] and e <= win[1]]
+        if region in reg:
+            w0, w1 = reg[region]
+            dw = [e - s for s, e in sel if s >= w0 and e <= w1]
             if dw:
-                lines.append(f"{kernel_substr}: launches inside region '{region}' {len(dw)}, "
+                lines.append(f"{kernel_substr}: launches inside roctx range '{region}' {len(dw)}, "
                              f"avg {sum(dw) / len(dw) / 1e6:.4f} ms, total {sum(dw) / 1e6:.1f} ms")
+    # counters (pmc runs)
+    try:
+        pmc = cur.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                          "group by kernel_name, counter_name").fetchall()
+    except Exception:
+        pmc = []
+    for kname, cname, val, cnt in pmc:
+        if kernel_substr in kname or "copyBuffer" in kname:
+            lines.append(f"pmc {cname} avg per dispatch {val:.1f} (x{cnt})  {kname[:80]}")
     return "\n".join(lines)
 
 
@@ -121,15 +148,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--nev", type=int, default=820)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--cold-steps", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rocprof-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
+    ap.add_argument("--summary-kernel", default=None, help="kernel name for --rocprof-summary")
+    ap.add_argument("--host-qr", action="store_true",
+                    help="factor the generator's Gaussian matrix on the host (for counter runs)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.rocprof_summary:
-        print(rocprof_summary(args.rocprof_summary))
+        print(rocprof_summary(args.rocprof_summary, args.summary_kernel or FILTER_KERNELS[args.precision]))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus above 1 is not supported "
@@ -145,7 +177,7 @@ def main():
     h = gevp.Handle(0)
     dev = "cuda"
     t0 = time.perf_counter()
-    A0, B, lam0, L, g = synth.make_pencil_torch(wl, args.seed, device=dev)
+    A0, B, lam0, L, g = synth.make_pencil_torch(wl, args.seed, device=dev, qr_on_host=args.host_qr)
     del L
     B = gevp.colmajor(B.contiguous())
     As = [gevp.colmajor(A0)]
@@ -156,6 +188,17 @@ def main():
     exact0 = torch.sort(lam0).values[: wl.nev]
     torch.cuda.synchronize()
     log(f"generated {nsteps} steps n={wl.n} in {time.perf_counter() - t0:.1f}s")
+
+    if args.calibration_copy:
+        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        _mark_push("calibration_copy_1GiB")
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _mark_pop()
+        del src, dst
 
     opts = gevp.make_opts(precision=args.precision)
     opts64 = gevp.make_opts(precision="fp64")
@@ -228,6 +271,7 @@ def main():
     filt_flops = sum(i["filter_flops"] for i in infos)
     filt_launches = sum(i["filter_launches"] for i in infos)
     dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}[args.precision]
+    kname = FILTER_KERNELS[args.precision]
     achieved = filt_flops / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
     peak = PEAK_TFLOPS[dtype]
     value = t_total / args.steps
@@ -242,14 +286,14 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype if dtype == "f64" else f"{dtype}+f64",
+        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16": "bf16x3+f64"}[dtype],
         "data": "synthetic",
         "config": {"workload": f"scf_sequence_n{wl.n}_nev{wl.nev}_steps{nsteps}_seeded_{args.precision}",
                    "n": wl.n, "nev": wl.nev, "block": kx, "tol": args.tol,
                    "precision": args.precision},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_zgemm (Chebyshev filter launches)",
+            "kernel": kname,
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
@@ -258,6 +302,10 @@ def main():
             "launches": filt_launches,
             "avg_launch_ms": filt_ms / max(filt_launches, 1),
             "flops_per_launch": filt_flops / max(filt_launches, 1),
+            "algorithmic_flops_per_unit": "8 n^2 per filtered column-step (complex multiply-add = 8 flops)",
+            # a split-BF16 product executes 3 BF16 MFMA products per real product
+            "executed_per_algorithmic": 3.0 if dtype == "bf16" else 1.0,
+            "executed_frac": (achieved * (3.0 if dtype == "bf16" else 1.0)) / peak if peak else None,
         },
         "cold_fp64_s_per_step": cold_mean,
         "speedup_vs_cold_fp64": cold_mean / value if value > 0 else None,

@@ -188,6 +188,21 @@ gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n
                          double gamma, const void* E, int64_t lde, const double* gcol,
                          void* D, int64_t ldd);
 
+/*
+ * One step of the low-precision residual-correction filter (the Chebyshev
+ * recurrence of the mixed-precision forms), per column j < m:
+ *   D(:, j) = alpha_j C G(:, j) + beta_j G(:, j) + gamma_j P(:, j) + delta_j R(:, j)
+ * C: device complex128 n x n Hermitian (full storage), converted internally to
+ * the precision's format (GEVP_FP32: complex64; GEVP_BF16X3: split-BF16 row
+ * planes).  G, P, R, D: device complex64 n x m; D may alias P.
+ * alpha..delta: device float64[m].  Asynchronous.
+ */
+gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t m,
+                               const void* C, int64_t ldc, const void* G, int64_t ldg,
+                               const void* P, int64_t ldp, const void* R, int64_t ldr, void* D,
+                               int64_t ldd, const double* alpha, const double* beta,
+                               const double* gamma, const double* delta);
+
 /* In-place Cholesky of the lower triangle of the n x n Hermitian M (upper
  * triangle zeroed).  Synchronous; returns GEVP_ERR_NOT_HPD with *pivot
  * (1-based) on failure. */

@@ -60,19 +60,18 @@ __global__ __launch_bounds__(NTHR, 2) void k_cgemm32_filter(CgemmParams p) {
       accI[i][j] = f4{0, 0, 0, 0};
     }
   zf ra[4], rb[4];
-  const zf zero = make_float2(0.f, 0.f);
   auto load = [&](int k0) {
     const int m = tid & 63, gm = row0 + m;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int gk = k0 + (tid >> 6) + 4 * i;
-      ra[i] = (gm < p.M && gk < p.K) ? p.A[gm + (int64_t)gk * p.lda] : zero;
+      ra[i] = (gm < p.M && gk < p.K) ? p.A[gm + (int64_t)gk * p.lda] : make_float2(0.f, 0.f);
     }
     const int k = tid & 15, gk = k0 + k;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int gn = col0 + (tid >> 4) + 16 * i;
-      rb[i] = (gn < p.N && gk < p.K) ? p.B[gk + (int64_t)gn * p.ldb] : zero;
+      rb[i] = (gn < p.N && gk < p.K) ? p.B[gk + (int64_t)gn * p.ldb] : make_float2(0.f, 0.f);
     }
   };
   auto store = [&](int buf) {

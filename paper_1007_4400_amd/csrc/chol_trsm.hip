@@ -14,119 +14,124 @@
 namespace {
 constexpr int NB = 64;
 
-// Inverse of the lower-triangular n x n (n <= 64) factor held in S[col][row]
-// (strict upper part free), by column-parallel forward substitution: a group
-// of four lanes owns column c of X = inv(L) and walks rows i = c..n-1,
-// x_i = -(sum_{c<=k<i} L(i,k) x_k) / L(i,i); lane q sums the k with
-// (k - c) % 4 == q and keeps exactly those x_k (strict part stored
-// transposed in S's upper triangle, S[i][c] = X(i,c); diagonal in dg), so
-// no lane reads another lane's LDS writes.  Result written to Dinv.
-__device__ void lds_inverse_to(zd (*S)[NB], zd* dg, int n, zd* Dinv, int64_t ldi) {
-  const int tid = threadIdx.x;
-  const int c = tid >> 2, q = tid & 3;
-  if (c < n) {
-    for (int i = c; i < n; ++i) {
-      zd xi;
-      if (i == c) {
-        const zd d = S[c][c];
-        const double dd = d.x * d.x + d.y * d.y;
-        xi = make_double2(d.x / dd, -d.y / dd);
-      } else {
-        double sr = 0.0, si = 0.0;
-        for (int k = c + q; k < i; k += 4) {
-          const zd l = S[k][i];
-          const zd x = (k == c) ? dg[c] : S[k][c];
-          sr += l.x * x.x - l.y * x.y;
-          si += l.x * x.y + l.y * x.x;
-        }
-        sr += __shfl_xor(sr, 1, 64);
-        si += __shfl_xor(si, 1, 64);
-        sr += __shfl_xor(sr, 2, 64);
-        si += __shfl_xor(si, 2, 64);
-        const zd d = S[i][i];
-        const double dd = d.x * d.x + d.y * d.y;
-        // xi = -(s) / d
-        xi = make_double2(-(sr * d.x + si * d.y) / dd, -(si * d.x - sr * d.y) / dd);
-      }
-      if (((i - c) & 3) == q) {
-        if (i == c) dg[c] = xi; else S[i][c] = xi;
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += 256) {
-    const int i = e % n, j = e / n;
-    zd v = make_double2(0.0, 0.0);
-    if (i == j) v = dg[i];
-    else if (i > j) v = S[i][j];
-    Dinv[i + (int64_t)j * ldi] = v;
-  }
+// Register-resident 64 x 64 block algorithms.  Thread t owns row i = t % 64
+// and the 16 columns c = kq + 4m (kq = t / 64, m = 0..15), so the four waves
+// split the columns and a wave reads a broadcast buffer at a uniform index.
+
+__device__ __forceinline__ zd zmul(zd a, zd b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Factor the n x n (n <= 64) diagonal block at M (lower triangle read) and
-// write L (upper part of the block zeroed) back, then write inv(L) to Dinv.
-// Right-looking, one barrier per column: the update of step j reads the
-// unscaled column j (scaling by 1/l_jj is folded into the update and applied
-// to the stored column at the end).  A non-positive or non-finite pivot is
-// recorded in *info (atomic min of the 1-based global index) and replaced by
-// 1 so the kernel always finishes.
-__global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, zd* Dinv,
-                                                     int64_t ldi, int* info, int goff) {
-  __shared__ zd S[NB][NB];  // S[col][row]
-  __shared__ zd dg[NB];
-  __shared__ double piv[NB];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e & (NB - 1), j = e >> 6;
-    zd v = make_double2(0.0, 0.0);
-    if (i < n && j < n && i >= j) v = M[i + (int64_t)j * ldm];
-    S[j][i] = v;
-  }
-  __syncthreads();
-  const int i = tid & 63, kq = tid >> 6;
-  for (int j = 0; j < n; ++j) {
-    double d = S[j][j].x;
-    const bool badp = !(d > 0.0) || !isfinite(d);
-    if (badp) d = 1.0;
-    if (badp && tid == 0) atomicMin(info, goff + j + 1);
-    const double id = 1.0 / d;  // 1 / l_jj^2
-    if (tid == 0) piv[j] = d;
-    if (i > j && i < n) {
-      const zd ci = S[j][i];
-      for (int k = j + 1 + kq; k <= i; k += 4) {
-        const zd ck = S[j][k];
-        zd s = S[k][i];  // s -= ci conj(ck) / l_jj^2
-        s.x -= (ci.x * ck.x + ci.y * ck.y) * id;
-        s.y -= (ci.y * ck.x - ci.x * ck.y) * id;
-        S[k][i] = s;
+// X = inv(L) for the lower-triangular n x n L held in S[col][row], by
+// right-looking forward substitution on L X = I: row k of X is finished at
+// step k and broadcast through a double-buffered row buffer (one barrier per
+// step).  X is written to Dinv (zeros above the diagonal).
+__device__ void reg_inverse_to(zd (*S)[NB], zd (*xrow)[NB], int n, zd* Dinv, int64_t ldi) {
+  const int tid = threadIdx.x, i = tid & 63, kq = tid >> 6;
+  zd b[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) b[m] = make_double2((kq + 4 * m == i) ? 1.0 : 0.0, 0.0);
+  for (int k = 0; k < n; ++k) {
+    zd* xr = xrow[k & 1];
+    if (i == k) {
+      const zd lkk = S[k][k];
+      const double dd = lkk.x * lkk.x + lkk.y * lkk.y;
+      const zd r = make_double2(lkk.x / dd, -lkk.y / dd);  // 1 / l_kk
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        b[m] = zmul(b[m], r);
+        xr[kq + 4 * m] = b[m];
       }
     }
     __syncthreads();
+    // rows i > k subtract l_ik * x_k (a zero multiplier elsewhere, no branch)
+    const zd lik = (i > k && i < n) ? S[k][i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const zd t = zmul(lik, xr[kq + 4 * m]);
+      b[m].x -= t.x;
+      b[m].y -= t.y;
+    }
   }
-  // scale the columns: l_jj = sqrt(d_j), l_ij = s_ij / l_jj
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & (NB - 1), j = e >> 6;
-    if (j < n && r >= j && r < n) {
-      const double lj = sqrt(piv[j]);
-      if (r == j) S[j][j] = make_double2(lj, 0.0);
-      else S[j][r] = make_double2(S[j][r].x / lj, S[j][r].y / lj);
+  if (i < n) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int c = kq + 4 * m;
+      if (c < n) Dinv[i + (int64_t)c * ldi] = (c <= i) ? b[m] : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Factor the n x n (n <= 64) diagonal block at M (lower triangle read), write
+// L back (upper part of the block zeroed) and inv(L) to Dinv.  Right-looking
+// in registers: column j (current values) is broadcast through a
+// double-buffered column buffer, one barrier per column; the 1/l_jj scaling is
+// folded into the updates and applied at the end.  A non-positive or
+// non-finite pivot is recorded in *info (atomic min of the 1-based global
+// index) and replaced by 1 so the kernel always finishes.
+__global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, zd* Dinv,
+                                                     int64_t ldi, int* info, int goff) {
+  __shared__ zd S[NB][NB];  // S[col][row]: the factor, for the inverse
+  __shared__ zd cb[2][NB];
+  __shared__ double piv[NB];
+  const int tid = threadIdx.x, i = tid & 63, kq = tid >> 6;
+  zd a[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int c = kq + 4 * m;
+    a[m] = (i < n && c < n && i >= c) ? M[i + (int64_t)c * ldm] : make_double2(0.0, 0.0);
+  }
+  for (int j = 0; j < n; ++j) {
+    if (kq == (j & 3)) {
+      // a[j / 4] without a dynamic register index (keeps a[] out of scratch)
+      zd v = a[0];
+#pragma unroll
+      for (int m = 1; m < 16; ++m)
+        if (m == (j >> 2)) v = a[m];
+      cb[j & 1][i] = v;
+    }
+    __syncthreads();
+    double d = cb[j & 1][j].x;
+    const bool badp = !(d > 0.0) || !isfinite(d);
+    if (badp) d = 1.0;
+    if (tid == 0) {
+      piv[j] = d;
+      if (badp) atomicMin(info, goff + j + 1);
+    }
+    const double id = 1.0 / d;  // 1 / l_jj^2
+    // a_ic -= a_ij conj(a_cj) / l_jj^2 for j < c <= i (a zero factor elsewhere)
+    const zd ci = (i > j && i < n) ? cb[j & 1][i] : make_double2(0.0, 0.0);
+    const zd cs = make_double2(ci.x * id, ci.y * id);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int c = kq + 4 * m;
+      const zd ck = (c > j && c <= i) ? cb[j & 1][c] : make_double2(0.0, 0.0);
+      a[m].x -= cs.x * ck.x + cs.y * ck.y;
+      a[m].y -= cs.y * ck.x - cs.x * ck.y;
     }
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += 256) {
-    const int r = e % n, j = e / n;
-    M[r + (int64_t)j * ldm] = (r >= j) ? S[j][r] : make_double2(0.0, 0.0);
+  // scale and write L; keep it in S for the inverse
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int c = kq + 4 * m;
+    zd v = make_double2(0.0, 0.0);
+    if (i < n && c < n && i >= c) {
+      const double lc = sqrt(piv[c]);
+      v = (i == c) ? make_double2(lc, 0.0) : make_double2(a[m].x / lc, a[m].y / lc);
+    }
+    S[c][i] = v;
+    if (i < n && c < n) M[i + (int64_t)c * ldm] = v;
   }
-  // the strict upper triangle of S is zero; it now receives inv(L)
   __syncthreads();
-  lds_inverse_to(S, dg, n, Dinv, ldi);
+  reg_inverse_to(S, cb, n, Dinv, ldi);
 }
 
 // inverse of the n x n (n <= 64) lower-triangular block at L into Dinv
 __global__ __launch_bounds__(256) void k_trtri_block(const zd* L, int64_t ldl, int64_t ntot, zd* Dinv,
                                                      int64_t ldi) {
   __shared__ zd S[NB][NB];
-  __shared__ zd dg[NB];
+  __shared__ zd xr[2][NB];
   const int tid = threadIdx.x;
   const int64_t off = (int64_t)blockIdx.x * NB;
   const int n = (int)((ntot - off) < NB ? (ntot - off) : NB);
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void k_trtri_block(const zd* L, int64_t ldl, i
     S[j][i] = (i < n && j < n && i >= j) ? Lb[i + (int64_t)j * ldl] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  lds_inverse_to(S, dg, n, Dinv + off, ldi);
+  reg_inverse_to(S, xr, n, Dinv + off, ldi);
 }
 
 __global__ void k_zero_upper(zd* M, int64_t ldm, int64_t n) {
@@ -162,7 +167,7 @@ gevp_status chol_rec(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64
   GEVP_TRY(trsm_right_lower_c(c, h, n - h, M, ldm, Dinv, ldi, M21, ldm));
   zd* M22 = M + h + h * ldm;
   GEVP_TRY(launch_zgemm(c, 0, 1, n - h, n - h, h, -1.0, M21, ldm, M21, ldm, 1.0, M22, ldm, 0.0,
-                        nullptr, 0, nullptr, M22, ldm));
+                        nullptr, 0, nullptr, M22, ldm, nullptr, 1));
   return chol_rec(c, n - h, M22, ldm, Dinv + h, ldi, info, goff + h);
 }
 }  // namespace
@@ -229,4 +234,29 @@ gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, i
   GEVP_TRY(launch_zgemm(c, 0, 1, m, n - h, h, -1.0, R, ldr, L + h, ldl, 1.0, R + h * ldr, ldr,
                         0.0, nullptr, 0, nullptr, R + h * ldr, ldr));
   return trsm_right_lower_c(c, n - h, m, L + h + h * ldl, ldl, Dinv + h, ldi, R + h * ldr, ldr);
+}
+
+namespace {
+// rows [c0, n) of columns [c0, c0 + nn) of R <- R L^{-H}
+gevp_status trsm_rlc_lower_rec(gevp_ctx* c, int64_t n, int64_t c0, int64_t nn, const zd* L,
+                               int64_t ldl, const zd* Dinv, int64_t ldi, zd* R, int64_t ldr) {
+  const zd* Lb = L + c0 + c0 * ldl;
+  zd* Rb = R + c0 + c0 * ldr;
+  const int64_t rows = n - c0;
+  if (nn <= NB)
+    return launch_zgemm(c, 0, 1, rows, nn, nn, 1.0, Rb, ldr, Dinv + c0, ldi, 0.0, nullptr, 0, 0.0,
+                        nullptr, 0, nullptr, Rb, ldr);
+  const int64_t h = split64(nn);
+  GEVP_TRY(trsm_rlc_lower_rec(c, n, c0, h, L, ldl, Dinv, ldi, R, ldr));
+  // R[c0+h:, c0+h : c0+nn] -= R[c0+h:, c0 : c0+h] L21^H,  L21 = L[c0+h : c0+nn, c0 : c0+h]
+  GEVP_TRY(launch_zgemm(c, 0, 1, n - c0 - h, nn - h, h, -1.0, Rb + h, ldr, Lb + h, ldl, 1.0,
+                        Rb + h + h * ldr, ldr, 0.0, nullptr, 0, nullptr, Rb + h + h * ldr, ldr));
+  return trsm_rlc_lower_rec(c, n, c0 + h, nn - h, L, ldl, Dinv, ldi, R, ldr);
+}
+}  // namespace
+
+gevp_status trsm_right_lower_c_lowerpart(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl,
+                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr) {
+  if (n <= 0) return GEVP_OK;
+  return trsm_rlc_lower_rec(c, n, 0, n, L, ldl, Dinv, ldi, R, ldr);
 }

@@ -54,11 +54,13 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 
 // D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E   (FP64 MFMA, complex128)
 // When `coef` (device double[3]) is non-null it supplies alpha, beta, gamma.
+// lower = 1 computes only the 64 x 64 tiles that touch the lower triangle
+// (Hermitian updates whose upper triangle is never read).
 gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef = nullptr);
+                         const double* coef = nullptr, int lower = 0);
 
 // Recursive blocked Cholesky of the lower triangle; Dinv (n x 64 column-major,
 // ld = ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev
@@ -72,6 +74,10 @@ gevp_status trsm_left_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, in
                               const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
 gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
                                const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+// Lower triangle only of R <- R L^{-H} for square n x n R: rows below each
+// column block's start are all that is computed (the Hermitian C = W L^{-H}).
+gevp_status trsm_right_lower_c_lowerpart(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl,
+                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
 // Inverses of the 64 x 64 diagonal blocks of an already factored L.
 gevp_status diag_block_inverses(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl, zd* Dinv,
                                 int64_t ldi);
@@ -139,6 +145,13 @@ gevp_status launch_resid_start32(gevp_ctx* c, int64_t rows, int64_t cols, const 
                                  const zd* Q, int64_t ld, const double* theta, const int* perm,
                                  const double* rho0, double sc, void* R, void* G1, void* G0,
                                  int64_t ldl);
+size_t bf16_planes_bytes(int64_t n);
+gevp_status launch_split_rows_bf16(gevp_ctx* c, int64_t n, const zd* C, int64_t ldc, void* planes);
+gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_t k,
+                                       const void* planes, const void* G, int64_t ldg,
+                                       const void* P, int64_t ldp, const void* R, int64_t ldr,
+                                       void* D, int64_t ldd, const double* al, const double* be,
+                                       const double* ga, const double* de);
 gevp_status launch_add_correction32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* Q,
                                     int64_t ldq, const int* perm, const void* G, int64_t ldg,
                                     zd* Y, int64_t ldy);

@@ -267,8 +267,10 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (nev < 1 || nev > n) return bad(11);
   if (!(tol > 0.0)) return bad(12);
   const Opts o = resolve(opts, nev);
-  if (o.precision != GEVP_FP64 && o.precision != GEVP_FP32) return bad(2);
+  if (o.precision != GEVP_FP64 && o.precision != GEVP_FP32 && o.precision != GEVP_BF16X3)
+    return bad(2);
   const bool mixed = (o.precision != GEVP_FP64);
+  const bool bf16 = (o.precision == GEVP_BF16X3);
   const int64_t nb = block_of(o, n, nev);
   if (kx < nev || kx > nb) return bad(13);
   if (X0_ && k0 > 0 && (ldx0 < n || k0 > nb)) return bad(10);
@@ -307,7 +309,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(double) * 4);                  // norms
   const size_t lp_elem = 8;                              // complex64
   if (mixed) {
-    need += ws_round(lp_elem * nn);                      // low-precision copy of C
+    need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
     need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
     need += ws_round(sizeof(double) * nb);               // rho0
     need += ws_round(sizeof(double) * 4 * nb * (o.deg_max + 2));  // per-column coefficients
@@ -349,7 +351,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* rho0 = nullptr;
   double* coef2 = nullptr;
   if (mixed) {
-    Clp = ws_take(c, lp_elem * nn);
+    Clp = ws_take(c, bf16 ? bf16_planes_bytes(n) : lp_elem * nn);
     G0 = ws_take(c, lp_elem * n * nb);
     G1 = ws_take(c, lp_elem * n * nb);
     Rlp = ws_take(c, lp_elem * n * nb);
@@ -387,17 +389,21 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   tm.start();
   GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
   GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
-  GEVP_TRY(trsm_right_lower_c(c, n, n, L, n, Dinv, n, C, n));
-  GEVP_TRY(launch_symmetrize(c, n, C, n));
-  if (mixed) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
+  // C = W L^{-H} is Hermitian: only its lower triangle is formed, then mirrored
+  GEVP_TRY(trsm_right_lower_c_lowerpart(c, n, L, n, Dinv, n, C, n));
+  GEVP_TRY(launch_mirror_lower(c, n, C, n, C, n, flags + 3));
+  if (mixed && bf16) GEVP_TRY(launch_split_rows_bf16(c, n, C, n, Clp));
+  if (mixed && !bf16) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
   tm.stop(info, GEVP_STAGE_REDUCE);
 
   // ---------------- bounds
   tm.start();
   const double frac = std::min(1.0, (double)nb / (double)n);
   GEVP_TRY(lanczos_bounds(c, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw));
-  GEVP_TRY(lanczos_bounds(c, n, Af, n, lz, o.seed ^ 0xA11CEull, frac, bA, lanw));
-  GEVP_TRY(lanczos_bounds(c, n, Bf, n, lz, o.seed ^ 0xB0Bull, frac, bB, lanw));
+  // norm estimates need fewer steps than the filter's upper bound
+  const int lzn = lz > 12 ? 12 : lz;
+  GEVP_TRY(lanczos_bounds(c, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw));
+  GEVP_TRY(lanczos_bounds(c, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw));
   GEVP_TRY(launch_copy_real(c, 1, bA + 5, norms));
   GEVP_TRY(launch_copy_real(c, 1, bB + 5, norms + 1));
   tm.stop(info, GEVP_STAGE_BOUNDS);
@@ -413,8 +419,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   QrWork qw{Gs, DinvG, flags + 2, shift};
   int fallbacks = 0;
-  // rounding floor of the FP32 filter products (K = n terms, FP32 accumulation)
-  const double u_target = 1e-6;
+  // rounding floor of the filter products: FP32 products with FP32
+  // accumulation over n terms, or split-BF16 products (about 2^-16 each)
+  const double u_target = bf16 ? 1e-4 : 1e-6;
   CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, u_target};
   std::vector<int> hst(4 + 260);
   std::vector<double> hsd(16);
@@ -468,8 +475,14 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       char* dst = (char*)F[(st + 1) & 1] + lp_elem * s0 * n;
       char* rr = (char*)Rlp + lp_elem * s0 * n;
       GEVP_TRY(fev_mark(c));
-      GEVP_TRY(launch_cgemm32_filter(c, n, cols, n, Clp, n, src, n, dst, n, rr, n, dst, n, row + s0,
-                                     row + nb + s0, row + 2 * nb + s0, row + 3 * nb + s0));
+      if (bf16)
+        GEVP_TRY(launch_cgemm_bf16x3_filter(c, n, cols, n, Clp, src, n, dst, n, rr, n, dst, n,
+                                            row + s0, row + nb + s0, row + 2 * nb + s0,
+                                            row + 3 * nb + s0));
+      else
+        GEVP_TRY(launch_cgemm32_filter(c, n, cols, n, Clp, n, src, n, dst, n, rr, n, dst, n,
+                                       row + s0, row + nb + s0, row + 2 * nb + s0,
+                                       row + 3 * nb + s0));
       GEVP_TRY(fev_mark(c));
     }
     GEVP_TRY(launch_add_correction32(c, n, nb, P0, n, perm, G0, n, P1, n));
@@ -633,6 +646,30 @@ gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n
   GEVP_HIP_TRY(hipSetDevice(h->device));
   return launch_zgemm(h, oa, ob, m, n, k, alpha, (const zd*)A, lda, (const zd*)B, ldb, beta,
                       (const zd*)Cm, ldc, gamma, (const zd*)E, lde, gcol, (zd*)D, ldd);
+}
+
+gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t m,
+                               const void* C, int64_t ldc, const void* G, int64_t ldg,
+                               const void* P, int64_t ldp, const void* R, int64_t ldr, void* D,
+                               int64_t ldd, const double* alpha, const double* beta,
+                               const double* gamma, const double* delta) {
+  if (!h || n < 1 || m < 0 || !C || ldc < n || !G || ldg < n || !P || ldp < n || !R || ldr < n ||
+      !D || ldd < n || !alpha || !beta || !gamma || !delta)
+    return GEVP_ERR_INVALID;
+  if (precision != GEVP_FP32 && precision != GEVP_BF16X3) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  const bool bf = precision == GEVP_BF16X3;
+  const size_t bytes = bf ? bf16_planes_bytes(n) : (size_t)8 * n * n;
+  GEVP_TRY(ws_reserve(h, ws_round(bytes)));
+  void* planes = ws_take(h, bytes);
+  if (bf) {
+    GEVP_TRY(launch_split_rows_bf16(h, n, (const zd*)C, ldc, planes));
+    return launch_cgemm_bf16x3_filter(h, n, m, n, planes, G, ldg, P, ldp, R, ldr, D, ldd, alpha, beta,
+                                      gamma, delta);
+  }
+  GEVP_TRY(launch_to_c32(h, n, n, (const zd*)C, ldc, planes, n));
+  return launch_cgemm32_filter(h, n, m, n, planes, n, G, ldg, P, ldp, R, ldr, D, ldd, alpha, beta,
+                               gamma, delta);
 }
 
 gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t* pivot) {

@@ -51,6 +51,7 @@ struct ZgemmParams {
   int tiles_n;
   int total;
   int remap;
+  int lower;  // 1: only tiles that touch the lower triangle (row >= col) are computed
 };
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
   }
   const int tm = L / p.tiles_n, tn = L - tm * p.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
+  if (p.lower && col0 > row0 + BM - 1) return;  // tile strictly above the diagonal
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -84,71 +86,76 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
       accI[i][j] = d4{0, 0, 0, 0};
     }
 
-  zd ra[4], rb[4];
-  const zd zero = make_double2(0.0, 0.0);
+  zd ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // next slice, in registers
+  const int opA = p.opA, opB = p.opB;
 
-  auto load = [&](int k0) {
-    if (p.opA == 0) {  // A col-major M x K: thread -> (m = tid%64, k = tid/64 + 4i)
-      const int m = tid & 63, gm = row0 + m;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gk = k0 + (tid >> 6) + 4 * i;
-        ra[i] = (gm < p.M && gk < p.K) ? p.A[gm + (int64_t)gk * p.lda] : zero;
-      }
-    } else {  // A stored K x M: op(A)(m,k) = conj(A[k + m lda]); k fastest
-      const int k = tid & 15, gk = k0 + k;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gm = row0 + (tid >> 4) + 16 * i;
-        ra[i] = (gm < p.M && gk < p.K) ? zconj(p.A[gk + (int64_t)gm * p.lda]) : zero;
-      }
-    }
-    if (p.opB == 0) {  // B col-major K x N: k fastest
-      const int k = tid & 15, gk = k0 + k;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gn = col0 + (tid >> 4) + 16 * i;
-        rb[i] = (gn < p.N && gk < p.K) ? p.B[gk + (int64_t)gn * p.ldb] : zero;
-      }
-    } else {  // B stored N x K: op(B)(k,n) = conj(B[n + k ldb]); n fastest
-      const int n = tid & 63, gn = col0 + n;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gk = k0 + (tid >> 6) + 4 * i;
-        rb[i] = (gn < p.N && gk < p.K) ? zconj(p.B[gn + (int64_t)gk * p.ldb]) : zero;
-      }
-    }
-  };
-  auto store = [&](int buf) {
-    if (p.opA == 0) {
-      const int m = tid & 63;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) As[buf][(tid >> 6) + 4 * i][m] = ra[i];
-    } else {
-      const int k = tid & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) As[buf][k][(tid >> 4) + 16 * i] = ra[i];
-    }
-    if (p.opB == 0) {
-      const int k = tid & 15;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[buf][k][(tid >> 4) + 16 * i] = rb[i];
-    } else {
-      const int n = tid & 63;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[buf][(tid >> 6) + 4 * i][n] = rb[i];
-    }
-  };
+  // A col-major M x K: thread -> (m = tid%64, k = tid/64 + 4i); A stored K x M
+  // ('C'): op(A)(m,k) = conj(A[k + m lda]), k fastest.  B col-major K x N: k
+  // fastest; B stored N x K ('C'): op(B)(k,n) = conj(B[n + k ldb]), n fastest.
+#define LDA_(i, dst)                                                                  \
+  do {                                                                                \
+    if (opA == 0) {                                                                   \
+      const int gm_ = row0 + (tid & 63), gk_ = k0 + (tid >> 6) + 4 * (i);             \
+      dst = (gm_ < p.M && gk_ < p.K) ? p.A[gm_ + (int64_t)gk_ * p.lda]: make_double2(0.0, 0.0);      \
+    } else {                                                                          \
+      const int gk_ = k0 + (tid & 15), gm_ = row0 + (tid >> 4) + 16 * (i);            \
+      dst = (gm_ < p.M && gk_ < p.K) ? zconj(p.A[gk_ + (int64_t)gm_ * p.lda]) : make_double2(0.0, 0.0); \
+    }                                                                                 \
+  } while (0)
+#define LDB_(i, dst)                                                                  \
+  do {                                                                                \
+    if (opB == 0) {                                                                   \
+      const int gk_ = k0 + (tid & 15), gn_ = col0 + (tid >> 4) + 16 * (i);            \
+      dst = (gn_ < p.N && gk_ < p.K) ? p.B[gk_ + (int64_t)gn_ * p.ldb]: make_double2(0.0, 0.0);      \
+    } else {                                                                          \
+      const int gn_ = col0 + (tid & 63), gk_ = k0 + (tid >> 6) + 4 * (i);             \
+      dst = (gn_ < p.N && gk_ < p.K) ? zconj(p.B[gn_ + (int64_t)gk_ * p.ldb]) : make_double2(0.0, 0.0); \
+    }                                                                                 \
+  } while (0)
+#define LOAD_(kk0)          \
+  do {                      \
+    const int k0 = (kk0);   \
+    LDA_(0, ra0);           \
+    LDA_(1, ra1);           \
+    LDA_(2, ra2);           \
+    LDA_(3, ra3);           \
+    LDB_(0, rb0);           \
+    LDB_(1, rb1);           \
+    LDB_(2, rb2);           \
+    LDB_(3, rb3);           \
+  } while (0)
+#define STA_(i, v)                                                   \
+  do {                                                               \
+    if (opA == 0) As[buf_][(tid >> 6) + 4 * (i)][tid & 63] = v;      \
+    else As[buf_][tid & 15][(tid >> 4) + 16 * (i)] = v;              \
+  } while (0)
+#define STB_(i, v)                                                   \
+  do {                                                               \
+    if (opB == 0) Bs[buf_][tid & 15][(tid >> 4) + 16 * (i)] = v;     \
+    else Bs[buf_][(tid >> 6) + 4 * (i)][tid & 63] = v;               \
+  } while (0)
+#define STORE_(b)           \
+  do {                      \
+    const int buf_ = (b);   \
+    STA_(0, ra0);           \
+    STA_(1, ra1);           \
+    STA_(2, ra2);           \
+    STA_(3, ra3);           \
+    STB_(0, rb0);           \
+    STB_(1, rb1);           \
+    STB_(2, rb2);           \
+    STB_(3, rb3);           \
+  } while (0)
 
   const int nk = (p.K + KT - 1) / KT;
   if (nk > 0) {
-    load(0);
-    store(0);
+    LOAD_(0);
+    STORE_(0);
   }
   __syncthreads();
   for (int t = 0; t < nk; ++t) {
     const int cur = t & 1;
-    if (t + 1 < nk) load((t + 1) * KT);
+    if (t + 1 < nk) LOAD_((t + 1) * KT);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kk = ks * 4 + lg;
@@ -179,9 +186,15 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
         for (int j = 0; j < 2; ++j)
           accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
     }
-    if (t + 1 < nk) store(cur ^ 1);
+    if (t + 1 < nk) STORE_(cur ^ 1);
     __syncthreads();
   }
+#undef LDA_
+#undef LDB_
+#undef LOAD_
+#undef STA_
+#undef STB_
+#undef STORE_
 
   double alpha = p.alpha, beta = p.beta, gamma = p.gamma;
   if (p.coef) {
@@ -224,7 +237,7 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef) {
+                         const double* coef, int lower) {
   if (m <= 0 || n <= 0) return GEVP_OK;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return GEVP_ERR_INVALID;
   ZgemmParams p;
@@ -254,6 +267,7 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   if (total > INT32_MAX) return GEVP_ERR_INVALID;
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
+  p.lower = lower;
   if (coef)
     hipLaunchKernelGGL(k_zgemm<1>, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
   else

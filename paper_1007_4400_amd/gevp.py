@@ -91,6 +91,8 @@ def load():
     lib.gevp_backward.restype = I
     lib.gevp_k_zgemm.argtypes = [P, C, C, L, L, L, D, P, L, P, L, D, P, L, D, P, L, P, P, L]
     lib.gevp_k_zgemm.restype = I
+    lib.gevp_k_filter_gemm.argtypes = [P, I, L, L, P, L, P, L, P, L, P, L, P, L, P, P, P, P]
+    lib.gevp_k_filter_gemm.restype = I
     lib.gevp_k_potrf.argtypes = [P, L, P, L, ctypes.POINTER(L)]
     lib.gevp_k_potrf.restype = I
     lib.gevp_k_trsm.argtypes = [P, C, C, L, L, P, L, P, L]
@@ -238,6 +240,22 @@ class Handle:
             raise GevpError(s, "gevp_k_zgemm")
         return out
 
+    def filter_gemm(self, precision, C, G, P, R, alpha, beta, gamma, delta):
+        """One low-precision filter step: D = alpha C G + beta G + gamma P + delta R
+        (per-column coefficients); C complex128, G/P/R complex64."""
+        C = colmajor(C)
+        G, P, R = colmajor(G), colmajor(P), colmajor(R)
+        n, m = G.shape
+        D = empty_colmajor(n, m, dtype=torch.complex64, device=G.device)
+        co = [x.to(torch.float64).contiguous() for x in (alpha, beta, gamma, delta)]
+        self._stream()
+        pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        s = self.lib.gevp_k_filter_gemm(self.h, pr, n, m, _ptr(C), _ld(C), _ptr(G), _ld(G), _ptr(P),
+                                        _ld(P), _ptr(R), _ld(R), _ptr(D), _ld(D), *[_ptr(x) for x in co])
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_filter_gemm")
+        return D
+
     def potrf(self, M):
         """In-place lower Cholesky on a column-major copy; returns (L, pivot)."""
         L = colmajor(M).clone()
@@ -271,3 +289,39 @@ class Handle:
         if s != GEVP_OK:
             raise GevpError(s, "gevp_k_heev")
         return th, Z
+
+
+class GEVPFunction(torch.autograd.Function):
+    """Differentiable lowest-eigenvalue solve: ``lam = GEVPFunction.apply(A, B,
+    nev, X0, tol, opts, handle)``.  Only eigenvalue cotangents are supported
+    (the gradient of a loss built from eigenvalues, e.g. an occupation-weighted
+    eigenvalue sum).  The gradients are those of the Hermitian pencil the
+    lower triangles define, as full Hermitian matrices:
+    dL/dA = X diag(g) X^H, dL/dB = -X diag(g lam) X^H (first-order perturbation
+    of B-orthonormal pairs, computed by gevp_backward on the GPU)."""
+
+    @staticmethod
+    def forward(ctx, A, B, nev, X0=None, tol=1e-10, opts=None, handle=None):
+        h = handle or _default_handle(A.device)
+        lam, X, _, info = h.solve(A.detach(), B.detach(), nev, X0=X0, tol=tol, opts=opts)
+        ctx.save_for_backward(X, lam)
+        ctx.h = h
+        ctx.mark_non_differentiable()
+        return lam
+
+    @staticmethod
+    def backward(ctx, glam):
+        X, lam = ctx.saved_tensors
+        need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dA, dB = ctx.h.backward(X, lam, glam.to(torch.float64), want_dA=need_a, want_dB=need_b)
+        return dA, dB, None, None, None, None, None
+
+
+_handles = {}
+
+
+def _default_handle(device):
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if idx not in _handles:
+        _handles[idx] = Handle(idx)
+    return _handles[idx]

@@ -196,10 +196,12 @@ def batched_workloads(count: int = 32, nmin: int = 1500, nmax: int = 3000, seed:
 # device (torch) construction for the large sizes
 
 
-def make_pencil_torch(wl: Workload, seed: int, device="cuda"):
+def make_pencil_torch(wl: Workload, seed: int, device="cuda", qr_on_host=False):
     """The same construction with a seeded torch generator on ``device``.
-    Returns (A, B, Lambda, gen) as torch tensors (row-major logical matrices,
-    complex128) plus the generator for the perturbations."""
+    Returns (A, B, Lambda, L, gen) as torch tensors (row-major logical
+    matrices, complex128) plus the generator for the perturbations.
+    qr_on_host: factor the Gaussian matrix on the host (same draws, same
+    construction; used where a device QR is unavailable)."""
     import torch
 
     g = torch.Generator(device=device)
@@ -220,7 +222,11 @@ def make_pencil_torch(wl: Workload, seed: int, device="cuda"):
     L = torch.eye(n, device=device, dtype=torch.complex128) + wl.lscale * torch.tril(G, -1)
     del G
     Z = torch.randn(n, n, generator=g, device=device, dtype=torch.complex128)
-    Q, R = torch.linalg.qr(Z)
+    if qr_on_host:
+        Q, R = torch.linalg.qr(Z.cpu())
+        Q, R = Q.to(device), R.to(device)
+    else:
+        Q, R = torch.linalg.qr(Z)
     del Z
     d = torch.diagonal(R)
     Q = Q * (d / d.abs())[None, :]

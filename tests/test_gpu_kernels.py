@@ -131,3 +131,27 @@ def test_heev_degenerate(h, oracle_mod):
     assert np.max(np.abs(th - ev)) <= 1e-12
     assert np.max(np.abs(H @ Z - Z * th[None, :])) <= 1e-11
     assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("n,m", [(64, 16), (200, 70), (333, 129), (520, 260)])
+def test_filter_gemm_low_precision(h, precision, tol, n, m):
+    """One residual-correction filter step in low precision against the
+    complex128 definition; the error bound is relative to the size of the
+    terms (normwise), the rounding scale of each format."""
+    print(f"filter gemm {precision} n={n} m={m}", flush=True)
+    rng = np.random.default_rng(n + m)
+    G0 = _cn(rng, n, n)
+    C = 0.5 * (G0 + G0.conj().T) / np.sqrt(n)
+    Gm = _cn(rng, n, m).astype(np.complex64)
+    P = _cn(rng, n, m).astype(np.complex64)
+    R = _cn(rng, n, m).astype(np.complex64)
+    al, be, ga, de = (rng.standard_normal(m) for _ in range(4))
+    ref = (C @ Gm.astype(complex)) * al + Gm * be + P * ga + R * de
+    d = [torch.from_numpy(x).cuda() for x in (al, be, ga, de)]
+    out = h.filter_gemm(precision, _dev(C), _dev(Gm), _dev(P), _dev(R), *d)
+    torch.cuda.synchronize()
+    out = _np(out)
+    scale = np.abs(C) @ np.abs(Gm) * np.abs(al) + np.abs(Gm * be) + np.abs(P * ga) + np.abs(R * de)
+    err = np.max(np.abs(out - ref) / scale)
+    assert err <= tol, err

@@ -40,7 +40,7 @@ def _check(oracle_mod, A, B, lam, X, nev):
     assert np.max(np.abs(ov - 1.0)) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("wl", [synth.SMALL, synth.scaled(synth.MEDIUM, 448, steps=4)])
 def test_mixed_sequence(h, oracle_mod, precision, wl):
     from paper_1007_4400_amd import gevp
