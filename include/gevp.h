@@ -70,7 +70,8 @@ typedef struct {
   int lanczos_steps;        /* spectral-bound Lanczos steps; 0 = 24 */
   unsigned long long seed;  /* random fill of non-seeded columns */
   int skip_final_residual;  /* 1: skip the original-basis residual check */
-  int reserved[8];
+  int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 4 */
+  int reserved[7];
 } gevp_opts;
 
 /* Diagnostics, filled on return when a non-NULL pointer is passed. */
@@ -154,6 +155,11 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n,
  * section 1: one pencil per Bloch vector k).  Arrays of length count hold
  * per-problem arguments as in gevp_solve (X0[i] may be NULL).  kx[i] = nev[i]
  * when kx is NULL.  infos may be NULL.  Returns the worst status.
+ * The problems run concurrently on opts->batch_streams HIP streams owned by
+ * the handle (one host thread each), largest first; every stream waits for
+ * the work already queued on the handle's stream, and the call returns when
+ * all problems are done.  Each stream keeps a workspace sized for the largest
+ * problem it has solved.
  */
 gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count,
                                const int64_t* n, const void* const* A, const int64_t* lda,

@@ -339,13 +339,14 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
   const size_t shm = (size_t)2 * (BM + BN) * ROWB;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // 136 KB of LDS per work-group (gfx950 has 160 KB per CU)
+  // 136 KB of LDS per work-group (gfx950 has 160 KB per CU); set once,
+  // thread-safely (batched solves launch from several host threads)
+  static const bool attr_set = [&]() {
     (void)hipFuncSetAttribute((const void*)k_cgemm_bf16x3_filter,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(NTHR), shm, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;

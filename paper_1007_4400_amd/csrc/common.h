@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <vector>
 
 #include "../../include/gevp.h"
 
@@ -42,6 +43,9 @@ struct gevp_ctx {
   hipEvent_t* fev = nullptr;
   int fev_cap = 0;
   int fev_used = 0;
+  // per-stream sub-contexts of gevp_solve_batched (own stream and workspace)
+  std::vector<gevp_ctx*> workers;
+  bool owns_stream = false;
 };
 
 // Workspace carving.  reserve() (re)allocates when `bytes` exceeds the current

@@ -13,9 +13,11 @@
 //   final    X = L^{-H} Y(:, 1:kx), original-basis residuals, phase fix
 // The only device-to-host traffic is a few status words per sweep.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -237,7 +239,10 @@ gevp_status gevp_set_profiling(gevp_handle h, int on) {
 void gevp_destroy(gevp_handle h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
+  for (gevp_ctx* w : h->workers) gevp_destroy(w);
+  h->workers.clear();
   (void)hipStreamSynchronize(h->stream);
+  if (h->owns_stream) (void)hipStreamDestroy(h->stream);
   if (h->ws) (void)hipFree(h->ws);
   for (int i = 0; i < h->fev_cap; ++i) (void)hipEventDestroy(h->fev[i]);
   delete[] h->fev;
@@ -617,14 +622,55 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
                                const int64_t* ldx, double* const* resid, gevp_info* infos) {
   if (!h || count < 0 || !n || !A || !lda || !B || !ldb || !nev || !lambda || !X || !ldx)
     return GEVP_ERR_INVALID;
+  if (count == 0) return GEVP_OK;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  int streams = (opts && opts->batch_streams > 0) ? opts->batch_streams : 4;
+  if (streams > 16) streams = 16;
+  if (streams > count) streams = count;
+  while ((int)h->workers.size() < streams) {
+    gevp_ctx* w = new gevp_ctx();
+    w->device = h->device;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return GEVP_ERR_HIP;
+    }
+    w->owns_stream = true;
+    h->workers.push_back(w);
+  }
+  // the worker streams start after the work already queued on the caller's stream
+  hipEvent_t ready;
+  GEVP_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  GEVP_HIP_TRY(hipEventRecord(ready, h->stream));
+  for (int w = 0; w < streams; ++w) GEVP_HIP_TRY(hipStreamWaitEvent(h->workers[w]->stream, ready, 0));
+  // largest problems first (cost ~ n^3)
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+  std::vector<gevp_status> st(count, GEVP_OK);
+  std::atomic<int> next(0);
+  auto work = [&](int w) {
+    gevp_ctx* c = h->workers[w];
+    (void)hipSetDevice(c->device);
+    for (;;) {
+      const int q = next.fetch_add(1);
+      if (q >= count) break;
+      const int i = order[q];
+      const void* x0 = X0 ? X0[i] : nullptr;
+      st[i] = gevp_solve(c, opts, n[i], A[i], lda[i], B[i], ldb[i], x0, ldx0 ? ldx0[i] : n[i],
+                         (k0 && x0) ? k0[i] : 0, nev[i], tol, kx ? kx[i] : nev[i], lambda[i], X[i],
+                         ldx[i], resid ? resid[i] : nullptr, infos ? infos + i : nullptr);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < streams; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto& t : pool) t.join();
+  (void)hipEventDestroy(ready);
   gevp_status worst = GEVP_OK;
   for (int i = 0; i < count; ++i) {
-    const void* x0 = X0 ? X0[i] : nullptr;
-    const gevp_status s = gevp_solve(h, opts, n[i], A[i], lda[i], B[i], ldb[i], x0,
-                                     ldx0 ? ldx0[i] : n[i], (k0 && x0) ? k0[i] : 0, nev[i], tol,
-                                     kx ? kx[i] : nev[i], lambda[i], X[i], ldx[i],
-                                     resid ? resid[i] : nullptr, infos ? infos + i : nullptr);
-    if (s != GEVP_OK && (worst == GEVP_OK || s < worst || worst == GEVP_ERR_NOCONV)) worst = s;
+    const gevp_status s = st[i];
+    if (s == GEVP_OK) continue;
+    if (worst == GEVP_OK || worst == GEVP_ERR_NOCONV) worst = s;
   }
   return worst;
 }

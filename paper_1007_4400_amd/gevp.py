@@ -30,7 +30,7 @@ class Opts(ctypes.Structure):
         ("precision", ctypes.c_int), ("nex", ctypes.c_int), ("deg_init", ctypes.c_int),
         ("deg_max", ctypes.c_int), ("maxit", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
         ("seed", ctypes.c_ulonglong), ("skip_final_residual", ctypes.c_int),
-        ("reserved", ctypes.c_int * 8),
+        ("batch_streams", ctypes.c_int), ("reserved", ctypes.c_int * 7),
     ]
 
 
@@ -85,7 +85,7 @@ def load():
                                ctypes.POINTER(Info)]
     lib.gevp_solve.restype = I
     lib.gevp_solve_batched.argtypes = [P, ctypes.POINTER(Opts), I, P, P, P, P, P, P, P, P, P, D, P,
-                                       P, P, P, P, ctypes.POINTER(Info)]
+                                       P, P, P, P, P]
     lib.gevp_solve_batched.restype = I
     lib.gevp_backward.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
     lib.gevp_backward.restype = I
@@ -131,12 +131,13 @@ def _ld(t: torch.Tensor) -> int:
 
 
 def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_steps=0, seed=0,
-              skip_final_residual=False) -> Opts:
+              skip_final_residual=False, batch_streams=0) -> Opts:
     o = Opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.nex, o.deg_init, o.deg_max, o.maxit = nex, deg_init, deg_max, maxit
     o.lanczos_steps, o.seed = lanczos_steps, seed
     o.skip_final_residual = int(bool(skip_final_residual))
+    o.batch_streams = int(batch_streams)
     return o
 
 
@@ -204,6 +205,42 @@ class Handle:
         d = info.as_dict()
         d["status"] = s
         return lam, X, res, d
+
+    def solve_batched(self, problems, tol=1e-10, opts: Optional[Opts] = None, raise_on_noconv=True):
+        """Independent pencils solved concurrently.  ``problems`` is a list of
+        dicts with keys A, B, nev and optional X0, kx.  Returns a list of
+        (lam, X, resid, info dict)."""
+        opts = opts or make_opts()
+        cnt = len(problems)
+        arr = lambda t, vals: (t * cnt)(*vals)
+        As = [colmajor(p["A"]) for p in problems]
+        Bs = [colmajor(p["B"]) for p in problems]
+        X0s = [colmajor(p["X0"]) if p.get("X0") is not None else None for p in problems]
+        ns = [a.shape[0] for a in As]
+        nevs = [p["nev"] for p in problems]
+        kxs = [p.get("kx") or p["nev"] for p in problems]
+        lams = [torch.empty(k, dtype=torch.float64, device=a.device) for k, a in zip(kxs, As)]
+        Xs = [empty_colmajor(n, k, device=a.device) for n, k, a in zip(ns, kxs, As)]
+        rs = [torch.empty(k, dtype=torch.float64, device=a.device) for k, a in zip(kxs, As)]
+        infos = (Info * cnt)()
+        L64, VP, DP = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        self._stream()
+        s = self.lib.gevp_solve_batched(
+            self.h, ctypes.byref(opts), cnt, arr(L64, ns), arr(VP, [a.data_ptr() for a in As]),
+            arr(L64, [_ld(a) for a in As]), arr(VP, [b.data_ptr() for b in Bs]),
+            arr(L64, [_ld(b) for b in Bs]),
+            arr(VP, [x.data_ptr() if x is not None else None for x in X0s]),
+            arr(L64, [_ld(x) if x is not None else n for x, n in zip(X0s, ns)]),
+            arr(L64, [x.shape[1] if x is not None else 0 for x in X0s]), arr(L64, nevs), float(tol),
+            arr(L64, kxs), arr(VP, [t.data_ptr() for t in lams]), arr(VP, [x.data_ptr() for x in Xs]),
+            arr(L64, [_ld(x) for x in Xs]), arr(VP, [t.data_ptr() for t in rs]), infos)
+        if s != GEVP_OK and not (s == GEVP_ERR_NOCONV and not raise_on_noconv):
+            raise GevpError(s, "gevp_solve_batched")
+        out = []
+        for i in range(cnt):
+            d = infos[i].as_dict()
+            out.append((lams[i], Xs[i], rs[i], d))
+        return out
 
     def backward(self, X, lam, w, want_dA=True, want_dB=True):
         X = colmajor(X)

@@ -196,12 +196,15 @@ def batched_workloads(count: int = 32, nmin: int = 1500, nmax: int = 3000, seed:
 # device (torch) construction for the large sizes
 
 
-def make_pencil_torch(wl: Workload, seed: int, device="cuda", qr_on_host=False):
+def make_pencil_torch(wl: Workload, seed: int, device="cuda", qr_on_host=False, exact_nev=0):
     """The same construction with a seeded torch generator on ``device``.
     Returns (A, B, Lambda, L, gen) as torch tensors (row-major logical
     matrices, complex128) plus the generator for the perturbations.
     qr_on_host: factor the Gaussian matrix on the host (same draws, same
-    construction; used where a device QR is unavailable)."""
+    construction; used where a device QR is unavailable).
+    exact_nev > 0: also return the exact lowest eigenvalues and B-orthonormal
+    eigenvectors L^{-H} Q(:, order) of the step-0 pencil (appended to the
+    returned tuple)."""
     import torch
 
     g = torch.Generator(device=device)
@@ -231,6 +234,11 @@ def make_pencil_torch(wl: Workload, seed: int, device="cuda", qr_on_host=False):
     d = torch.diagonal(R)
     Q = Q * (d / d.abs())[None, :]
     del R
+    exact = None
+    if exact_nev:
+        order = torch.argsort(lam)[:exact_nev]
+        Xe = torch.linalg.solve_triangular(L.conj().T.contiguous(), Q[:, order].contiguous(), upper=True)
+        exact = (lam[order], Xe)
     M = L @ Q
     del Q
     A = (M * lam[None, :].to(M.dtype)) @ M.conj().T.contiguous()
@@ -238,6 +246,8 @@ def make_pencil_torch(wl: Workload, seed: int, device="cuda", qr_on_host=False):
     A = 0.5 * (A + A.conj().T)
     B = L @ L.conj().T.contiguous()
     B = 0.5 * (B + B.conj().T)
+    if exact_nev:
+        return A, B, lam, L, g, exact
     return A, B, lam, L, g
 
 

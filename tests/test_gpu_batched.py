@@ -1,0 +1,64 @@
+"""Batched k-points (the paper, section 1: one independent pencil per Bloch
+vector): uneven sizes solved concurrently on several streams must give the
+same pairs as one-by-one solves (bitwise: each problem's arithmetic is the
+same) and pass the oracle bar."""
+import numpy as np
+import pytest
+
+from paper_1007_4400_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1007_4400_amd import gevp
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return gevp.Handle(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_batched_matches_single_and_oracle(h, oracle_mod, precision):
+    from paper_1007_4400_amd import gevp
+
+    wls = synth.batched_workloads(count=6, nmin=150, nmax=330, seed=3, steps=2)
+    opts = gevp.make_opts(precision=precision, batch_streams=3)
+    pencils = [synth.make_pencil(wl, s)[0] for wl, s in wls]
+    probs = [{"A": _dev(p.A), "B": _dev(p.B), "nev": wl.nev} for p, (wl, _) in zip(pencils, wls)]
+    print("batched", precision, [wl.n for wl, _ in wls], flush=True)
+    out = h.solve_batched(probs, tol=TOL, opts=opts)
+    for (lam, X, res, info), p, (wl, _) in zip(out, pencils, wls):
+        lam1, X1, _, _ = h.solve(_dev(p.A), _dev(p.B), wl.nev, tol=TOL, opts=opts)
+        assert torch.equal(lam, lam1) and torch.equal(X, X1)
+        lam_ref, _ = oracle_mod.solve(p.A, p.B, wl.nev)
+        ln = lam.cpu().numpy()
+        assert np.max(np.abs(ln - lam_ref) / np.maximum(np.abs(lam_ref), 1)) <= TOL
+        r, orth = oracle_mod.residuals(p.A, p.B, ln, X.cpu().numpy())
+        assert r.max() <= TOL * np.linalg.norm(p.A, 2) and orth <= 1e-9
+
+
+def test_batched_seeded_sequence(h, oracle_mod):
+    from paper_1007_4400_amd import gevp
+
+    wls = synth.batched_workloads(count=4, nmin=120, nmax=260, seed=5, steps=3)
+    opts = gevp.make_opts(precision="bf16x3", batch_streams=4)
+    seqs = [list(synth.sequence(wl, s)) for wl, s in wls]
+    X = [None] * len(wls)
+    for k in range(3):
+        probs = [{"A": _dev(seq[k][0]), "B": _dev(seq[k][1]), "nev": wl.nev, "X0": X[i],
+                  "kx": h.block_size(wl.n, wl.nev, opts)} for i, ((wl, _), seq) in enumerate(zip(wls, seqs))]
+        out = h.solve_batched(probs, tol=TOL, opts=opts)
+        for i, ((lam, Xi, res, info), (wl, _), seq) in enumerate(zip(out, wls, seqs)):
+            A, B = seq[k]
+            lam_ref, _ = oracle_mod.solve(A, B, wl.nev)
+            ln = lam.cpu().numpy()[: wl.nev]
+            assert np.max(np.abs(ln - lam_ref) / np.maximum(np.abs(lam_ref), 1)) <= TOL
+            X[i] = Xi

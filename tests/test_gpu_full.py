@@ -1,0 +1,97 @@
+"""Parity at the benchmark's full size (n = 8192, nev = 820, the launch
+configuration bench.py times), where the oracle cannot solve in seconds:
+step 0 against the constructed spectrum (closed form), the library's own
+FP64 residual check on every step, and sampled pairs re-checked by the
+oracle's O(n^2) residual on the host.  Also the n = 2048 sequence with
+seeded and cold solves compared, and the gradient at n = 4096 against the
+closed form."""
+import numpy as np
+import pytest
+
+from paper_1007_4400_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1007_4400_amd import gevp
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return gevp.Handle(0)
+
+
+def test_full_size_sequence_bf16x3(h, oracle_mod):
+    from paper_1007_4400_amd import gevp
+
+    wl = synth.LARGE
+    A0, B, lam0, L, g = synth.make_pencil_torch(wl, 0)
+    del L
+    B = gevp.colmajor(B.contiguous())
+    A = gevp.colmajor(A0)
+    del A0
+    opts = gevp.make_opts(precision="bf16x3")
+    kx = h.block_size(wl.n, wl.nev, opts)
+    exact = torch.sort(lam0).values[: wl.nev]
+    lam, X, res, info = h.solve(A, B, wl.nev, tol=TOL, kx=kx, opts=opts)
+    err = ((lam[: wl.nev] - exact).abs() / exact.abs().clamp(min=1)).max().item()
+    print("step 0", info["outer_iters"], info["max_resid"], err, flush=True)
+    assert err <= TOL and info["max_resid"] <= TOL
+    for k in (1, 2):
+        Hk = synth.unit_hermitian_torch(wl.n, g)
+        A = gevp.colmajor((A + synth.eps(wl, k) * Hk).contiguous())
+        del Hk
+        lam, X, res, info = h.solve(A, B, wl.nev, X0=X, tol=TOL, kx=kx, opts=opts)
+        print("step", k, info["outer_iters"], info["max_resid"], flush=True)
+        assert info["max_resid"] <= TOL
+    # sampled pairs, checked independently on the host
+    An, Bn = A.cpu().numpy(), B.cpu().numpy()
+    ln, Xn = lam.cpu().numpy(), X.cpu().numpy()
+    for i in (0, 409, wl.nev - 1):
+        r, q = oracle_mod.pair_residual(An, Bn, ln[i], Xn[:, i])
+        assert r <= TOL * info["normA"] and abs(q - 1.0) <= 1e-9
+
+
+def test_medium_sequence_seeded_vs_cold(h, oracle_mod):
+    """n = 2048, nev = 205: a seeded sequence of 6 steps; steps 0 and 5 also
+    against the oracle; seeded and cold solves of step 5 agree."""
+    wl = synth.scaled(synth.MEDIUM, 2048, steps=6)
+    X = None
+    kx = h.block_size(wl.n, wl.nev)
+    seq = list(synth.sequence(wl, 0))
+    for k, (A, B) in enumerate(seq):
+        Ad = torch.from_numpy(np.asfortranarray(A)).cuda()
+        Bd = torch.from_numpy(np.asfortranarray(B)).cuda()
+        lam, X, res, info = h.solve(Ad, Bd, wl.nev, X0=X, tol=TOL, kx=kx)
+        assert info["max_resid"] <= TOL
+        if k in (0, len(seq) - 1):
+            lam_ref, _ = oracle_mod.solve(A, B, wl.nev)
+            ln = lam.cpu().numpy()[: wl.nev]
+            assert np.max(np.abs(ln - lam_ref) / np.maximum(np.abs(lam_ref), 1)) <= TOL
+    lam_c, _, _, info_c = h.solve(Ad, Bd, wl.nev, tol=TOL)
+    assert torch.max((lam_c - lam[: wl.nev]).abs() / lam_c.abs().clamp(min=1)).item() <= TOL
+    assert info["col_degrees"] < info_c["col_degrees"]
+
+
+def test_gradient_n4096_closed_form(h):
+    """The adjoint at the unperturbed n = 4096 pencil (nev = 410, Fermi-Dirac
+    weights at kT = 0.01 around the 380th eigenvalue) against the gradient
+    built from the construction alone, X = L^{-H} Q (no eigensolver)."""
+    from paper_1007_4400_amd import gevp
+
+    wl = synth.GRAD
+    A0, B, lam0, L, g, (ex, Xe) = synth.make_pencil_torch(wl, 1, exact_nev=wl.nev)
+    del L
+    lam, X, _, _ = h.solve(gevp.colmajor(A0), gevp.colmajor(B.contiguous()), wl.nev, tol=TOL)
+    assert ((lam - ex).abs() / ex.abs().clamp(min=1)).max().item() <= TOL
+    f = 1.0 / (1.0 + torch.exp((ex - ex[379]) / 0.01))
+    dA, dB = h.backward(X, lam, f)
+    GA = (Xe * f[None, :].to(Xe.dtype)) @ Xe.conj().T.contiguous()
+    GB = -(Xe * (f * ex)[None, :].to(Xe.dtype)) @ Xe.conj().T.contiguous()
+    ea = torch.linalg.norm(dA - GA).item() / torch.linalg.norm(GA).item()
+    eb = torch.linalg.norm(dB - GB).item() / torch.linalg.norm(GB).item()
+    print("grad n4096 rel err", ea, eb, flush=True)
+    assert ea <= 1e-6 and eb <= 1e-6
