@@ -44,11 +44,19 @@ __device__ void reg_inverse_to(zd (*S)[NB], zd (*xrow)[NB], int n, zd* Dinv, int
       }
     }
     __syncthreads();
-    // rows i > k subtract l_ik * x_k (a zero multiplier elsewhere, no branch)
-    const zd lik = (i > k && i < n) ? S[k][i] : make_double2(0.0, 0.0);
+    // rows i > k subtract l_ik * x_k; every load is unconditional (valid
+    // addresses) and a 0/1 factor masks the update, so no branch splits the
+    // batch of LDS reads
+    const double fk = (i > k && i < n) ? 1.0 : 0.0;
+    zd lik = S[k][i];
+    lik.x *= fk;
+    lik.y *= fk;
+    zd xv[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) xv[m] = xr[kq + 4 * m];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const zd t = zmul(lik, xr[kq + 4 * m]);
+      const zd t = zmul(lik, xv[m]);
       b[m].x -= t.x;
       b[m].y -= t.y;
     }
@@ -99,15 +107,21 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
       if (badp) atomicMin(info, goff + j + 1);
     }
     const double id = 1.0 / d;  // 1 / l_jj^2
-    // a_ic -= a_ij conj(a_cj) / l_jj^2 for j < c <= i (a zero factor elsewhere)
-    const zd ci = (i > j && i < n) ? cb[j & 1][i] : make_double2(0.0, 0.0);
-    const zd cs = make_double2(ci.x * id, ci.y * id);
+    // a_ic -= a_ij conj(a_cj) / l_jj^2 for j < c <= i; unconditional loads,
+    // a 0/1 factor masks the update (no branch between the LDS reads)
+    const zd ci = cb[j & 1][i];
+    const double fi = (i > j && i < n) ? id : 0.0;
+    const zd cs = make_double2(ci.x * fi, ci.y * fi);
+    zd ck[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) ck[m] = cb[j & 1][kq + 4 * m];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int c = kq + 4 * m;
-      const zd ck = (c > j && c <= i) ? cb[j & 1][c] : make_double2(0.0, 0.0);
-      a[m].x -= cs.x * ck.x + cs.y * ck.y;
-      a[m].y -= cs.y * ck.x - cs.x * ck.y;
+      const double f = (c > j && c <= i) ? 1.0 : 0.0;
+      const double sr = cs.x * ck[m].x + cs.y * ck[m].y, si = cs.y * ck[m].x - cs.x * ck[m].y;
+      a[m].x -= f * sr;
+      a[m].y -= f * si;
     }
   }
   __syncthreads();

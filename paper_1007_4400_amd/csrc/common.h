@@ -115,6 +115,7 @@ gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const do
 gevp_status launch_scale_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                               const double* w, zd* D, int64_t ldd);
 gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d);
+gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out);
 
 // Lanczos bounds: runs `steps` steps on the Hermitian M (full storage) and
 // writes into out[0..5]: theta_min, theta_max, beta_last, upper bound

@@ -56,62 +56,89 @@ struct TrdArgs {
 };
 
 // Reflector s (0 <= s <= n-2); s == n-1 finishes the last diagonal entry.
-__global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
-  extern __shared__ zd vs[];  // v_s, indices s+1 .. n-1 stored at [i]
-  __shared__ double sh[4];
-  __shared__ double shK[2];
+// One pass over global memory per step: every thread first loads its share
+// of column s, v_{s-1} and p_{s-1} (rows s .. n-1, at most QMAX per thread)
+// together with one partial sum, everything else is formed in registers and
+// LDS: w_{s-1} = p - K v (K from the partials), the updated column s, the
+// reflector, and the staged vectors v_s, w_{s-1}, v_{s-1} that the column
+// updates read.
+// LDS: sm = [v_s | w_{s-1} | v_{s-1}], each n complex; sh: 8 doubles.
+constexpr int QMAX = 8;  // rows per thread: n <= QMAX * HT
+
+__device__ __forceinline__ zd bsum2(zd v, double* sh) {
+  v.x = wsum(v.x);
+  v.y = wsum(v.y);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    sh[2 * w] = v.x;
+    sh[2 * w + 1] = v.y;
+  }
+  __syncthreads();
+  const zd r = make_double2(sh[0] + sh[2] + sh[4] + sh[6], sh[1] + sh[3] + sh[5] + sh[7]);
+  __syncthreads();
+  return r;
+}
+
+__device__ void hetrd_body(const TrdArgs& a, int s, zd* sm, double* sh, zd* bc) {
   const int n = a.n, tid = threadIdx.x, wg = blockIdx.x;
   const int prev = s - 1;
-  // scalars of the previous reflector: K = 1/2 conj(tau) sum(partials),
-  // w = p - K v
-  zd K = make_double2(0.0, 0.0);
+  zd* vs = sm;            // v_s
+  zd* sw = sm + n;        // w_{s-1}
+  zd* sv = sm + 2 * n;    // v_{s-1}
   const zd* vp = (prev >= 0) ? a.V + (int64_t)prev * a.ldv : nullptr;
   const zd* pprev = (prev >= 0) ? a.pb + (int64_t)(prev & 1) * n : nullptr;
+  const zd* cs = a.H + (int64_t)s * a.ldh;
+  // ---- the one round of global loads
+  zd hc[QMAX], vv[QMAX], pv[QMAX];
+  zd ppart = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int i = s + tid + q * HT;
+    hc[q] = (i < n) ? cs[i] : make_double2(0.0, 0.0);
+    vv[q] = (prev >= 0 && i < n) ? vp[i] : make_double2(0.0, 0.0);
+    pv[q] = (prev >= 0 && i < n) ? pprev[i] : make_double2(0.0, 0.0);
+  }
+  if (prev >= 0 && tid < a.G) ppart = a.pp[(int64_t)(prev & 1) * a.G + tid];
+  const zd taup = (prev >= 0) ? a.tau[prev] : make_double2(0.0, 0.0);
+  // ---- K = 1/2 conj(tau) sum(partials); w = p - K v
+  zd K = make_double2(0.0, 0.0);
   if (prev >= 0) {
-    double sr = 0.0, si = 0.0;
-    for (int g = tid; g < a.G; g += HT) {
-      const zd q = a.pp[(int64_t)(prev & 1) * a.G + g];
-      sr += q.x;
-      si += q.y;
-    }
-    sr = bsum(sr, sh);
-    si = bsum(si, sh);
-    const zd t = cconj(a.tau[prev]);
-    const zd k2 = cmul(t, make_double2(sr, si));
+    const zd ps = bsum2(ppart, sh);
+    const zd k2 = cmul(cconj(taup), ps);
     K = make_double2(0.5 * k2.x, 0.5 * k2.y);
   }
-  auto wprev = [&](int i) -> zd {  // w_{s-1}[i]
-    const zd p = pprev[i], v = vp[i], kv = cmul(K, v);
-    return make_double2(p.x - kv.x, p.y - kv.y);
-  };
-  // updated column s entry i (i >= s): H(i,s) - v_i conj(w_s) - w_i conj(v_s)
-  zd vps = make_double2(0.0, 0.0), wps = make_double2(0.0, 0.0);
-  if (prev >= 0) {
-    vps = vp[s];
-    wps = wprev(s);
+  zd ww[QMAX];
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const zd kv = cmul(K, vv[q]);
+    ww[q] = make_double2(pv[q].x - kv.x, pv[q].y - kv.y);
   }
-  auto colS = [&](int i) -> zd {
-    zd h = a.H[i + (int64_t)s * a.ldh];
-    if (prev >= 0) {
-      const zd v = vp[i], w = wprev(i);
-      const zd t1 = cmul(v, cconj(wps)), t2 = cmul(w, cconj(vps));
-      h.x -= t1.x + t2.x;
-      h.y -= t1.y + t2.y;
-    }
-    return h;
-  };
+  // v_s and w_s of the previous reflector (row s, owned by thread 0, q = 0)
+  if (tid == 0) {
+    bc[0] = vv[0];
+    bc[1] = ww[0];
+  }
+  __syncthreads();
+  const zd vps = bc[0], wps = bc[1];
+  // updated column s: H(i,s) - v_i conj(w_s) - w_i conj(v_s)
+  double sig = 0.0;
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int i = s + tid + q * HT;
+    const zd t1 = cmul(vv[q], cconj(wps)), t2 = cmul(ww[q], cconj(vps));
+    hc[q].x -= t1.x + t2.x;
+    hc[q].y -= t1.y + t2.y;
+    if (i >= s + 2 && i < n) sig += hc[q].x * hc[q].x + hc[q].y * hc[q].y;
+    if (i == s + 1) bc[2] = hc[q];
+    if (i == s) bc[3] = hc[q];
+  }
+  sig = bsum(sig, sh);  // its barriers also publish bc[2], bc[3]
   if (s == n - 1) {  // finish: last diagonal entry only
-    if (wg == 0 && tid == 0) a.d[s] = colS(s).x;
+    if (wg == 0 && tid == 0) a.d[s] = bc[3].x;
     return;
   }
-  // reflector s from x = column s, rows s+1 .. n-1
-  double sig = 0.0;
-  for (int i = s + 2 + tid; i < n; i += HT) {
-    const zd c = colS(i);
-    sig += c.x * c.x + c.y * c.y;
-  }
-  sig = bsum(sig, sh);
-  const zd alpha = colS(s + 1);
+  const zd alpha = bc[2];
   zd tau = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   double beta;
   if (sig == 0.0 && alpha.y == 0.0) {
@@ -124,7 +151,16 @@ __global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
     const double dd = den.x * den.x + den.y * den.y;
     scal = make_double2(den.x / dd, -den.y / dd);
   }
-  for (int i = s + 1 + tid; i < n; i += HT) vs[i] = (i == s + 1) ? make_double2(1.0, 0.0) : cmul(colS(i), scal);
+  // stage v_s, w_{s-1}, v_{s-1} in LDS
+#pragma unroll
+  for (int q = 0; q < QMAX; ++q) {
+    const int i = s + tid + q * HT;
+    if (i < n) {
+      vs[i] = (i == s + 1) ? make_double2(1.0, 0.0) : (i > s + 1 ? cmul(hc[q], scal) : make_double2(0.0, 0.0));
+      sw[i] = ww[q];
+      sv[i] = vv[q];
+    }
+  }
   __syncthreads();
   if (wg == 0) {
     zd* vcol = a.V + (int64_t)s * a.ldv;
@@ -132,28 +168,24 @@ __global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
     if (tid == 0) {
       a.tau[s] = tau;
       a.e[s] = beta;
-      a.d[s] = colS(s).x;
+      a.d[s] = bc[3].x;
     }
   }
   // own columns j >= s+1, j % G == wg: finish the previous update on rows
-  // >= s+1 and accumulate p_s[j] = tau (v_s^H H(:, j))^* ... via Hermitian
-  // symmetry: p_j = tau sum_i conj(H(i,j)) v_i
+  // >= s+1 and accumulate p_s[j] = tau sum_i conj(H(i,j)) v_i (Hermitian
+  // symmetry turns the row product into a contiguous column product)
   const int lane = tid & 63, wave = tid >> 6;
   zd part = make_double2(0.0, 0.0);
   zd* pcur = a.pb + (int64_t)(s & 1) * n;
-  int j0 = s + 1 + ((wg - (s + 1)) % a.G + a.G) % a.G;
+  const int j0 = s + 1 + ((wg - (s + 1)) % a.G + a.G) % a.G;
   for (int j = j0 + wave * a.G; j < n; j += 4 * a.G) {
     zd* col = a.H + (int64_t)j * a.ldh;
-    zd vj = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
-    if (prev >= 0) {
-      vj = vp[j];
-      wj = wprev(j);
-    }
+    const zd vj = sv[j], wj = sw[j];
     double ar = 0.0, ai = 0.0;
     for (int i = s + 1 + lane; i < n; i += 64) {
       zd h = col[i];
       if (prev >= 0) {
-        const zd v = vp[i], w = wprev(i);
+        const zd v = sv[i], w = sw[i];
         const zd t1 = cmul(v, cconj(wj)), t2 = cmul(w, cconj(vj));
         h.x -= t1.x + t2.x;
         h.y -= t1.y + t2.y;
@@ -168,17 +200,21 @@ __global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
     const zd pj = cmul(tau, make_double2(ar, ai));
     if (lane == 0) {
       pcur[j] = pj;
-      const zd cv = cconj(vs[j]);
-      const zd t = cmul(cv, pj);
+      const zd t = cmul(cconj(vs[j]), pj);
       part.x += t.x;
       part.y += t.y;
     }
   }
   // work-group partial of v_s^H p_s
-  double pr = bsum(lane == 0 ? part.x : 0.0, sh);
-  double pi = bsum(lane == 0 ? part.y : 0.0, sh);
-  if (tid == 0) a.pp[(int64_t)(s & 1) * a.G + wg] = make_double2(pr, pi);
-  (void)shK;
+  const zd pt = bsum2(lane == 0 ? part : make_double2(0.0, 0.0), sh);
+  if (tid == 0) a.pp[(int64_t)(s & 1) * a.G + wg] = pt;
+}
+
+__global__ __launch_bounds__(HT) void k_hetrd_step(TrdArgs a, int s) {
+  extern __shared__ double sm[];
+  __shared__ double sh[8];
+  __shared__ zd bc[4];
+  hetrd_body(a, s, reinterpret_cast<zd*>(sm), sh, bc);
 }
 
 // Sturm count: number of eigenvalues of T smaller than x.
@@ -493,14 +529,24 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   double* tn = (double*)take(sizeof(double) * 8);
 
   const size_t shv = sizeof(zd) * (size_t)n;
+  const size_t sh3 = 3 * shv;  // v_s, w_{s-1}, v_{s-1}
+  static const bool attr = [&]() {
+    (void)hipFuncSetAttribute((const void*)k_hetrd_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(3 * sizeof(zd) * 2048));
+    return true;
+  }();
+  (void)attr;
   if (n == 1) {
-    hipLaunchKernelGGL(k_hetrd_step, dim3(1), dim3(HT), shv, c->stream, a, 0);
+    hipLaunchKernelGGL(k_hetrd_step, dim3(1), dim3(HT), sh3, c->stream, a, 0);
     GEVP_HIP_TRY(hipGetLastError());
     GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd), c->stream));
   } else {
     GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd) * n, c->stream));
+    // one launch per reflector: the kernel boundary is the grid-wide barrier
+    // (a cooperative single launch with explicit barriers measured slower,
+    // because each barrier must write back and invalidate the XCD caches)
     for (int s = 0; s <= n - 1; ++s) {
-      hipLaunchKernelGGL(k_hetrd_step, dim3(G), dim3(HT), shv, c->stream, a, s);
+      hipLaunchKernelGGL(k_hetrd_step, dim3(G), dim3(HT), sh3, c->stream, a, s);
       GEVP_HIP_TRY(hipGetLastError());
     }
   }

@@ -269,6 +269,13 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
     sd[4] = tol_abs;
     sd[5] = (double)sum;
     sd[6] = mu;
+    double rmax = 0.0, rmin = 1e300;
+    for (int i = 0; i < nev && i < nb; ++i) {
+      rmax = fmax(rmax, resid[i]);
+      rmin = fmin(rmin, resid[i]);
+    }
+    sd[7] = rmax;
+    sd[8] = rmin;
     // filter coefficients, step j at coefs[3 (j - 1)]
     const double s1 = e / (mu - c);
     double sg = s1;

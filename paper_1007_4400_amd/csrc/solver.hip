@@ -126,12 +126,22 @@ struct QrWork {
   double* shift;
 };
 
+// try_skip: the block may already be orthonormal (a seed from the previous
+// step with an unchanged overlap): if the first Gram matrix is the identity
+// to 5e-13, no factorisation is needed.
 gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWork& w,
-                    int* fallbacks) {
+                    int* fallbacks, bool try_skip = false) {
   for (int pass = 0; pass < 2; ++pass) {
     GEVP_TRY(launch_colnorm_scale(c, n, m, P, ldp));
     GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
                           nullptr, w.G, m));
+    if (pass == 0 && try_skip) {
+      double dev = 1.0;
+      GEVP_TRY(launch_max_offident(c, m, w.G, m, w.shift + 1));
+      GEVP_HIP_TRY(hipMemcpyAsync(&dev, w.shift + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+      if (dev <= 5e-13) return GEVP_OK;
+    }
     const int big = 0x7fffffff;
     GEVP_HIP_TRY(hipMemcpyAsync(w.flag, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
     GEVP_TRY(chol_lower(c, m, w.G, m, w.Dg, m, w.flag));
@@ -508,7 +518,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   cp.mode = mixed ? 2 : 0;
   for (it = 0; it < o.maxit; ++it) {
     tm.start();
-    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks));
+    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, seeded && it == 0 && k0 >= nb));
     tm.stop(info, GEVP_STAGE_QR);
     tm.start();
     GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
@@ -533,8 +543,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
     info->nconv = hst[0];
     if (gevp_log_enabled())
-      fprintf(stderr, "[gevp] it %d nconv %d maxdeg %d a %.4g b %.4g tol %.3g\n", it, hst[0], hst[1],
-              hsd[0], hsd[1], hsd[4]);
+      fprintf(stderr, "[gevp] it %d nconv %d maxdeg %d a %.4g b %.4g tol %.3g resid %.3g..%.3g\n", it,
+              hst[0], hst[1], hsd[0], hsd[1], hsd[4], hsd[8], hsd[7]);
     if (hst[2]) {
       converged = true;
       break;

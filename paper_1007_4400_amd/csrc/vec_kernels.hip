@@ -256,6 +256,25 @@ __global__ void k_copy_real(int64_t n, const double* s, double* d) {
   if (i < n) d[i] = s[i];
 }
 
+// out[0] = max_ij |M(i,j) - delta_ij| (one work-group)
+__global__ __launch_bounds__(1024) void k_max_offident(int64_t n, const zd* M, int64_t ldm, double* out) {
+  __shared__ double sh[1024];
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < n * n; e += 1024) {
+    const int64_t i = e % n, j = e / n;
+    zd v = M[i + j * ldm];
+    if (i == j) v.x -= 1.0;
+    mx = fmax(mx, hypot(v.x, v.y));
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 inline unsigned gx(int64_t rows) {
   int64_t b = (rows + 255) / 256;
   return (unsigned)(b < 64 ? (b < 1 ? 1 : b) : 64);
@@ -375,6 +394,12 @@ gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d)
   if (n <= 0) return GEVP_OK;
   hipLaunchKernelGGL(k_copy_real, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, s,
                      d);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out) {
+  hipLaunchKernelGGL(k_max_offident, dim3(1), dim3(1024), 0, c->stream, n, M, ldm, out);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }
