@@ -136,8 +136,17 @@ def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="time
     except Exception:
         pmc = []
     for kname, cname, val, cnt in pmc:
-        if kernel_substr in kname or "copyBuffer" in kname:
-            lines.append(f"pmc {cname} avg per dispatch {val:.1f} (x{cnt})  {kname[:80]}")
+        if kernel_substr in kname:
+            lines.append(f"pmc {cname} avg per dispatch {val:.1f} KiB (x{cnt})  {kname[:80]}")
+    if pmc:
+        # the calibration copy (1 GiB read, 1 GiB written) is the largest
+        # device copy of the run
+        cal = cur.execute("select counter_name, max(value), grid_size from counters_collection "
+                          "where kernel_name like '%copyBuffer%' group by counter_name").fetchall()
+        for cname, val, grid in cal:
+            if val and val > 0:
+                lines.append(f"calibration copy {cname} {val:.1f} KiB (grid {grid}); "
+                             f"factor to true bytes {1048576.0 / val:.4f}")
     return "\n".join(lines)
 
 

@@ -15,14 +15,24 @@
 // (re hi, re lo, im hi, im lo) of its ROWS: C is Hermitian, so row i is the
 // conjugate of stored column i and the conversion reads columns
 // contiguously; in the planes 8 consecutive k of one row (one MFMA fragment)
-// are 16 contiguous bytes.  B is the FP32 complex iterate, split into planes
-// while it is staged into LDS.
+// are 16 contiguous bytes.  B, the FP32 complex iterate, is split into the
+// same plane layout (per column) by a pass before the product, so the main
+// loop stages both operands as plain 16-byte copies and does no conversion.
 //
 // Tiling: 512 threads (8 waves, 2 x 4) own a 128 x 128 complex output tile,
 // each wave 64 x 32 (4 x 2 MFMA blocks); K advances 32 per slice through a
-// double-buffered LDS stage (row stride padded by 16 bytes so a fragment
-// read by 16 lanes touches 64 distinct banks), with the next slice's global
-// loads in flight during the current slice's MFMAs.
+// double-buffered LDS stage.  A staged row keeps the global order (k-group
+// major, plane minor, 256 bytes) and is padded by 16 bytes, so both the
+// fragment reads (16 rows, one chunk each) and the staging writes (4 rows x 4
+// k-groups) of 16 lanes touch 64 distinct banks.  Global loads run two
+// slices ahead of the MFMAs.
+//
+// One work-group per compute unit runs at a time (136 KB of LDS), so a grid
+// of T tiles takes ceil(T / CUs) rounds.  When that rounds badly (T = 384 on
+// 256 CUs costs two full rounds for 1.5 rounds of work) the K range is split
+// in s parts: each work-group writes its FP32 partial tile to a workspace
+// and a second kernel sums the s partials in a fixed order and applies the
+// epilogue, so the result does not depend on scheduling.
 #include "common.h"
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -49,7 +59,11 @@ struct BfParams {
   const double* beta;
   const double* gamma;
   const double* delta;
-  int tiles_n, total, remap;
+  const uint4* Bp;    // B planes: [(col * KG + g) * 4 + plane]
+  zf* part;           // split-K partial tiles (splits > 1)
+  int tiles_n, tiles, total, remap;
+  int nks;            // K slices per split
+  int splits;
 };
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
@@ -72,21 +86,6 @@ __device__ __forceinline__ void split8(const float* x, uint4& hi, uint4& lo) {
   lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
 }
 
-__device__ __forceinline__ unsigned pack_split(float a, float b, unsigned& lo) {
-  const unsigned short ha = bf16_rne(a), hb = bf16_rne(b);
-  const unsigned short la = bf16_rne(a - bf16_f(ha)), lb = bf16_rne(b - bf16_f(hb));
-  lo = (unsigned)la | ((unsigned)lb << 16);
-  return (unsigned)ha | ((unsigned)hb << 16);
-}
-__device__ __forceinline__ void split8v(float x0, float x1, float x2, float x3, float x4, float x5,
-                                        float x6, float x7, uint4& hi, uint4& lo) {
-  unsigned l0, l1, l2, l3;
-  const unsigned h0 = pack_split(x0, x1, l0), h1 = pack_split(x2, x3, l1);
-  const unsigned h2 = pack_split(x4, x5, l2), h3 = pack_split(x6, x7, l3);
-  hi = make_uint4(h0, h1, h2, h3);
-  lo = make_uint4(l0, l1, l2, l3);
-}
-
 __device__ __forceinline__ bf8 as_bf8(uint4 v) { return __builtin_bit_cast(bf8, v); }
 __device__ __forceinline__ uint4 negbf(uint4 v) {
   return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
@@ -104,7 +103,8 @@ __global__ __launch_bounds__(NTHR, 1) void k_cgemm_bf16x3_filter(BfParams p) {
     const int per = p.total >> 3;
     L = (L & 7) * per + (L >> 3);
   }
-  const int tm = L / p.tiles_n, tn = L - tm * p.tiles_n;
+  const int kc = L / p.tiles, tile = L - kc * p.tiles;
+  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 2, wc = wave & 3;  // 2 x 4 waves; wave tile 64 x 32
@@ -120,126 +120,137 @@ __global__ __launch_bounds__(NTHR, 1) void k_cgemm_bf16x3_filter(BfParams p) {
     }
 
   // staging assignment: thread -> (row/col = tid / 4, k-group q = tid % 4);
-  // held in plain vector registers (no arrays, so nothing lands in scratch)
+  // two register sets (suffix _0 / _1) keep the global loads two K slices
+  // ahead of the MFMAs, enough to cover a miss to the last-level cache; plain
+  // vector registers (no arrays, so nothing lands in scratch)
   const int sr = tid >> 2, sq = tid & 3;
-  uint4 pa0, pa1, pa2, pa3;  // planes of one k-group of row sr
-  float4 gb0, gb1, gb2, gb3;  // 8 complex of column sr, k-group sq (re, im interleaved)
+  uint4 pa0_0, pa1_0, pa2_0, pa3_0, pb0_0, pb1_0, pb2_0, pb3_0;
+  uint4 pa0_1, pa1_1, pa2_1, pa3_1, pb0_1, pb1_1, pb2_1, pb3_1;
   const uint4 z4 = make_uint4(0, 0, 0, 0);
-  const float4 zf4 = make_float4(0.f, 0.f, 0.f, 0.f);
 
-#define GLOAD(t)                                                                 \
+#define GLOAD(t, S)                                                              \
   do {                                                                           \
     const int g_ = (t) * 4 + sq;                                                 \
     const int gm_ = row0 + sr;                                                   \
     if (gm_ < p.M && g_ < p.KG) {                                                \
       const uint4* src_ = p.A + ((int64_t)gm_ * p.KG + g_) * 4;                  \
-      pa0 = src_[0];                                                             \
-      pa1 = src_[1];                                                             \
-      pa2 = src_[2];                                                             \
-      pa3 = src_[3];                                                             \
+      pa0_##S = src_[0];                                                         \
+      pa1_##S = src_[1];                                                         \
+      pa2_##S = src_[2];                                                         \
+      pa3_##S = src_[3];                                                         \
     } else {                                                                     \
-      pa0 = pa1 = pa2 = pa3 = z4;                                                \
+      pa0_##S = pa1_##S = pa2_##S = pa3_##S = z4;                                \
     }                                                                            \
     const int gn_ = col0 + sr;                                                   \
-    const int k0_ = g_ * 8;                                                      \
-    if (gn_ < p.N && k0_ + 8 <= p.K) {                                           \
-      const float4* col_ = (const float4*)(p.B + (int64_t)gn_ * p.ldb + k0_);   \
-      gb0 = col_[0];                                                             \
-      gb1 = col_[1];                                                             \
-      gb2 = col_[2];                                                             \
-      gb3 = col_[3];                                                             \
-    } else if (gn_ < p.N) {                                                      \
-      const zf* col_ = p.B + (int64_t)gn_ * p.ldb;                               \
-      const zf v0 = (k0_ + 0 < p.K) ? col_[k0_ + 0] : make_float2(0.f, 0.f);     \
-      const zf v1 = (k0_ + 1 < p.K) ? col_[k0_ + 1] : make_float2(0.f, 0.f);     \
-      const zf v2 = (k0_ + 2 < p.K) ? col_[k0_ + 2] : make_float2(0.f, 0.f);     \
-      const zf v3 = (k0_ + 3 < p.K) ? col_[k0_ + 3] : make_float2(0.f, 0.f);     \
-      const zf v4 = (k0_ + 4 < p.K) ? col_[k0_ + 4] : make_float2(0.f, 0.f);     \
-      const zf v5 = (k0_ + 5 < p.K) ? col_[k0_ + 5] : make_float2(0.f, 0.f);     \
-      const zf v6 = (k0_ + 6 < p.K) ? col_[k0_ + 6] : make_float2(0.f, 0.f);     \
-      const zf v7 = (k0_ + 7 < p.K) ? col_[k0_ + 7] : make_float2(0.f, 0.f);     \
-      gb0 = make_float4(v0.x, v0.y, v1.x, v1.y);                                 \
-      gb1 = make_float4(v2.x, v2.y, v3.x, v3.y);                                 \
-      gb2 = make_float4(v4.x, v4.y, v5.x, v5.y);                                 \
-      gb3 = make_float4(v6.x, v6.y, v7.x, v7.y);                                 \
+    if (gn_ < p.N && g_ < p.KG) {                                                \
+      const uint4* src_ = p.Bp + ((int64_t)gn_ * p.KG + g_) * 4;                 \
+      pb0_##S = src_[0];                                                         \
+      pb1_##S = src_[1];                                                         \
+      pb2_##S = src_[2];                                                         \
+      pb3_##S = src_[3];                                                         \
     } else {                                                                     \
-      gb0 = gb1 = gb2 = gb3 = zf4;                                               \
+      pb0_##S = pb1_##S = pb2_##S = pb3_##S = z4;                                \
     }                                                                            \
   } while (0)
 
-#define SSTORE(buf)                                                              \
+#define SSTORE(buf, S)                                                           \
   do {                                                                           \
     uint4* ra_ = (uint4*)(As(buf) + sr * ROWB);                                  \
-    ra_[0 * 4 + sq] = pa0;                                                       \
-    ra_[1 * 4 + sq] = pa1;                                                       \
-    ra_[2 * 4 + sq] = pa2;                                                       \
-    ra_[3 * 4 + sq] = pa3;                                                       \
-    uint4 rh_, rl_, ih_, il_;                                                    \
-    split8v(gb0.x, gb0.z, gb1.x, gb1.z, gb2.x, gb2.z, gb3.x, gb3.z, rh_, rl_);   \
-    split8v(gb0.y, gb0.w, gb1.y, gb1.w, gb2.y, gb2.w, gb3.y, gb3.w, ih_, il_);   \
+    ra_[sq * 4 + 0] = pa0_##S;                                                   \
+    ra_[sq * 4 + 1] = pa1_##S;                                                   \
+    ra_[sq * 4 + 2] = pa2_##S;                                                   \
+    ra_[sq * 4 + 3] = pa3_##S;                                                   \
     uint4* rb_ = (uint4*)(Bs(buf) + sr * ROWB);                                  \
-    rb_[0 * 4 + sq] = rh_;                                                       \
-    rb_[1 * 4 + sq] = rl_;                                                       \
-    rb_[2 * 4 + sq] = ih_;                                                       \
-    rb_[3 * 4 + sq] = il_;                                                       \
+    rb_[sq * 4 + 0] = pb0_##S;                                                   \
+    rb_[sq * 4 + 1] = pb1_##S;                                                   \
+    rb_[sq * 4 + 2] = pb2_##S;                                                   \
+    rb_[sq * 4 + 3] = pb3_##S;                                                   \
   } while (0)
 
+  // one K slice from LDS stage `cur`: fragments lane -> (row/col l16 of the
+  // block, k-group lg); twelve MFMAs per block (four real products, three
+  // split terms each)
+#define COMPUTE(cur)                                                                \
+  do {                                                                              \
+    uint4 bf_[2][4];                                                                \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                 \
+      const uint4* src_ = (const uint4*)(Bs(cur) + (wc * 32 + j * 16 + l16) * ROWB); \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) bf_[j][q] = src_[lg * 4 + q];   \
+    }                                                                               \
+    uint4 nbh_[2], nbl_[2];                                                         \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                 \
+      nbh_[j] = negbf(bf_[j][2]);                                                   \
+      nbl_[j] = negbf(bf_[j][3]);                                                   \
+    }                                                                               \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                 \
+      const uint4* src_ = (const uint4*)(As(cur) + (wr * 64 + i * 16 + l16) * ROWB); \
+      const bf8 arh = as_bf8(src_[lg * 4 + 0]), arl = as_bf8(src_[lg * 4 + 1]);     \
+      const bf8 aih = as_bf8(src_[lg * 4 + 2]), ail = as_bf8(src_[lg * 4 + 3]);     \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j) {                               \
+        const bf8 brh = as_bf8(bf_[j][0]), brl = as_bf8(bf_[j][1]);                 \
+        const bf8 bih = as_bf8(bf_[j][2]), bil = as_bf8(bf_[j][3]);                 \
+        const bf8 nih = as_bf8(nbh_[j]), nil = as_bf8(nbl_[j]);                     \
+        f4 r = accR[i][j], m = accI[i][j];                                          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, m, 0, 0, 0);          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, m, 0, 0, 0);          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, m, 0, 0, 0);          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nih, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, m, 0, 0, 0);          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nil, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, m, 0, 0, 0);          \
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nih, r, 0, 0, 0);          \
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, m, 0, 0, 0);          \
+        accR[i][j] = r;                                                             \
+        accI[i][j] = m;                                                             \
+      }                                                                             \
+    }                                                                               \
+  } while (0)
+
+  // slices t0 .. t1-1; local slice u sits in LDS stage u & 1 and arrives in
+  // register set u & 1, loaded two slices earlier
   const int nk = (p.KG + 3) / 4;
-  if (nk > 0) {
-    GLOAD(0);
-    SSTORE(0);
+  const int t0 = kc * p.nks;
+  const int t1 = (t0 + p.nks < nk) ? t0 + p.nks : nk;
+  const int nloc = t1 - t0;
+  if (nloc > 0) {
+    GLOAD(t0, 0);
+    if (nloc > 1) GLOAD(t0 + 1, 1);
+    SSTORE(0, 0);
   }
   __syncthreads();
-  for (int t = 0; t < nk; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < nk) GLOAD(t + 1);
-    // fragments: lane -> (row/col l16 of the block, k-group lg)
-    uint4 bf[2][4];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const uint4* src = (const uint4*)(Bs(cur) + (wc * 32 + j * 16 + l16) * ROWB);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bf[j][q] = src[q * 4 + lg];
-    }
-    uint4 nbh[2], nbl[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      nbh[j] = negbf(bf[j][2]);
-      nbl[j] = negbf(bf[j][3]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint4* src = (const uint4*)(As(cur) + (wr * 64 + i * 16 + l16) * ROWB);
-      const bf8 arh = as_bf8(src[0 * 4 + lg]), arl = as_bf8(src[1 * 4 + lg]);
-      const bf8 aih = as_bf8(src[2 * 4 + lg]), ail = as_bf8(src[3 * 4 + lg]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const bf8 brh = as_bf8(bf[j][0]), brl = as_bf8(bf[j][1]);
-        const bf8 bih = as_bf8(bf[j][2]), bil = as_bf8(bf[j][3]);
-        const bf8 nih = as_bf8(nbh[j]), nil = as_bf8(nbl[j]);
-        f4 r = accR[i][j], m = accI[i][j];
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brh, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bih, m, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, brl, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bil, m, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, brh, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bih, m, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nih, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brh, m, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, nil, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, brl, m, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, nih, r, 0, 0, 0);
-        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, brh, m, 0, 0, 0);
-        accR[i][j] = r;
-        accI[i][j] = m;
-      }
-    }
-    if (t + 1 < nk) SSTORE(cur ^ 1);
+  for (int u = 0; u < nloc; u += 2) {
+    if (u + 2 < nloc) GLOAD(t0 + u + 2, 0);
+    COMPUTE(0);
+    if (u + 1 < nloc) SSTORE(1, 1);
+    __syncthreads();
+    if (u + 1 >= nloc) break;
+    if (u + 3 < nloc) GLOAD(t0 + u + 3, 1);
+    COMPUTE(1);
+    if (u + 2 < nloc) SSTORE(0, 0);
     __syncthreads();
   }
+#undef COMPUTE
 #undef GLOAD
 #undef SSTORE
   // D layout of v_mfma_f32_16x16x32_bf16: lane l, register r -> row 4 (l/16) + r, col l%16
+  if (p.splits > 1) {  // raw partial tile, [col][row] within the tile
+    zf* pt = p.part + ((int64_t)kc * p.tiles + tile) * (BM * BN);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int cl = wc * 32 + j * 16 + l16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rl = wr * 64 + i * 16 + 4 * lg + r;
+          pt[cl * BM + rl] = make_float2(accR[i][j][r], accI[i][j][r]);
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int col = col0 + wc * 32 + j * 16 + l16;
@@ -267,6 +278,77 @@ __global__ __launch_bounds__(NTHR, 1) void k_cgemm_bf16x3_filter(BfParams p) {
         p.D[row + (int64_t)col * p.ldd] = make_float2(vr, vi);
       }
   }
+}
+
+// Sum of the split-K partial tiles in split order, then the epilogue; one
+// thread per output element, consecutive threads on consecutive rows.
+__global__ __launch_bounds__(256) void k_bf16_splitk_reduce(BfParams p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t per = (int64_t)BM * BN;
+  if (e >= (int64_t)p.tiles * per) return;
+  const int tile = (int)(e / per);
+  const int w = (int)(e - (int64_t)tile * per);
+  const int cl = w / BM, rl = w - cl * BM;
+  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
+  const int row = tm * BM + rl, col = tn * BN + cl;
+  if (row >= p.M || col >= p.N) return;
+  float ar = 0.f, ai = 0.f;
+  for (int kc = 0; kc < p.splits; ++kc) {
+    const zf v = p.part[((int64_t)kc * p.tiles + tile) * per + w];
+    ar += v.x;
+    ai += v.y;
+  }
+  const float al = (float)p.alpha[col], be = (float)p.beta[col];
+  const float ga = (float)p.gamma[col], de = (float)p.delta[col];
+  const zf g = p.B[row + (int64_t)col * p.ldb];
+  float vr = al * ar + be * g.x, vi = al * ai + be * g.y;
+  if (ga != 0.f) {
+    const zf q = p.P[row + (int64_t)col * p.ldp];
+    vr += ga * q.x;
+    vi += ga * q.y;
+  }
+  if (de != 0.f) {
+    const zf q = p.R[row + (int64_t)col * p.ldr];
+    vr += de * q.x;
+    vi += de * q.y;
+  }
+  p.D[row + (int64_t)col * p.ldd] = make_float2(vr, vi);
+}
+
+// Planes of the columns of the FP32 complex iterate G (k rows): column c,
+// k-group g holds G(8g .. 8g+7, c) split into re hi/lo, im hi/lo (rows past
+// k are zero).
+__global__ __launch_bounds__(256) void k_split_cols_bf16(int k, int KG, int cols, const zf* G,
+                                                         int64_t ldg, uint4* planes) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)cols * KG) return;
+  const int c = (int)(e / KG), g = (int)(e - (int64_t)c * KG);
+  const zf* col = G + (int64_t)c * ldg;
+  const int k0 = g * 8;
+  float re[8], im[8];
+  if (k0 + 8 <= k) {
+    const float4* v = (const float4*)(col + k0);
+    const float4 v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+    re[0] = v0.x; im[0] = v0.y; re[1] = v0.z; im[1] = v0.w;
+    re[2] = v1.x; im[2] = v1.y; re[3] = v1.z; im[3] = v1.w;
+    re[4] = v2.x; im[4] = v2.y; re[5] = v2.z; im[5] = v2.w;
+    re[6] = v3.x; im[6] = v3.y; re[7] = v3.z; im[7] = v3.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const zf v = (k0 + q < k) ? col[k0 + q] : make_float2(0.f, 0.f);
+      re[q] = v.x;
+      im[q] = v.y;
+    }
+  }
+  uint4 rh, rl, ih, il;
+  split8(re, rh, rl);
+  split8(im, ih, il);
+  uint4* o = planes + e * 4;
+  o[0] = rh;
+  o[1] = rl;
+  o[2] = ih;
+  o[3] = il;
 }
 
 // Planes of the rows of the Hermitian C: row i, k-group g holds
@@ -310,11 +392,40 @@ gevp_status launch_split_rows_bf16(gevp_ctx* c, int64_t n, const zd* C, int64_t 
   return GEVP_OK;
 }
 
+namespace {
+constexpr int PART_TILES_MAX = 1024;  // partial tiles the workspace holds
+
+// K splits for T tiles of nk slices on `cus` compute units: minimise
+// rounds(T s) * ceil(nk / s) plus the reduction's traffic (about 1/40 of a
+// slice per partial tile), keeping at least 8 slices per part
+int choose_splits(int64_t T, int nk, int cus) {
+  int best = 1;
+  double best_cost = (double)((T + cus - 1) / cus) * nk;
+  for (int s = 2; s <= 8; ++s) {
+    const int nks = (nk + s - 1) / s;
+    if (nks < 8) break;
+    const int se = (nk + nks - 1) / nks;
+    if (T * se > PART_TILES_MAX) break;
+    const double cost = (double)((T * se + cus - 1) / cus) * nks + 0.025 * (double)(T * se) + 2.0;
+    if (cost < 0.95 * best_cost) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+}  // namespace
+
+size_t bf16_filter_work_bytes(int64_t k, int64_t cols) {
+  const int64_t KG = ((k + 31) / 32) * 4;
+  return ws_round((size_t)cols * KG * 64) + ws_round((size_t)PART_TILES_MAX * BM * BN * sizeof(zf));
+}
+
 gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_t k,
                                        const void* planes, const void* G, int64_t ldg,
                                        const void* P, int64_t ldp, const void* R, int64_t ldr,
                                        void* D, int64_t ldd, const double* al, const double* be,
-                                       const double* ga, const double* de) {
+                                       const double* ga, const double* de, void* work) {
   if (m <= 0 || n <= 0) return GEVP_OK;
   BfParams p;
   p.M = (int)m;
@@ -334,8 +445,25 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   p.beta = be;
   p.gamma = ga;
   p.delta = de;
+  char* wb = (char*)work;
+  uint4* bp = (uint4*)wb;
+  p.Bp = bp;
+  p.part = (zf*)(wb + ws_round((size_t)n * p.KG * 64));
+  // B planes
+  {
+    const int64_t items = n * (int64_t)p.KG;
+    hipLaunchKernelGGL(k_split_cols_bf16, dim3((unsigned)((items + 255) / 256)), dim3(256), 0,
+                       c->stream, (int)k, p.KG, (int)n, (const zf*)G, ldg, bp);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
   p.tiles_n = (int)((n + BN - 1) / BN);
-  const int64_t total = ((m + BM - 1) / BM) * p.tiles_n;
+  const int64_t tiles = ((m + BM - 1) / BM) * p.tiles_n;
+  const int nk = (p.KG + 3) / 4;
+  const int s = choose_splits(tiles, nk, gevp_device_cus(c->device));
+  p.nks = (nk + s - 1) / s;
+  p.splits = (nk + p.nks - 1) / p.nks;
+  p.tiles = (int)tiles;
+  const int64_t total = tiles * p.splits;
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
   const size_t shm = (size_t)2 * (BM + BN) * ROWB;
@@ -349,5 +477,11 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   (void)attr_set;
   hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(NTHR), shm, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
+  if (p.splits > 1) {
+    const int64_t elems = tiles * BM * BN;
+    hipLaunchKernelGGL(k_bf16_splitk_reduce, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,
+                       c->stream, p);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
   return GEVP_OK;
 }

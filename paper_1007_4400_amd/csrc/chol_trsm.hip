@@ -71,74 +71,206 @@ __device__ void reg_inverse_to(zd (*S)[NB], zd (*xrow)[NB], int n, zd* Dinv, int
 }
 
 // Factor the n x n (n <= 64) diagonal block at M (lower triangle read), write
-// L back (upper part of the block zeroed) and inv(L) to Dinv.  Right-looking
-// in registers: column j (current values) is broadcast through a
-// double-buffered column buffer, one barrier per column; the 1/l_jj scaling is
-// folded into the updates and applied at the end.  A non-positive or
-// non-finite pivot is recorded in *info (atomic min of the 1-based global
-// index) and replaced by 1 so the kernel always finishes.
+// L back (upper part of the block zeroed) and inv(L) to Dinv.
+//
+// Blocked right-looking in LDS with 16-wide panels.  Per panel: one wave
+// factors the 16 x 16 diagonal block and inverts it (lanes own a row and
+// four columns; a wave's LDS accesses are ordered, so no barrier is needed
+// inside), then all threads form the panel below as A21 inv(L11)^H and
+// update the trailing lower triangle.  inv(L) is then assembled block row by
+// block row from the diagonal inverses: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ.
+// Entries past n are the identity, so a ragged block needs no special case.
+// A non-positive or non-finite pivot is recorded in *info (atomic min of the
+// 1-based global index) and replaced by 1 so the kernel always finishes.
+constexpr int PB = 16;       // panel width
+constexpr int SLD = NB + 1;  // LDS column stride in complex entries (odd: rows spread over banks)
+constexpr size_t POTRF_LDS = 2 * sizeof(zd) * NB * SLD;
+
+__device__ __forceinline__ zd zmulc(zd a, zd b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
 __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, zd* Dinv,
                                                      int64_t ldi, int* info, int goff) {
-  __shared__ zd S[NB][NB];  // S[col][row]: the factor, for the inverse
-  __shared__ zd cb[2][NB];
-  __shared__ double piv[NB];
-  const int tid = threadIdx.x, i = tid & 63, kq = tid >> 6;
-  zd a[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int c = kq + 4 * m;
-    a[m] = (i < n && c < n && i >= c) ? M[i + (int64_t)c * ldm] : make_double2(0.0, 0.0);
+  extern __shared__ double potrf_lds[];
+  zd* S = reinterpret_cast<zd*>(potrf_lds);  // L, S[c * SLD + r]
+  zd* X = S + NB * SLD;                      // inv(L), same layout
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & (NB - 1), c = e >> 6;
+    zd v = make_double2(0.0, 0.0);
+    if (r < n && c < n) {
+      if (r >= c) v = M[r + (int64_t)c * ldm];
+    } else if (r == c) {
+      v = make_double2(1.0, 0.0);
+    }
+    S[c * SLD + r] = v;
+    X[c * SLD + r] = make_double2(0.0, 0.0);
   }
-  for (int j = 0; j < n; ++j) {
-    if (kq == (j & 3)) {
-      // a[j / 4] without a dynamic register index (keeps a[] out of scratch)
-      zd v = a[0];
+  __syncthreads();
+  for (int p0 = 0; p0 < NB; p0 += PB) {
+    if (wave == 0) {
+      // lane: row r of the diagonal block, columns cg + 4m (m = 0..3)
+      const int r = lane & 15, cg = lane >> 4;
+      for (int j = 0; j < PB; ++j) {
+        const int gj = p0 + j;
+        zd* colj = S + gj * SLD + p0;
+        double d = colj[j].x;
+        const bool bad = !(d > 0.0) || !isfinite(d);
+        if (bad) d = 1.0;
+        if (lane == 0 && bad && gj < n) atomicMin(info, goff + gj + 1);
+        const double ljj = sqrt(d), il = 1.0 / ljj;
+        if (cg == (j & 3)) {
+          if (r == j) {
+            colj[r] = make_double2(ljj, 0.0);
+          } else if (r > j) {
+            const zd v = colj[r];
+            colj[r] = make_double2(v.x * il, v.y * il);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const zd lr = colj[r];  // L(r, j)
 #pragma unroll
-      for (int m = 1; m < 16; ++m)
-        if (m == (j >> 2)) v = a[m];
-      cb[j & 1][i] = v;
+        for (int m = 0; m < 4; ++m) {
+          const int c = cg + 4 * m;
+          if (c > j && c <= r) {
+            const zd t = zmulc(lr, colj[c]);
+            zd* a = S + (p0 + c) * SLD + p0 + r;
+            const zd v = *a;
+            *a = make_double2(v.x - t.x, v.y - t.y);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      // inverse of the diagonal block: right-looking forward substitution on
+      // L11 X = I for the lane's four columns
+      zd x[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[m] = make_double2((cg + 4 * m == r) ? 1.0 : 0.0, 0.0);
+      for (int k = 0; k < PB; ++k) {
+        zd* colk = S + (p0 + k) * SLD + p0;
+        if (r == k) {
+          const double il = 1.0 / colk[k].x;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            x[m] = make_double2(x[m].x * il, x[m].y * il);
+            X[(p0 + cg + 4 * m) * SLD + p0 + k] = x[m];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (r > k) {
+          const zd lrk = colk[r];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const zd xk = X[(p0 + cg + 4 * m) * SLD + p0 + k];
+            const zd t = make_double2(lrk.x * xk.x - lrk.y * xk.y, lrk.x * xk.y + lrk.y * xk.x);
+            x[m] = make_double2(x[m].x - t.x, x[m].y - t.y);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
     }
     __syncthreads();
-    double d = cb[j & 1][j].x;
-    const bool badp = !(d > 0.0) || !isfinite(d);
-    if (badp) d = 1.0;
-    if (tid == 0) {
-      piv[j] = d;
-      if (badp) atomicMin(info, goff + j + 1);
-    }
-    const double id = 1.0 / d;  // 1 / l_jj^2
-    // a_ic -= a_ij conj(a_cj) / l_jj^2 for j < c <= i; unconditional loads,
-    // a 0/1 factor masks the update (no branch between the LDS reads)
-    const zd ci = cb[j & 1][i];
-    const double fi = (i > j && i < n) ? id : 0.0;
-    const zd cs = make_double2(ci.x * fi, ci.y * fi);
-    zd ck[16];
+    const int R = NB - p0 - PB;  // rows below the panel
+    if (R > 0) {
+      // L21 = A21 inv(L11)^H: entry (row, c) = sum_{k <= c} A21(row, k) conj(X11(c, k))
+      zd v[3];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) ck[m] = cb[j & 1][kq + 4 * m];
+      for (int q = 0; q < 3; ++q) {
+        const int e = tid + 256 * q;
+        v[q] = make_double2(0.0, 0.0);
+        if (e < R * PB) {
+          const int row = p0 + PB + e % R, c = e / R;
+          for (int k = 0; k <= c; ++k) {
+            const zd t = zmulc(S[(p0 + k) * SLD + row], X[(p0 + k) * SLD + p0 + c]);
+            v[q].x += t.x;
+            v[q].y += t.y;
+          }
+        }
+      }
+      __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int c = kq + 4 * m;
-      const double f = (c > j && c <= i) ? 1.0 : 0.0;
-      const double sr = cs.x * ck[m].x + cs.y * ck[m].y, si = cs.y * ck[m].x - cs.x * ck[m].y;
-      a[m].x -= f * sr;
-      a[m].y -= f * si;
+      for (int q = 0; q < 3; ++q) {
+        const int e = tid + 256 * q;
+        if (e < R * PB) S[(p0 + e / R) * SLD + p0 + PB + e % R] = v[q];
+      }
+      __syncthreads();
+      // trailing lower triangle: A22 -= L21 L21^H
+      for (int e = tid; e < R * R; e += 256) {
+        const int rr = p0 + PB + e % R, cc = p0 + PB + e / R;
+        if (rr < cc) continue;
+        zd acc = S[cc * SLD + rr];
+#pragma unroll 4
+        for (int k = 0; k < PB; ++k) {
+          const zd t = zmulc(S[(p0 + k) * SLD + rr], S[(p0 + k) * SLD + cc]);
+          acc.x -= t.x;
+          acc.y -= t.y;
+        }
+        S[cc * SLD + rr] = acc;
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
-  // scale and write L; keep it in S for the inverse
+  // off-diagonal blocks of inv(L), block row I = 1..3
+  for (int I = 1; I < NB / PB; ++I) {
+    // T_IJ = sum_{K=J}^{I-1} L_IK X_KJ, into X's block (I, J)
+    zd v[3];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int c = kq + 4 * m;
-    zd v = make_double2(0.0, 0.0);
-    if (i < n && c < n && i >= c) {
-      const double lc = sqrt(piv[c]);
-      v = (i == c) ? make_double2(lc, 0.0) : make_double2(a[m].x / lc, a[m].y / lc);
+    for (int q = 0; q < 3; ++q) {
+      const int e = tid + 256 * q;
+      v[q] = make_double2(0.0, 0.0);
+      if (e < I * PB * PB) {
+        const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
+        const int row = I * PB + r, col = J * PB + c;
+        for (int k = J * PB + c; k < I * PB; ++k) {  // X(k, col) = 0 for k < col
+          const zd l = S[k * SLD + row], xk = X[col * SLD + k];
+          v[q].x += l.x * xk.x - l.y * xk.y;
+          v[q].y += l.x * xk.y + l.y * xk.x;
+        }
+      }
     }
-    S[c][i] = v;
-    if (i < n && c < n) M[i + (int64_t)c * ldm] = v;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = tid + 256 * q;
+      if (e < I * PB * PB) {
+        const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
+        X[(J * PB + c) * SLD + I * PB + r] = v[q];
+      }
+    }
+    __syncthreads();
+    // X_IJ = -X_II T_IJ (X_II lower triangular)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = tid + 256 * q;
+      v[q] = make_double2(0.0, 0.0);
+      if (e < I * PB * PB) {
+        const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
+        const int row = I * PB + r, col = J * PB + c;
+        for (int k = 0; k <= r; ++k) {
+          const zd xi = X[(I * PB + k) * SLD + row], t = X[col * SLD + I * PB + k];
+          v[q].x -= xi.x * t.x - xi.y * t.y;
+          v[q].y -= xi.x * t.y + xi.y * t.x;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = tid + 256 * q;
+      if (e < I * PB * PB) {
+        const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
+        X[(J * PB + c) * SLD + I * PB + r] = v[q];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  reg_inverse_to(S, cb, n, Dinv, ldi);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & (NB - 1), c = e >> 6;
+    if (r < n && c < n) {
+      M[r + (int64_t)c * ldm] = (r >= c) ? S[c * SLD + r] : make_double2(0.0, 0.0);
+      Dinv[r + (int64_t)c * ldi] = (r >= c) ? X[c * SLD + r] : make_double2(0.0, 0.0);
+    }
+  }
 }
 
 // inverse of the n x n (n <= 64) lower-triangular block at L into Dinv
@@ -170,8 +302,14 @@ inline int64_t split64(int64_t n) { return ((n / 2 + NB - 1) / NB) * NB; }
 gevp_status chol_rec(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
                      int* info, int64_t goff) {
   if (n <= NB) {
-    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 0, c->stream, M, ldm, (int)n, Dinv,
-                       ldi, info, (int)goff);
+    static const bool attr = [] {
+      (void)hipFuncSetAttribute((const void*)k_potrf_block,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)POTRF_LDS);
+      return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), POTRF_LDS, c->stream, M, ldm, (int)n,
+                       Dinv, ldi, info, (int)goff);
     GEVP_HIP_TRY(hipGetLastError());
     return GEVP_OK;
   }

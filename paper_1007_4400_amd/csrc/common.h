@@ -30,6 +30,7 @@ typedef double2 zd;  // complex128 stored as (re, im)
   } while (0)
 
 int gevp_log_enabled();
+int gevp_device_cus(int device);  // compute units of a device (cached)
 
 struct gevp_ctx {
   int device = 0;
@@ -43,6 +44,9 @@ struct gevp_ctx {
   hipEvent_t* fev = nullptr;
   int fev_cap = 0;
   int fev_used = 0;
+  // split-K partial products of launch_zgemm (grown on demand, freed by destroy)
+  void* skw = nullptr;
+  size_t skw_bytes = 0;
   // per-stream sub-contexts of gevp_solve_batched (own stream and workspace)
   std::vector<gevp_ctx*> workers;
   bool owns_stream = false;
@@ -59,7 +63,8 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 // D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E   (FP64 MFMA, complex128)
 // When `coef` (device double[3]) is non-null it supplies alpha, beta, gamma.
 // lower = 1 computes only the 64 x 64 tiles that touch the lower triangle
-// (Hermitian updates whose upper triangle is never read).
+// (Hermitian updates whose upper triangle is never read).  Products with few
+// output tiles and a long K run split-K through c->skw (see zgemm.hip).
 gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
@@ -132,6 +137,7 @@ struct CtlParams {
   int nb, nev, deg_max, deg_init;
   int mode;         // 0: from Ritz data, 1: cold start, 2: Ritz data, residual-correction filter
   double u_target;  // mode 2: smallest per-sweep residual reduction worth aiming for
+  double margin;    // degrees aim at tol / margin (convergence is still tested at tol)
 };
 gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
                            const double* resid, const double* bounds, const double* norms,
@@ -156,7 +162,9 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
                                        const void* planes, const void* G, int64_t ldg,
                                        const void* P, int64_t ldp, const void* R, int64_t ldr,
                                        void* D, int64_t ldd, const double* al, const double* be,
-                                       const double* ga, const double* de);
+                                       const double* ga, const double* de, void* work);
+// workspace of launch_cgemm_bf16x3_filter for a k x k C and up to `cols` columns
+size_t bf16_filter_work_bytes(int64_t k, int64_t cols);
 gevp_status launch_add_correction32(gevp_ctx* c, int64_t rows, int64_t cols, const zd* Q,
                                     int64_t ldq, const int* perm, const void* G, int64_t ldg,
                                     zd* Y, int64_t ldy);

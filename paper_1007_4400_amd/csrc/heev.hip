@@ -483,8 +483,12 @@ __global__ void k_tri_norm(const double* d, const double* e, int n, double* out)
 }
 }  // namespace
 
+// work-groups of a tridiagonalisation step: one wave per trailing column
+// while n - 1 <= 4 G, at most one work-group per compute unit
+inline int trd_groups(int64_t n) { return (int)(n - 1 < 256 ? (n > 1 ? n - 1 : 1) : 256); }
+
 size_t heev_work_bytes(int64_t n) {
-  const int G = (int)(n < 128 ? (n > 1 ? n - 1 : 1) : 128);
+  const int G = trd_groups(n);
   size_t b = 0;
   b += ws_round(sizeof(zd) * n * n);          // V (reflectors)
   b += ws_round(sizeof(zd) * n);              // tau
@@ -501,7 +505,7 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   if (n64 <= 0) return GEVP_OK;
   if (n64 > 2048) return GEVP_ERR_INVALID;  // v_s and one column of Z must fit 64 KB of LDS
   const int n = (int)n64;
-  const int G = n < 128 ? (n > 1 ? n - 1 : 1) : 128;
+  const int G = trd_groups(n);
   char* w = (char*)work;
   auto take = [&](size_t bytes) {
     void* p = w;

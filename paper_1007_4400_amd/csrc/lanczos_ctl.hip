@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
           const double rho = fabs(t) + sqrt(t * t - 1.0);
           // reduction wanted this sweep; a low-precision filter (mode 2) cannot
           // beat its rounding floor, so it aims no further than u_target
-          double red = resid[i] / tol_abs;
+          double red = resid[i] * p.margin / tol_abs;
           if (p.mode == 2 && red * p.u_target > 1.0) red = 1.0 / p.u_target;
           const double need = log(red) / log(rho);
           m = (int)ceil(need) + 1;

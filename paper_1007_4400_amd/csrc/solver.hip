@@ -254,6 +254,7 @@ void gevp_destroy(gevp_handle h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->owns_stream) (void)hipStreamDestroy(h->stream);
   if (h->ws) (void)hipFree(h->ws);
+  if (h->skw) (void)hipFree(h->skw);
   for (int i = 0; i < h->fev_cap; ++i) (void)hipEventDestroy(h->fev[i]);
   delete[] h->fev;
   delete h;
@@ -325,6 +326,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   const size_t lp_elem = 8;                              // complex64
   if (mixed) {
     need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
+    if (bf16) need += bf16_filter_work_bytes(n, nb);     // iterate planes, split-K partials
     need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
     need += ws_round(sizeof(double) * nb);               // rho0
     need += ws_round(sizeof(double) * 4 * nb * (o.deg_max + 2));  // per-column coefficients
@@ -360,6 +362,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
   void* Clp = nullptr;
+  void* bfw = nullptr;  // split-BF16 filter workspace
   void* G0 = nullptr;
   void* G1 = nullptr;
   void* Rlp = nullptr;
@@ -367,6 +370,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* coef2 = nullptr;
   if (mixed) {
     Clp = ws_take(c, bf16 ? bf16_planes_bytes(n) : lp_elem * nn);
+    if (bf16) bfw = ws_take(c, bf16_filter_work_bytes(n, nb));
     G0 = ws_take(c, lp_elem * n * nb);
     G1 = ws_take(c, lp_elem * n * nb);
     Rlp = ws_take(c, lp_elem * n * nb);
@@ -437,7 +441,11 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // rounding floor of the filter products: FP32 products with FP32
   // accumulation over n terms, or split-BF16 products (about 2^-16 each)
   const double u_target = bf16 ? 1e-4 : 1e-6;
-  CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, u_target};
+  // the degree model is a first-order estimate: aiming a few times below tol
+  // lets the columns it slightly misjudges converge in the same sweep instead
+  // of costing another orthonormalisation and Rayleigh-Ritz round
+  const double margin = 4.0;
+  CtlParams cp{(int)nb, (int)nev, o.deg_max, o.deg_init, 0, u_target, margin};
   std::vector<int> hst(4 + 260);
   std::vector<double> hsd(16);
   int it = 0;
@@ -493,7 +501,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       if (bf16)
         GEVP_TRY(launch_cgemm_bf16x3_filter(c, n, cols, n, Clp, src, n, dst, n, rr, n, dst, n,
                                             row + s0, row + nb + s0, row + 2 * nb + s0,
-                                            row + 3 * nb + s0));
+                                            row + 3 * nb + s0, bfw));
       else
         GEVP_TRY(launch_cgemm32_filter(c, n, cols, n, Clp, n, src, n, dst, n, rr, n, dst, n,
                                        row + s0, row + nb + s0, row + 2 * nb + s0,
@@ -716,12 +724,14 @@ gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t 
   GEVP_HIP_TRY(hipSetDevice(h->device));
   const bool bf = precision == GEVP_BF16X3;
   const size_t bytes = bf ? bf16_planes_bytes(n) : (size_t)8 * n * n;
-  GEVP_TRY(ws_reserve(h, ws_round(bytes)));
+  const size_t wbytes = bf ? bf16_filter_work_bytes(n, m) : 0;
+  GEVP_TRY(ws_reserve(h, ws_round(bytes) + wbytes));
   void* planes = ws_take(h, bytes);
   if (bf) {
+    void* work = ws_take(h, wbytes);
     GEVP_TRY(launch_split_rows_bf16(h, n, (const zd*)C, ldc, planes));
     return launch_cgemm_bf16x3_filter(h, n, m, n, planes, G, ldg, P, ldp, R, ldr, D, ldd, alpha, beta,
-                                      gamma, delta);
+                                      gamma, delta, work);
   }
   GEVP_TRY(launch_to_c32(h, n, n, (const zd*)C, ldc, planes, n));
   return launch_cgemm32_filter(h, n, m, n, planes, n, G, ldg, P, ldp, R, ldr, D, ldd, alpha, beta,

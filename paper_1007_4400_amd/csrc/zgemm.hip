@@ -21,6 +21,8 @@
 //
 // The Chebyshev filter uses the epilogue with Cm = the B operand and E = the
 // previous iterate, coefficients read from device memory (`coef`).
+#include <atomic>
+
 #include "common.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -28,6 +30,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 namespace {
 constexpr int BM = 64, BN = 64, KT = 16, NTHR = 256;
 constexpr int PADA = BM + 1, PADB = BN + 1;
+constexpr int64_t SPLIT_TILES_MAX = 2048;  // partial tiles the split-K buffer holds (128 MiB)
 // The in-place base cases of the triangular solves rely on a 64-wide block
 // fitting in one output tile.
 static_assert(BM >= 64 && BN >= 64, "trsm base cases need 64-wide tiles");
@@ -49,9 +52,12 @@ struct ZgemmParams {
   double alpha, beta, gamma;
   const double* coef;
   int tiles_n;
+  int tiles;  // output tiles; blocks = tiles * splits
   int total;
   int remap;
   int lower;  // 1: only tiles that touch the lower triangle (row >= col) are computed
+  int splits, nks;  // K split in `splits` parts of nks slices
+  zd* part;         // splits > 1: raw partial tiles [split][tile][col][row]
 };
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
@@ -69,7 +75,8 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
     const int per = p.total >> 3;
     L = (L & 7) * per + (L >> 3);
   }
-  const int tm = L / p.tiles_n, tn = L - tm * p.tiles_n;
+  const int kc = L / p.tiles, tile = L - kc * p.tiles;
+  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   if (p.lower && col0 > row0 + BM - 1) return;  // tile strictly above the diagonal
 
@@ -148,14 +155,16 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
   } while (0)
 
   const int nk = (p.K + KT - 1) / KT;
-  if (nk > 0) {
-    LOAD_(0);
+  const int t0 = kc * p.nks;
+  const int t1 = (t0 + p.nks < nk) ? t0 + p.nks : nk;
+  if (t0 < t1) {
+    LOAD_(t0 * KT);
     STORE_(0);
   }
   __syncthreads();
-  for (int t = 0; t < nk; ++t) {
-    const int cur = t & 1;
-    if (t + 1 < nk) LOAD_((t + 1) * KT);
+  for (int t = t0; t < t1; ++t) {
+    const int cur = (t - t0) & 1;
+    if (t + 1 < t1) LOAD_((t + 1) * KT);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kk = ks * 4 + lg;
@@ -186,7 +195,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
         for (int j = 0; j < 2; ++j)
           accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
     }
-    if (t + 1 < nk) STORE_(cur ^ 1);
+    if (t + 1 < t1) STORE_(cur ^ 1);
     __syncthreads();
   }
 #undef LDA_
@@ -196,6 +205,19 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
 #undef STB_
 #undef STORE_
 
+  // D layout of v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, col l%16
+  if (p.splits > 1) {  // raw partial tile, [col][row] within the tile
+    zd* pt = p.part + ((int64_t)kc * p.tiles + tile) * (BM * BN);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          pt[(wc * 32 + j * 16 + l16) * BM + wr * 32 + i * 16 + lg + 4 * r] =
+              make_double2(accR[i][j][r], accI[i][j][r]);
+    return;
+  }
   double alpha = p.alpha, beta = p.beta, gamma = p.gamma;
   if (p.coef) {
     alpha = p.coef[0];
@@ -204,7 +226,6 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
   }
   const bool useC = (p.Cm != nullptr) && (beta != 0.0);
   const bool useE = (p.E != nullptr) && (gamma != 0.0);
-  // D layout of v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, col l%16
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -230,6 +251,66 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
         p.D[row + (int64_t)col * p.ldd] = make_double2(vr, vi);
       }
     }
+}
+
+// Split-K: sum of the partial tiles in split order, then the epilogue; one
+// thread per output element, consecutive threads on consecutive rows.
+__global__ __launch_bounds__(256) void k_zgemm_splitk_reduce(ZgemmParams p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t per = (int64_t)BM * BN;
+  if (e >= (int64_t)p.tiles * per) return;
+  const int tile = (int)(e / per);
+  const int w = (int)(e - (int64_t)tile * per);
+  const int cl = w / BM, rl = w - cl * BM;
+  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
+  const int row = tm * BM + rl, col = tn * BN + cl;
+  if (row >= p.M || col >= p.N) return;
+  if (p.lower && tn * BN > tm * BM + BM - 1) return;
+  double ar = 0.0, ai = 0.0;
+  for (int kc = 0; kc < p.splits; ++kc) {
+    const zd v = p.part[((int64_t)kc * p.tiles + tile) * per + w];
+    ar += v.x;
+    ai += v.y;
+  }
+  double alpha = p.alpha, beta = p.beta, gamma = p.gamma;
+  if (p.coef) {
+    alpha = p.coef[0];
+    beta = p.coef[1];
+    gamma = p.coef[2];
+  }
+  double vr = alpha * ar, vi = alpha * ai;
+  if (p.Cm != nullptr && beta != 0.0) {
+    const zd cv = p.Cm[row + (int64_t)col * p.ldc];
+    vr += beta * cv.x;
+    vi += beta * cv.y;
+  }
+  if (p.E != nullptr && gamma != 0.0) {
+    const double g = gamma * (p.gcol ? p.gcol[col] : 1.0);
+    const zd ev = p.E[row + (int64_t)col * p.lde];
+    vr += g * ev.x;
+    vi += g * ev.y;
+  }
+  p.D[row + (int64_t)col * p.ldd] = make_double2(vr, vi);
+}
+
+// K splits for T tiles of nk slices when `slots` work-groups run at once:
+// minimise rounds(T s) * ceil(nk / s) plus the reduction (about 1/100 of a
+// slice per partial tile), keeping at least 8 slices per part
+int zgemm_splits(int64_t T, int nk, int64_t slots, int64_t max_parts) {
+  int best = 1;
+  double best_cost = (double)((T + slots - 1) / slots) * nk;
+  for (int s = 2; s <= 16; ++s) {
+    const int nks = (nk + s - 1) / s;
+    if (nks < 8) break;
+    const int se = (nk + nks - 1) / nks;
+    if (T * se > max_parts) break;
+    const double cost = (double)((T * se + slots - 1) / slots) * nks + 0.01 * (double)(T * se) + 2.0;
+    if (cost < 0.95 * best_cost) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 }  // namespace
 
@@ -265,13 +346,56 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   const int64_t tiles_m = (m + BM - 1) / BM;
   const int64_t total = tiles_m * p.tiles_n;
   if (total > INT32_MAX) return GEVP_ERR_INVALID;
-  p.total = (int)total;
-  p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
+  p.tiles = (int)total;
   p.lower = lower;
+  const int nk = (p.K + KT - 1) / KT;
+  int s = zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
+  p.nks = nk > 0 ? (nk + s - 1) / s : 1;
+  p.splits = nk > 0 ? (nk + p.nks - 1) / p.nks : 1;
+  p.part = nullptr;
+  if (p.splits > 1) {
+    const size_t need = (size_t)p.splits * total * BM * BN * sizeof(zd);
+    if (need > c->skw_bytes) {
+      if (c->skw) {
+        GEVP_HIP_TRY(hipStreamSynchronize(c->stream));  // earlier launches may still read it
+        GEVP_HIP_TRY(hipFree(c->skw));
+        c->skw = nullptr;
+        c->skw_bytes = 0;
+      }
+      const size_t cap = (size_t)SPLIT_TILES_MAX * BM * BN * sizeof(zd);
+      if (hipMalloc(&c->skw, cap) != hipSuccess) {
+        c->skw = nullptr;
+        return GEVP_ERR_ALLOC;
+      }
+      c->skw_bytes = cap;
+    }
+    p.part = (zd*)c->skw;
+  }
+  const int64_t blocks = total * p.splits;
+  p.total = (int)blocks;
+  p.remap = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
   if (coef)
-    hipLaunchKernelGGL(k_zgemm<1>, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
+    hipLaunchKernelGGL(k_zgemm<1>, dim3((unsigned)blocks), dim3(NTHR), 0, c->stream, p);
   else
-    hipLaunchKernelGGL(k_zgemm<0>, dim3((unsigned)total), dim3(NTHR), 0, c->stream, p);
+    hipLaunchKernelGGL(k_zgemm<0>, dim3((unsigned)blocks), dim3(NTHR), 0, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
+  if (p.splits > 1) {
+    const int64_t elems = total * BM * BN;
+    hipLaunchKernelGGL(k_zgemm_splitk_reduce, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,
+                       c->stream, p);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
   return GEVP_OK;
+}
+
+int gevp_device_cus(int dev) {
+  static std::atomic<int> cache[64];
+  if (dev < 0 || dev >= 64) return 256;
+  int v = cache[dev].load();
+  if (v > 0) return v;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+    cu = 256;
+  cache[dev].store(cu);
+  return cu;
 }

@@ -30,7 +30,7 @@ def _np(t):
 
 
 @pytest.mark.parametrize("opA,opB", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
-@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (70, 45, 33), (130, 200, 257), (1, 3, 1)])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 16), (70, 45, 33), (130, 200, 257), (1, 3, 1), (200, 150, 4000)])
 def test_zgemm_ops(h, opA, opB, m, n, k):
     print(f"zgemm {opA}{opB} m={m} n={n} k={k}", flush=True)
     rng = np.random.default_rng(m * 1000 + n + k)
@@ -64,7 +64,7 @@ def test_zgemm_plain_and_inplace_beta(h):
     assert np.allclose(_np(Dd), C - A @ B, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333])
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333, 1000])
 def test_potrf(h, n):
     print(f"potrf n={n}", flush=True)
     rng = np.random.default_rng(n)
@@ -134,7 +134,7 @@ def test_heev_degenerate(h, oracle_mod):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16x3", 1e-4)])
-@pytest.mark.parametrize("n,m", [(64, 16), (200, 70), (333, 129), (520, 260)])
+@pytest.mark.parametrize("n,m", [(64, 16), (200, 70), (333, 129), (520, 260), (1100, 300)])
 def test_filter_gemm_low_precision(h, precision, tol, n, m):
     """One residual-correction filter step in low precision against the
     complex128 definition; the error bound is relative to the size of the
