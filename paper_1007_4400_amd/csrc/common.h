@@ -47,6 +47,8 @@ struct gevp_ctx {
   // split-K partial products of launch_zgemm (grown on demand, freed by destroy)
   void* skw = nullptr;
   size_t skw_bytes = 0;
+  // second stream of a seeded solve (own split-K buffer; created on demand)
+  gevp_ctx* aux = nullptr;
   // per-stream sub-contexts of gevp_solve_batched (own stream and workspace)
   std::vector<gevp_ctx*> workers;
   bool owns_stream = false;
@@ -63,13 +65,15 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 // D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E   (FP64 MFMA, complex128)
 // When `coef` (device double[3]) is non-null it supplies alpha, beta, gamma.
 // lower = 1 computes only the 64 x 64 tiles that touch the lower triangle
-// (Hermitian updates whose upper triangle is never read).  Products with few
+// (Hermitian updates whose upper triangle is never read).  upperA = 1 declares
+// op(A) upper triangular (e.g. L^H): each output row block skips the K range
+// below its first row.  Products with few
 // output tiles and a long K run split-K through c->skw (see zgemm.hip).
 gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef = nullptr, int lower = 0);
+                         const double* coef = nullptr, int lower = 0, int upperA = 0);
 
 // Recursive blocked Cholesky of the lower triangle; Dinv (n x 64 column-major,
 // ld = ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev

@@ -298,7 +298,8 @@ __device__ __forceinline__ uint64_t hmix(uint64_t z) {
 __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double* eg, int n,
                                                   const double* theta, double* U, double* Vv,
                                                   double* Ww, double* Lm, double* Sw, double* Zt,
-                                                  double tnorm) {
+                                                  const double* tnorm_dev) {
+  const double tnorm = *tnorm_dev;
   extern __shared__ double sm[];
   double* d = sm;
   double* e = sm + n;
@@ -311,8 +312,13 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
   if (j >= n) return;
   const double lam = theta[j];
   const double tiny = DBL_EPSILON * fmax(tnorm, DBL_MIN);
-  auto at = [&](double* A, int i) -> double& { return A[(int64_t)i * n + j]; };
-  // working row k: (al, be) on columns (k, k+1)
+  // thread j's entry k of an n x n work array; consecutive threads are
+  // consecutive addresses.  Every pass below keeps its recurrence in
+  // registers; the loads it needs do not depend on the recurrence and are
+  // issued IB steps at a time, so a pass costs n / IB memory latencies.
+  auto at = [&](double* A, int k) -> double& { return A[(int64_t)k * n + j]; };
+  constexpr int IB = 16;
+  // LU with partial pivoting of T - lam I; working row k: (al, be) on columns (k, k+1)
   double al = d[0] - lam, be = (n > 1) ? e[0] : 0.0;
   for (int k = 0; k < n - 1; ++k) {
     const double ck = e[k], an = d[k + 1] - lam, bn = (k + 1 < n - 1) ? e[k + 1] : 0.0;
@@ -345,43 +351,96 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
   }
   double nrm = 0.0;
   for (int it = 0; it < 2; ++it) {
-    for (int k = 0; k < n - 1; ++k) {
-      const double l = at(Lm, k);
-      const double yk = at(Zt, k), yk1 = at(Zt, k + 1);
-      if (at(Sw, k) != 0.0) {
-        at(Zt, k) = yk1;
-        at(Zt, k + 1) = yk - l * yk1;
-      } else {
-        at(Zt, k + 1) = yk1 - l * yk;
+    // forward: apply the row swaps and multipliers; c is the current y_k
+    double c = at(Zt, 0);
+    for (int k0 = 0; k0 < n - 1; k0 += IB) {
+      double lv[IB], sv[IB], av[IB];
+#pragma unroll
+      for (int q = 0; q < IB; ++q) {
+        const int k = k0 + q;
+        if (k < n - 1) {
+          lv[q] = at(Lm, k);
+          sv[q] = at(Sw, k);
+          av[q] = at(Zt, k + 1);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < IB; ++q) {
+        const int k = k0 + q;
+        if (k < n - 1) {
+          if (sv[q] != 0.0) {  // rows k, k+1 swapped
+            at(Zt, k) = av[q];
+            c = c - lv[q] * av[q];
+          } else {
+            at(Zt, k) = c;
+            c = av[q] - lv[q] * c;
+          }
+        }
       }
     }
+    at(Zt, n - 1) = c;
+    // backward: U x = y with U upper triangular, bandwidth 3
     double x1 = 0.0, x2 = 0.0, mx = 0.0;
-    for (int k = n - 1; k >= 0; --k) {
-      double y = at(Zt, k);
-      if (k + 1 < n) y -= at(Vv, k) * x1;
-      if (k + 2 < n) y -= at(Ww, k) * x2;
-      const double x = y / at(U, k);
-      at(Zt, k) = x;
-      x2 = x1;
-      x1 = x;
-      mx = fmax(mx, fabs(x));
+    for (int k0 = n - 1; k0 >= 0; k0 -= IB) {
+      double yv[IB], vv[IB], wv[IB], uv[IB];
+#pragma unroll
+      for (int q = 0; q < IB; ++q) {
+        const int k = k0 - q;
+        if (k >= 0) {
+          yv[q] = at(Zt, k);
+          vv[q] = at(Vv, k);
+          wv[q] = at(Ww, k);
+          uv[q] = at(U, k);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < IB; ++q) {
+        const int k = k0 - q;
+        if (k >= 0) {
+          double y = yv[q];
+          if (k + 1 < n) y -= vv[q] * x1;
+          if (k + 2 < n) y -= wv[q] * x2;
+          const double x = y / uv[q];
+          at(Zt, k) = x;
+          x2 = x1;
+          x1 = x;
+          mx = fmax(mx, fabs(x));
+        }
+      }
     }
     const double sc = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
     nrm = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = at(Zt, i) * sc;
-      at(Zt, i) = v;
-      nrm += v * v;
+    for (int k0 = 0; k0 < n; k0 += IB) {
+      double zv[IB];
+#pragma unroll
+      for (int q = 0; q < IB; ++q)
+        if (k0 + q < n) zv[q] = at(Zt, k0 + q);
+#pragma unroll
+      for (int q = 0; q < IB; ++q)
+        if (k0 + q < n) {
+          const double v = zv[q] * sc;
+          at(Zt, k0 + q) = v;
+          nrm += v * v;
+        }
     }
   }
   const double inv = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
-  for (int i = 0; i < n; ++i) at(Zt, i) *= inv;
+  for (int k0 = 0; k0 < n; k0 += IB) {
+    double zv[IB];
+#pragma unroll
+    for (int q = 0; q < IB; ++q)
+      if (k0 + q < n) zv[q] = at(Zt, k0 + q);
+#pragma unroll
+    for (int q = 0; q < IB; ++q)
+      if (k0 + q < n) at(Zt, k0 + q) = zv[q] * inv;
+  }
 }
 
 // Modified Gram-Schmidt inside clusters of (numerically) equal eigenvalues:
 // work-group b handles the cluster that starts at index b (if any).
 __global__ __launch_bounds__(HT) void k_tri_cluster_mgs(const double* theta, int n, double* Zt,
-                                                        double ctol) {
+                                                        const double* tnorm_dev) {
+  const double ctol = 1e3 * DBL_EPSILON * fmax(*tnorm_dev, 1e-300);
   __shared__ double sh[4];
   const int b = blockIdx.x;
   if (b >= n) return;
@@ -561,14 +620,10 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   GEVP_HIP_TRY(hipGetLastError());
   // ||T|| is needed on the host only as a scale for the zero-pivot guard and
   // the cluster tolerance; read it back (one small synchronous copy).
-  double tnorm = 0.0;
-  GEVP_HIP_TRY(hipMemcpyAsync(&tnorm, tn, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
   hipLaunchKernelGGL(k_tri_invit, dim3((n + 63) / 64), dim3(64), sizeof(double) * 2 * n, c->stream,
-                     a.d, a.e, n, theta, U, Vv, Ww, Lm, Sw, Zt, tnorm);
+                     a.d, a.e, n, theta, U, Vv, Ww, Lm, Sw, Zt, tn);
   GEVP_HIP_TRY(hipGetLastError());
-  const double ctol = 1e3 * DBL_EPSILON * fmax(tnorm, 1e-300);
-  hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, ctol);
+  hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, tn);
   GEVP_HIP_TRY(hipGetLastError());
   const unsigned tb = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);

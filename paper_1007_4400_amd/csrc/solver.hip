@@ -130,7 +130,8 @@ struct QrWork {
 // step with an unchanged overlap): if the first Gram matrix is the identity
 // to 5e-13, no factorisation is needed.
 gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWork& w,
-                    int* fallbacks, bool try_skip = false) {
+                    int* fallbacks, bool try_skip = false, bool* skipped = nullptr) {
+  if (skipped) *skipped = false;
   for (int pass = 0; pass < 2; ++pass) {
     GEVP_TRY(launch_colnorm_scale(c, n, m, P, ldp));
     GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
@@ -140,7 +141,10 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
       GEVP_TRY(launch_max_offident(c, m, w.G, m, w.shift + 1));
       GEVP_HIP_TRY(hipMemcpyAsync(&dev, w.shift + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
-      if (dev <= 5e-13) return GEVP_OK;
+      if (dev <= 5e-13) {
+        if (skipped) *skipped = true;
+        return GEVP_OK;
+      }
     }
     const int big = 0x7fffffff;
     GEVP_HIP_TRY(hipMemcpyAsync(w.flag, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -251,6 +255,8 @@ void gevp_destroy(gevp_handle h) {
   (void)hipSetDevice(h->device);
   for (gevp_ctx* w : h->workers) gevp_destroy(w);
   h->workers.clear();
+  if (h->aux) gevp_destroy(h->aux);
+  h->aux = nullptr;
   (void)hipStreamSynchronize(h->stream);
   if (h->owns_stream) (void)hipStreamDestroy(h->stream);
   if (h->ws) (void)hipFree(h->ws);
@@ -264,6 +270,37 @@ int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev) {
   if (n < 1 || nev < 1 || nev > n) return 0;
   return block_of(resolve(opts, nev), n, nev);
 }
+
+namespace {
+// the handle's second stream (non-blocking, default priority), created once
+gevp_status aux_ctx(gevp_ctx* c, gevp_ctx** out) {
+  if (!c->aux) {
+    gevp_ctx* w = new gevp_ctx();
+    w->device = c->device;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return GEVP_ERR_HIP;
+    }
+    w->owns_stream = true;
+    c->aux = w;
+  }
+  *out = c->aux;
+  return GEVP_OK;
+}
+
+// Fork/join events of the second stream.  Every exit from the solve, early
+// error returns included, waits for the second stream's work first: it reads
+// the caller's X0 and writes workspace the next call reuses.
+struct EventPair {
+  hipEvent_t fork = nullptr, join = nullptr;
+  bool joined_needed = false;
+  ~EventPair() {
+    if (joined_needed) (void)hipEventSynchronize(join);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+};
+}  // namespace
 
 gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const void* A_,
                        int64_t lda, const void* B_, int64_t ldb, const void* X0_, int64_t ldx0,
@@ -390,6 +427,37 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (seeded) GEVP_TRY(launch_check_finite(c, n, k0, X0, ldx0, flags));
   tm.stop(info, GEVP_STAGE_STAGE);
 
+  // A full seed block X0 is B-orthonormal when the overlap matrix has not
+  // changed; then its Rayleigh-Ritz projection needs no reduced matrix:
+  // (L^H X0)^H C (L^H X0) = X0^H A X0.  The projection and its eigensolve run
+  // on a second stream while B is factored and A reduced; the result is used
+  // if the orthonormality test of L^H X0 at the first iteration passes (the
+  // usual path runs otherwise).  The second stream writes only T, Hs, Zs,
+  // theta and the eigensolver workspace, which the main stream does not touch
+  // before the join.
+  const bool spec = seeded && k0 >= nb;
+  EventPair evs;
+  if (spec) {
+    gevp_ctx* ax = nullptr;
+    GEVP_TRY(aux_ctx(c, &ax));
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventRecord(evs.fork, c->stream));
+    GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.fork, 0));
+    auto seed_rr = [&]() -> gevp_status {
+      GEVP_TRY(launch_zgemm(ax, 0, 0, n, nb, n, 1.0, Af, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr,
+                            0, nullptr, T, n));
+      GEVP_TRY(launch_zgemm(ax, 1, 0, nb, nb, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr,
+                            0, nullptr, Hs, nb));
+      GEVP_TRY(launch_symmetrize(ax, nb, Hs, nb));
+      return heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw);
+    };
+    const gevp_status sst = seed_rr();
+    GEVP_HIP_TRY(hipEventRecord(evs.join, ax->stream));
+    evs.joined_needed = true;
+    GEVP_TRY(sst);
+  }
+
   // ---------------- Cholesky of B
   tm.start();
   GEVP_TRY(launch_copy2d(c, n, n, Bf, n, L, n));
@@ -431,7 +499,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (seeded) {
     // C-space seed: y = L^H x
     GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, P0, n));
+                          nullptr, P0, n, nullptr, 0, 1));
   }
   const int64_t kseed = seeded ? k0 : 0;
   GEVP_TRY(launch_randn(c, n, nb - kseed, P0 + kseed * n, n, kseed, o.seed));
@@ -526,19 +594,29 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   cp.mode = mixed ? 2 : 0;
   for (it = 0; it < o.maxit; ++it) {
     tm.start();
-    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, seeded && it == 0 && k0 >= nb));
+    bool skipped = false;
+    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, spec && it == 0, &skipped));
+    if (spec && it == 0) GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evs.join, 0));
     tm.stop(info, GEVP_STAGE_QR);
     tm.start();
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, W, n));
-    GEVP_TRY(launch_zgemm(c, 1, 0, nb, nb, n, 1.0, P0, n, W, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, Hs, nb));
-    GEVP_TRY(launch_symmetrize(c, nb, Hs, nb));
-    GEVP_TRY(heev_small(c, nb, Hs, nb, theta, Zs, nb, heevw));
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, P1, n));
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, W, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, T, n));
+    if (spec && it == 0 && skipped) {
+      // Ritz pairs of the seed from the second stream: rotate the basis, then W = C P
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr,
+                            0, nullptr, P1, n));
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P1, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, T, n));
+    } else {
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, W, n));
+      GEVP_TRY(launch_zgemm(c, 1, 0, nb, nb, n, 1.0, P0, n, W, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, Hs, nb));
+      GEVP_TRY(launch_symmetrize(c, nb, Hs, nb));
+      GEVP_TRY(heev_small(c, nb, Hs, nb, theta, Zs, nb, heevw));
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr,
+                            0, nullptr, P1, n));
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, W, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, T, n));
+    }
     std::swap(P0, P1);
     std::swap(W, T);
     GEVP_TRY(launch_resid_cols(c, n, nb, W, n, P0, n, theta, rres));

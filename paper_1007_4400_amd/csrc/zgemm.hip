@@ -56,6 +56,7 @@ struct ZgemmParams {
   int total;
   int remap;
   int lower;  // 1: only tiles that touch the lower triangle (row >= col) are computed
+  int upperA;       // op(A) upper triangular: slices below the tile's first row are zero
   int splits, nks;  // K split in `splits` parts of nks slices
   zd* part;         // splits > 1: raw partial tiles [split][tile][col][row]
 };
@@ -155,8 +156,9 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
   } while (0)
 
   const int nk = (p.K + KT - 1) / KT;
-  const int t0 = kc * p.nks;
+  int t0 = kc * p.nks;
   const int t1 = (t0 + p.nks < nk) ? t0 + p.nks : nk;
+  if (p.upperA && row0 / KT > t0) t0 = row0 / KT;
   if (t0 < t1) {
     LOAD_(t0 * KT);
     STORE_(0);
@@ -318,7 +320,7 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef, int lower) {
+                         const double* coef, int lower, int upperA) {
   if (m <= 0 || n <= 0) return GEVP_OK;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return GEVP_ERR_INVALID;
   ZgemmParams p;
@@ -349,7 +351,9 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.tiles = (int)total;
   p.lower = lower;
   const int nk = (p.K + KT - 1) / KT;
-  int s = zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
+  p.upperA = upperA;
+  int s = upperA ? 1
+                 : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
   p.nks = nk > 0 ? (nk + s - 1) / s : 1;
   p.splits = nk > 0 ? (nk + p.nks - 1) / p.nks : 1;
   p.part = nullptr;
