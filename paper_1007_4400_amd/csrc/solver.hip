@@ -293,9 +293,9 @@ gevp_status aux_ctx(gevp_ctx* c, gevp_ctx** out) {
 // the caller's X0 and writes workspace the next call reuses.
 struct EventPair {
   hipEvent_t fork = nullptr, join = nullptr;
-  bool joined_needed = false;
+  hipStream_t second = nullptr;  // set once work is queued on the second stream
   ~EventPair() {
-    if (joined_needed) (void)hipEventSynchronize(join);
+    if (second) (void)hipStreamSynchronize(second);
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
   }
@@ -352,7 +352,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += 3 * ws_round(sizeof(zd) * nb * nb);            // H, Z, G
   need += ws_round(sizeof(zd) * nb * 64);                // DinvG
   need += heev_work_bytes(nb);
-  need += lanczos_work_bytes(n, lz);
+  need += 2 * lanczos_work_bytes(n, lz);                 // main and second stream
   need += 3 * ws_round(sizeof(double) * 8);              // bounds C, A, B
   need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, negl, spare
   need += ws_round(sizeof(int) * nb);                    // perm
@@ -384,6 +384,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   zd* DinvG = (zd*)ws_take(c, sizeof(zd) * nb * 64);
   void* heevw = ws_take(c, heev_work_bytes(nb));
   void* lanw = ws_take(c, lanczos_work_bytes(n, lz));
+  void* lanw2 = ws_take(c, lanczos_work_bytes(n, lz));
   double* bC = (double*)ws_take(c, sizeof(double) * 8);
   double* bA = (double*)ws_take(c, sizeof(double) * 8);
   double* bB = (double*)ws_take(c, sizeof(double) * 8);
@@ -429,32 +430,38 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   // A full seed block X0 is B-orthonormal when the overlap matrix has not
   // changed; then its Rayleigh-Ritz projection needs no reduced matrix:
-  // (L^H X0)^H C (L^H X0) = X0^H A X0.  The projection and its eigensolve run
-  // on a second stream while B is factored and A reduced; the result is used
-  // if the orthonormality test of L^H X0 at the first iteration passes (the
-  // usual path runs otherwise).  The second stream writes only T, Hs, Zs,
-  // theta and the eigensolver workspace, which the main stream does not touch
-  // before the join.
+  // (L^H X0)^H C (L^H X0) = X0^H A X0.  The projection, its eigensolve and
+  // the norm estimates of A and B run on a second stream while B is factored
+  // and A reduced.  The projection is used if the orthonormality test of
+  // L^H X0 at the first iteration passes (the usual path runs otherwise).  The second stream writes only T, Hs,
+  // Zs, theta, norms, its Lanczos workspace and the eigensolver workspace,
+  // none of which the main stream touches before the join.
   const bool spec = seeded && k0 >= nb;
+  const int lzn = lz > 12 ? 12 : lz;  // norm estimates need fewer steps than the filter bound
+  const double frac = std::min(1.0, (double)nb / (double)n);
   EventPair evs;
+  gevp_ctx* ax = nullptr;
   if (spec) {
-    gevp_ctx* ax = nullptr;
     GEVP_TRY(aux_ctx(c, &ax));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventRecord(evs.fork, c->stream));
     GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.fork, 0));
-    auto seed_rr = [&]() -> gevp_status {
+    evs.second = ax->stream;
+    auto second = [&]() -> gevp_status {
       GEVP_TRY(launch_zgemm(ax, 0, 0, n, nb, n, 1.0, Af, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, T, n));
       GEVP_TRY(launch_zgemm(ax, 1, 0, nb, nb, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, Hs, nb));
       GEVP_TRY(launch_symmetrize(ax, nb, Hs, nb));
-      return heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw);
+      GEVP_TRY(heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw));
+      GEVP_TRY(lanczos_bounds(ax, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw2));
+      GEVP_TRY(lanczos_bounds(ax, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw2));
+      GEVP_TRY(launch_copy_real(ax, 1, bA + 5, norms));
+      return launch_copy_real(ax, 1, bB + 5, norms + 1);
     };
-    const gevp_status sst = seed_rr();
+    const gevp_status sst = second();
     GEVP_HIP_TRY(hipEventRecord(evs.join, ax->stream));
-    evs.joined_needed = true;
     GEVP_TRY(sst);
   }
 
@@ -485,14 +492,13 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   // ---------------- bounds
   tm.start();
-  const double frac = std::min(1.0, (double)nb / (double)n);
   GEVP_TRY(lanczos_bounds(c, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw));
-  // norm estimates need fewer steps than the filter's upper bound
-  const int lzn = lz > 12 ? 12 : lz;
-  GEVP_TRY(lanczos_bounds(c, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw));
-  GEVP_TRY(lanczos_bounds(c, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw));
-  GEVP_TRY(launch_copy_real(c, 1, bA + 5, norms));
-  GEVP_TRY(launch_copy_real(c, 1, bB + 5, norms + 1));
+  if (!spec) {
+    GEVP_TRY(lanczos_bounds(c, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw));
+    GEVP_TRY(lanczos_bounds(c, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw));
+    GEVP_TRY(launch_copy_real(c, 1, bA + 5, norms));
+    GEVP_TRY(launch_copy_real(c, 1, bB + 5, norms + 1));
+  }
   tm.stop(info, GEVP_STAGE_BOUNDS);
 
   // ---------------- initial block
