@@ -81,6 +81,36 @@ def _mark_pop():
 FILTER_KERNELS = {"fp64": "k_zgemm<1>", "fp32": "k_cgemm32_filter", "bf16x3": "k_cgemm_bf16x3_filter"}
 
 
+KERNEL_SOURCES = {"k_cgemm_bf16x3_filter": "paper_1007_4400_amd/csrc/cgemm_bf16.hip",
+                  "k_cgemm32_filter": "paper_1007_4400_amd/csrc/cgemm32.hip",
+                  "k_zgemm<1>": "paper_1007_4400_amd/csrc/zgemm.hip"}
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_n8192_nev820_seq12_hbm_counters.txt), or None when
+    there is none or the kernel's source has changed since the counters were
+    taken (the summary records the source's SHA-256)."""
+    import hashlib
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    prof = os.path.join(here, "profiles", f"{kernel}_n8192_nev820_seq12_hbm_counters.txt")
+    src = KERNEL_SOURCES.get(kernel)
+    if not src or not os.path.exists(prof):
+        return None
+    with open(os.path.join(here, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    vals = {}
+    with open(prof) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def _regions(cur):
     """{message: (start, end)} of the roctx ranges in a rocprofv3 database."""
     out = {}
@@ -97,7 +127,7 @@ def _regions(cur):
     return out
 
 
-def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="timed"):
+def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="timed", pmc_last=0):
     """Text summary of a rocprofv3 database: per-kernel totals from a
     --kernel-trace run, the filter kernel's launches inside the roctx range
     'timed' (the launches bench.py times with HIP events), and, for a --pmc
@@ -138,6 +168,17 @@ def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="time
     for kname, cname, val, cnt in pmc:
         if kernel_substr in kname:
             lines.append(f"pmc {cname} avg per dispatch {val:.1f} KiB (x{cnt})  {kname[:80]}")
+    if pmc and pmc_last > 0:
+        # the last pmc_last dispatches of the kernel: the launches of the
+        # timed steps (a --pmc run cannot carry the marker range)
+        for cname in sorted({r[1] for r in pmc}):
+            vals = [v for (v,) in cur.execute(
+                "select value from counters_collection where kernel_name like ? and counter_name = ? "
+                "order by start", ("%" + kernel_substr + "%", cname)).fetchall()]
+            tail = vals[-pmc_last:]
+            if tail:
+                lines.append(f"pmc {cname} avg per dispatch over the last {len(tail)} (timed) "
+                             f"{sum(tail) / len(tail):.1f} KiB")
     if pmc:
         # the calibration copy (1 GiB read, 1 GiB written) is the largest
         # device copy of the run
@@ -233,11 +274,14 @@ def main():
     ap.add_argument("--summary-kernel", default=None, help="kernel name for --rocprof-summary")
     ap.add_argument("--host-qr", action="store_true",
                     help="factor the generator's Gaussian matrix on the host (for counter runs)")
+    ap.add_argument("--pmc-last", type=int, default=0,
+                    help="with --rocprof-summary: average counters over the kernel's last N dispatches")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.rocprof_summary:
-        print(rocprof_summary(args.rocprof_summary, args.summary_kernel or FILTER_KERNELS[args.precision]))
+        print(rocprof_summary(args.rocprof_summary, args.summary_kernel or FILTER_KERNELS[args.precision],
+                              pmc_last=args.pmc_last))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus above 1 is not supported "
@@ -376,7 +420,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak if peak else None,
-            "traffic": None,
+            "traffic": committed_traffic(kname),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
             "launches": filt_launches,
             "avg_launch_ms": filt_ms / max(filt_launches, 1),
             "flops_per_launch": filt_flops / max(filt_launches, 1),

@@ -475,8 +475,10 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
     return true;
   }();
   (void)attr_set;
+  GEVP_TRY(fev_mark(c));
   hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(NTHR), shm, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
+  GEVP_TRY(fev_mark(c));
   if (p.splits > 1) {
     const int64_t elems = tiles * BM * BN;
     hipLaunchKernelGGL(k_bf16_splitk_reduce, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,

@@ -30,6 +30,8 @@ typedef double2 zd;  // complex128 stored as (re, im)
   } while (0)
 
 int gevp_log_enabled();
+// event pair around one filter product kernel (profiling bit 2), see solver.hip
+gevp_status fev_mark(gevp_ctx* c);
 int gevp_device_cus(int device);  // compute units of a device (cached)
 
 struct gevp_ctx {

@@ -55,6 +55,23 @@ void* ws_take(gevp_ctx* c, size_t bytes) {
   return p;
 }
 
+// Event pair around one filter product kernel (profiling flag 2); the pool
+// grows on demand and is summed after the solve's final synchronisation.
+gevp_status fev_mark(gevp_ctx* c) {
+  if (!(c->profiling & 2)) return GEVP_OK;
+  if (c->fev_used == c->fev_cap) {
+    const int cap = c->fev_cap ? 2 * c->fev_cap : 512;
+    hipEvent_t* nv = new hipEvent_t[cap];
+    for (int i = 0; i < c->fev_cap; ++i) nv[i] = c->fev[i];
+    for (int i = c->fev_cap; i < cap; ++i) GEVP_HIP_TRY(hipEventCreate(&nv[i]));
+    delete[] c->fev;
+    c->fev = nv;
+    c->fev_cap = cap;
+  }
+  GEVP_HIP_TRY(hipEventRecord(c->fev[c->fev_used++], c->stream));
+  return GEVP_OK;
+}
+
 namespace {
 
 struct Opts {
@@ -171,23 +188,6 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
     }
     GEVP_TRY(trsm_right_lower_c(c, m, n, w.G, m, w.Dg, m, P, ldp));
   }
-  return GEVP_OK;
-}
-
-// Event pair around one filter launch (profiling bit 1); the pool grows on
-// demand and is summed after the solve's final synchronisation.
-gevp_status fev_mark(gevp_ctx* c) {
-  if (!(c->profiling & 2)) return GEVP_OK;
-  if (c->fev_used == c->fev_cap) {
-    const int cap = c->fev_cap ? 2 * c->fev_cap : 512;
-    hipEvent_t* nv = new hipEvent_t[cap];
-    for (int i = 0; i < c->fev_cap; ++i) nv[i] = c->fev[i];
-    for (int i = c->fev_cap; i < cap; ++i) GEVP_HIP_TRY(hipEventCreate(&nv[i]));
-    delete[] c->fev;
-    c->fev = nv;
-    c->fev_cap = cap;
-  }
-  GEVP_HIP_TRY(hipEventRecord(c->fev[c->fev_used++], c->stream));
   return GEVP_OK;
 }
 
@@ -571,16 +571,17 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       char* src = (char*)F[st & 1] + lp_elem * s0 * n;
       char* dst = (char*)F[(st + 1) & 1] + lp_elem * s0 * n;
       char* rr = (char*)Rlp + lp_elem * s0 * n;
-      GEVP_TRY(fev_mark(c));
-      if (bf16)
+      if (bf16) {  // the launcher brackets its product kernel with the event pair
         GEVP_TRY(launch_cgemm_bf16x3_filter(c, n, cols, n, Clp, src, n, dst, n, rr, n, dst, n,
                                             row + s0, row + nb + s0, row + 2 * nb + s0,
                                             row + 3 * nb + s0, bfw));
-      else
+      } else {
+        GEVP_TRY(fev_mark(c));
         GEVP_TRY(launch_cgemm32_filter(c, n, cols, n, Clp, n, src, n, dst, n, rr, n, dst, n,
                                        row + s0, row + nb + s0, row + 2 * nb + s0,
                                        row + 3 * nb + s0));
-      GEVP_TRY(fev_mark(c));
+        GEVP_TRY(fev_mark(c));
+      }
     }
     GEVP_TRY(launch_add_correction32(c, n, nb, P0, n, perm, G0, n, P1, n));
     std::swap(P0, P1);
