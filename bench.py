@@ -348,8 +348,10 @@ def main():
     torch.cuda.synchronize()
     _mark_push("timed")
     t_start = time.perf_counter()
+    Xprev_last = None
     for k in range(args.warmup, nsteps):
         ts = time.perf_counter()
+        Xprev_last = X
         lam, X, info = solve(As[k], X, opts)
         per_step.append(time.perf_counter() - ts)
         infos.append(info)
@@ -388,6 +390,28 @@ def main():
         del An, Bn
     except Exception as e:  # the check is reported, never silently skipped
         parity["oracle_pair_check_error"] = repr(e)
+
+    # seed monitor (untimed): principal-angle RMS sine and deviation angles of
+    # the last step's result against its seed, and what the monitor adds to
+    # a seeded solve (best of two solves each way)
+    monitor = {}
+    try:
+        X0m = Xprev_last
+        om = gevp.make_opts(precision=args.precision, seed_monitor=True)
+        t_on, t_off = [], []
+        for _ in range(2):
+            for o_, acc in ((om, t_on), (opts, t_off)):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                _, _, _, inf_m = h.solve(As[-1], B, wl.nev, X0=X0m, tol=args.tol, kx=kx, opts=o_)
+                torch.cuda.synchronize()
+                acc.append(time.perf_counter() - ts)
+                if o_ is om:
+                    monitor = {k_: inf_m[k_] for k_ in ("seed_sin_rms", "seed_dev_mean", "seed_dev_max",
+                                                         "seed_reindexed")}
+        monitor["added_ms"] = (min(t_on) - min(t_off)) * 1e3
+    except Exception as e:  # reported, never silently skipped
+        monitor = {"error": repr(e)}
 
     filt_ms = sum(i["filter_kernel_ms"] for i in infos)
     filt_flops = sum(i["filter_flops"] for i in infos)
@@ -434,6 +458,7 @@ def main():
         "speedup_vs_cold_fp64": cold_mean / value if value > 0 else None,
         "per_step_s": per_step,
         "parity": parity,
+        "seed_monitor": monitor,
     }
     if not args.no_cpu_baseline:
         try:

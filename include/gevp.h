@@ -71,7 +71,9 @@ typedef struct {
   unsigned long long seed;  /* random fill of non-seeded columns */
   int skip_final_residual;  /* 1: skip the original-basis residual check */
   int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 4 */
-  int reserved[7];
+  int seed_monitor;         /* 1: with a seed X0, report how it relates to the result
+                               (gevp_info seed_*; needs the final residual check) */
+  int reserved[6];
 } gevp_opts;
 
 /* Diagnostics, filled on return when a non-NULL pointer is passed. */
@@ -88,6 +90,19 @@ typedef struct {
   double ms[8];           /* stage times (ms), profiling bit 0: see gevp_stage */
   double filter_kernel_ms;  /* summed duration of the filter GEMM launches, profiling bit 1 */
   int64_t filter_launches;  /* number of those launches */
+  /* Seed monitor (opts.seed_monitor, seeded solves; section 2, paragraph
+     "Eigenvectors evolution": how far eigenvectors move between SCF steps).
+     With k = min(nev, k0) and M = X0(:, :k)^H B X(:, :k) (both blocks
+     B-orthonormal, so the singular values of M are the cosines of the
+     principal angles between the two spans):
+       seed_sin_rms   = sqrt(max(0, k - ||M||_F^2) / k), the RMS sine of those angles;
+       seed_dev_mean, seed_dev_max: per result column j, the deviation angle
+                        arccos(max_i |M(i, j)|) / (pi/2) (1 = orthogonal), mean and max;
+       seed_reindexed = columns j whose best-matching seed column is not j.
+     -1 (and 0) when not computed. */
+  double seed_sin_rms;
+  double seed_dev_mean, seed_dev_max;
+  int seed_reindexed;
 } gevp_info;
 
 typedef enum {

@@ -19,6 +19,10 @@ Functions and the parts of the paper they follow:
 * ``bisect``           -- k-th eigenvalue by bisection on inertia counts.
 * ``inverse_iteration``-- eigenvector at a given eigenvalue estimate.
 * ``grad``             -- gradient of sum_i w_i lambda_i with respect to A, B.
+* ``seed_monitor``     -- how far a block of eigenvectors moved between two SCF
+                          steps: principal angles and per-vector deviation
+                          angles (section 2, paragraph "Eigenvectors
+                          evolution"); plain numpy, FP64.
 """
 import ctypes
 import os
@@ -182,3 +186,25 @@ def cholesky(B):
     if rc:
         raise OracleError(n + rc, n)
     return np.array(L)
+
+
+def seed_monitor(X0, X, B, k):
+    """Seed monitor of two B-orthonormal blocks (section 2, paragraph
+    "Eigenvectors evolution": deviation angles between corresponding
+    eigenvectors of adjacent iterations, here matched by largest overlap).
+
+    With M = X0[:, :k]^H B X[:, :k], the singular values of M are the cosines
+    of the principal angles between the two spans, so sum sin^2 = k - ||M||_F^2.
+    Returns (sin_rms, dev_mean, dev_max, reindexed, dev) where dev[j] =
+    arccos(min(1, max_i |M[i, j]|)) / (pi/2) and reindexed counts the columns
+    j whose largest |M[i, j]| is not at i = j (the lowest such i on ties)."""
+    X0 = np.asarray(X0, dtype=np.complex128)[:, :k]
+    X = np.asarray(X, dtype=np.complex128)[:, :k]
+    B = np.asarray(B, dtype=np.complex128)
+    M = X0.conj().T @ (B @ X)
+    absM = np.abs(M)
+    sin_rms = float(np.sqrt(max(0.0, k - float(np.sum(absM ** 2))) / k))
+    best = np.array([int(np.argmax(absM[:, j])) for j in range(k)])
+    dev = np.array([np.arccos(min(1.0, absM[best[j], j])) / (np.pi / 2) for j in range(k)])
+    reindexed = int(np.sum(best != np.arange(k)))
+    return sin_rms, float(dev.mean()), float(dev.max()), reindexed, dev

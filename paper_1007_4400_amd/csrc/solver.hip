@@ -78,6 +78,7 @@ struct Opts {
   int precision, nex, deg_init, deg_max, maxit, lanczos;
   unsigned long long seed;
   int skip_final;
+  int seed_monitor;
 };
 
 Opts resolve(const gevp_opts* o, int64_t nev) {
@@ -97,6 +98,7 @@ Opts resolve(const gevp_opts* o, int64_t nev) {
   r.lanczos = (o && o->lanczos_steps > 0) ? o->lanczos_steps : 24;
   r.seed = o ? o->seed : 0ull;
   r.skip_final = o ? o->skip_final_residual : 0;
+  r.seed_monitor = o ? o->seed_monitor : 0;
   return r;
 }
 
@@ -309,6 +311,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   gevp_info dummy;
   if (!info) info = &dummy;
   std::memset(info, 0, sizeof(*info));
+  info->seed_sin_rms = info->seed_dev_mean = info->seed_dev_max = -1.0;
   auto bad = [&](int arg) {
     info->lapack_info = -arg;
     return GEVP_ERR_INVALID;
@@ -360,6 +363,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
   need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
   need += ws_round(sizeof(double) * 4);                  // norms
+  need += ws_round(sizeof(double) * (3 * nb + 4));       // seed monitor
   const size_t lp_elem = 8;                              // complex64
   if (mixed) {
     need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
@@ -399,6 +403,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   int* flags = (int*)ws_take(c, sizeof(int) * 8);
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
+  double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 4));  // per-column stats, then 4 results
   void* Clp = nullptr;
   void* bfw = nullptr;  // split-BF16 filter workspace
   void* G0 = nullptr;
@@ -669,9 +674,25 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
                           W, n));
     GEVP_TRY(launch_colnorms(c, n, kx, W, n, fres));
     if (resid_out) GEVP_TRY(launch_copy_real(c, kx, fres, resid_out));
+    // seed monitor: M = X0(:, :k)^H (B X)(:, :k), B X is T
+    const int64_t km = std::min<int64_t>(nev, k0);
+    const bool monitor = seeded && o.seed_monitor && km > 0;
+    double hm[4] = {-1.0, -1.0, -1.0, 0.0};
+    if (monitor) {
+      GEVP_TRY(launch_zgemm(c, 1, 0, km, km, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, Hs, km));
+      GEVP_TRY(launch_seed_monitor(c, km, Hs, km, mon, mon + 3 * nb));
+      GEVP_HIP_TRY(hipMemcpyAsync(hm, mon + 3 * nb, sizeof(hm), hipMemcpyDeviceToHost, c->stream));
+    }
     std::vector<double> hr(kx);
     GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kx, hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    if (monitor) {
+      info->seed_sin_rms = hm[0];
+      info->seed_dev_mean = hm[1];
+      info->seed_dev_max = hm[2];
+      info->seed_reindexed = (int)hm[3];
+    }
     double mx = 0.0;
     for (int64_t i = 0; i < nev; ++i) mx = std::max(mx, hr[i]);
     info->max_resid = (hn[0] > 0.0) ? mx / hn[0] : mx;

@@ -167,6 +167,79 @@ __global__ __launch_bounds__(256) void k_resid_cols(int64_t rows, const zd* W, i
   if (threadIdx.x == 0) out[j] = sqrt(s);
 }
 
+// Seed monitor, per column j of the k x k cross-overlap M: sum_i |M(i,j)|^2,
+// max_i |M(i,j)| and its row (lowest row on ties).
+__global__ __launch_bounds__(256) void k_seed_cols(int k, const zd* M, int64_t ldm, double* stat) {
+  __shared__ double ss[256], sm[256];
+  __shared__ int si[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const zd* col = M + (int64_t)j * ldm;
+  double s2 = 0.0, mx = -1.0;
+  int arg = 0;
+  for (int i = t; i < k; i += 256) {
+    const double a = col[i].x * col[i].x + col[i].y * col[i].y;
+    s2 += a;
+    if (a > mx) {
+      mx = a;
+      arg = i;
+    }
+  }
+  ss[t] = s2;
+  sm[t] = mx;
+  si[t] = arg;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      ss[t] += ss[t + w];
+      if (sm[t + w] > sm[t] || (sm[t + w] == sm[t] && si[t + w] < si[t])) {
+        sm[t] = sm[t + w];
+        si[t] = si[t + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    stat[3 * j] = ss[0];
+    stat[3 * j + 1] = sqrt(fmax(sm[0], 0.0));
+    stat[3 * j + 2] = (double)si[0];
+  }
+}
+
+// out[0] = sqrt(max(0, k - ||M||_F^2) / k), out[1] / out[2] = mean / max of
+// acos(min(1, max_i |M(i,j)|)) / (pi/2), out[3] = columns whose best row is not j
+__global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, double* out) {
+  __shared__ double sf[256], sd[256], sx[256], sr[256];
+  const int t = threadIdx.x;
+  double f = 0.0, d = 0.0, x = 0.0, r = 0.0;
+  for (int j = t; j < k; j += 256) {
+    f += stat[3 * j];
+    const double dev = acos(fmin(1.0, stat[3 * j + 1])) * 0.63661977236758134;  // / (pi/2)
+    d += dev;
+    x = fmax(x, dev);
+    r += ((int)stat[3 * j + 2] != j) ? 1.0 : 0.0;
+  }
+  sf[t] = f;
+  sd[t] = d;
+  sx[t] = x;
+  sr[t] = r;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sf[t] += sf[t + w];
+      sd[t] += sd[t + w];
+      sx[t] = fmax(sx[t], sx[t + w]);
+      sr[t] += sr[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = sqrt(fmax(0.0, (double)k - sf[0]) / (double)k);
+    out[1] = sd[0] / (double)k;
+    out[2] = sx[0];
+    out[3] = sr[0];
+  }
+}
+
 __global__ void k_gather_cols(int64_t rows, const zd* S, int64_t lds, const int* perm, zd* D,
                               int64_t ldd) {
   const int64_t j = blockIdx.y;
@@ -345,6 +418,16 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
   if (rows <= 0 || cols <= 0) return GEVP_OK;
   hipLaunchKernelGGL(k_resid_cols, dim3((unsigned)cols), dim3(256), 0, c->stream, rows, W, ldw, V,
                      ldv, theta, out);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
+                                double* out) {
+  if (k <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_seed_cols, dim3((unsigned)k), dim3(256), 0, c->stream, (int)k, M, ldm, stat);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_seed_finish, dim3(1), dim3(256), 0, c->stream, (int)k, stat, out);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
         ("precision", ctypes.c_int), ("nex", ctypes.c_int), ("deg_init", ctypes.c_int),
         ("deg_max", ctypes.c_int), ("maxit", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
         ("seed", ctypes.c_ulonglong), ("skip_final_residual", ctypes.c_int),
-        ("batch_streams", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+        ("batch_streams", ctypes.c_int), ("seed_monitor", ctypes.c_int),
+        ("reserved", ctypes.c_int * 6),
     ]
 
 
@@ -41,6 +42,8 @@ class Info(ctypes.Structure):
         ("max_resid", ctypes.c_double), ("normA", ctypes.c_double), ("normB", ctypes.c_double),
         ("filter_flops", ctypes.c_double), ("ms", ctypes.c_double * 8),
         ("filter_kernel_ms", ctypes.c_double), ("filter_launches", ctypes.c_int64),
+        ("seed_sin_rms", ctypes.c_double), ("seed_dev_mean", ctypes.c_double),
+        ("seed_dev_max", ctypes.c_double), ("seed_reindexed", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -131,13 +134,14 @@ def _ld(t: torch.Tensor) -> int:
 
 
 def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_steps=0, seed=0,
-              skip_final_residual=False, batch_streams=0) -> Opts:
+              skip_final_residual=False, batch_streams=0, seed_monitor=False) -> Opts:
     o = Opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.nex, o.deg_init, o.deg_max, o.maxit = nex, deg_init, deg_max, maxit
     o.lanczos_steps, o.seed = lanczos_steps, seed
     o.skip_final_residual = int(bool(skip_final_residual))
     o.batch_streams = int(batch_streams)
+    o.seed_monitor = int(bool(seed_monitor))
     return o
 
 

@@ -92,6 +92,38 @@ def test_seeded_equals_cold(h, oracle_mod):
     assert info_s["col_degrees"] <= info_c["col_degrees"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_seed_monitor_matches_oracle(h, oracle_mod, precision):
+    """The solve's seed monitor (principal-angle RMS sine, per-column
+    deviation angles, re-index count of the result against the seed) equals
+    the oracle's on the same seed and returned eigenvectors; without a seed
+    or without the flag it is not computed."""
+    from paper_1007_4400_amd import gevp
+
+    print(f"seed monitor {precision}", flush=True)
+    wl = synth.scaled(synth.MEDIUM, 300, nev=30)
+    seq = list(synth.sequence(wl, 4, steps=3))
+    kx = h.block_size(wl.n, wl.nev)
+    B = seq[0][1]
+    _, X0, _, info0 = h.solve(_dev(seq[0][0]), _dev(B), wl.nev, tol=TOL, kx=kx,
+                              opts=gevp.make_opts(seed_monitor=True))
+    assert info0["seed_sin_rms"] == -1.0 and info0["seed_reindexed"] == 0
+    for step in (1, 2):
+        o = gevp.make_opts(precision=precision, seed_monitor=True)
+        lam, X, _, info = h.solve(_dev(seq[step][0]), _dev(B), wl.nev, X0=X0, tol=TOL, kx=kx, opts=o)
+        _check(oracle_mod, seq[step][0], B, lam, X, wl.nev)
+        s, dm, dx, r, _ = oracle_mod.seed_monitor(X0.cpu().numpy(), X.cpu().numpy(), B, wl.nev)
+        print(step, info["seed_sin_rms"], s, info["seed_dev_mean"], dm, info["seed_dev_max"], dx,
+              info["seed_reindexed"], r, flush=True)
+        assert abs(info["seed_sin_rms"] - s) <= 1e-9
+        assert abs(info["seed_dev_mean"] - dm) <= 1e-7 and abs(info["seed_dev_max"] - dx) <= 1e-7
+        assert info["seed_reindexed"] == r
+        assert 0.0 < s < 0.5  # a perturbed step moves the subspace, but not far
+        X0 = X
+    _, _, _, info_off = h.solve(_dev(seq[1][0]), _dev(B), wl.nev, X0=X0, tol=TOL, kx=kx)
+    assert info_off["seed_sin_rms"] == -1.0
+
+
 def test_not_hpd(h):
     from paper_1007_4400_amd import gevp
 

@@ -262,3 +262,49 @@ def test_lower_triangle_only(oracle_mod):
     l1, _ = oracle_mod.solve(A, B, 5)
     l2, _ = oracle_mod.solve(Ag, Bg, 5)
     assert np.array_equal(l1, l2)
+
+
+def _b_orthonormal_pair(rng, n, k):
+    """HPD B, a B-orthonormal block X0 (n x k) and a B-orthonormal block Y
+    (n x k) whose span is B-orthogonal to span(X0): the first 2k columns of
+    L^{-H} Q for B = L L^H and a unitary Q."""
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    L = np.eye(n) + 0.1 * np.tril(G, -1) / np.sqrt(n)
+    B = L @ L.conj().T
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 2 * k)) + 1j * rng.standard_normal((n, 2 * k)))
+    V = sl.solve_triangular(L.conj().T, Q, lower=False)
+    return B, V[:, :k], V[:, k:]
+
+
+def test_seed_monitor_constructed_angles(oracle_mod):
+    """x_j = cos(t_j) x0_j + sin(t_j) e^{i phi_j} y_j with y_j B-orthogonal to
+    span(X0): the principal angles are exactly t_j, so sin_rms = rms(sin t),
+    each column's deviation angle is t_j / (pi/2) (its best match is x0_j
+    while cos t_j > 0), nothing is re-indexed; a column permutation of X
+    leaves the angles and moves the matches."""
+    rng = np.random.default_rng(11)
+    n, k = 40, 7
+    B, X0, Y = _b_orthonormal_pair(rng, n, k)
+    t = np.array([0.0, 0.01, 0.05, 0.2, 0.4, 0.7, 1.0])
+    ph = rng.uniform(0, 2 * np.pi, k)
+    X = X0 * np.cos(t) + Y * (np.sin(t) * np.exp(1j * ph))
+    assert np.max(np.abs(X.conj().T @ B @ X - np.eye(k))) < 1e-12
+    sin_rms, dmean, dmax, reidx, dev = oracle_mod.seed_monitor(X0, X, B, k)
+    assert abs(sin_rms - np.sqrt(np.mean(np.sin(t) ** 2))) < 1e-12
+    assert np.max(np.abs(dev - t / (np.pi / 2))) < 1e-7  # arccos near 1 loses half the digits
+    assert abs(dmax - 1.0 / (np.pi / 2)) < 1e-12 and reidx == 0
+    perm = np.array([2, 0, 1, 3, 4, 6, 5])
+    s2, m2, x2, r2, d2 = oracle_mod.seed_monitor(X0, X[:, perm], B, k)
+    assert abs(s2 - sin_rms) < 1e-12 and abs(m2 - dmean) < 1e-12 and abs(x2 - dmax) < 1e-12
+    assert r2 == 5 and np.max(np.abs(d2 - dev[perm])) < 1e-12
+
+
+def test_seed_monitor_identity_and_orthogonal(oracle_mod):
+    """Same block: every angle 0; a B-orthogonal block: sin_rms 1 and every
+    deviation angle pi/2 (normalised to 1)."""
+    rng = np.random.default_rng(12)
+    B, X0, Y = _b_orthonormal_pair(rng, 30, 5)
+    s, m, x, r, _ = oracle_mod.seed_monitor(X0, X0 * np.exp(0.3j), B, 5)
+    assert s < 1e-7 and x < 1e-6 and r == 0
+    s, m, x, r, _ = oracle_mod.seed_monitor(X0, Y, B, 5)
+    assert abs(s - 1.0) < 1e-12 and abs(m - 1.0) < 1e-6 and abs(x - 1.0) < 1e-6
