@@ -1,12 +1,13 @@
-// Cholesky factorisation and triangular solves, FP64 complex, recursive.
+// Cholesky factorisation and triangular solves, FP64 complex.
 //
-// Every level of the recursion splits the triangle in two halves (rounded to
-// the 64-wide block), so the off-diagonal work is one large GEMM on the FP64
-// matrix cores per level; only the 64 x 64 diagonal blocks are factored by a
-// single work-group in LDS, which also writes the block's inverse.  The
-// triangular solves then apply those inverses with GEMMs (base case, in place:
-// a 64-wide block fits one output tile of the GEMM, so every tile reads its
-// whole K range before it writes) and recurse exactly like the factorisation.
+// The factorisation is right-looking and blocked by 64 with one block of
+// lookahead on a second stream (see chol_lower); each 64 x 64 diagonal block
+// is factored and inverted by one work-group in LDS.  The triangular solves
+// recurse: every level splits the triangle in two halves (rounded to the
+// 64-wide block), so the off-diagonal work is one large GEMM on the FP64
+// matrix cores per level, and the base case applies a diagonal block's
+// inverse with a GEMM (in place: a 64-wide block fits one output tile of the
+// GEMM, so every tile reads its whole K range before it writes).
 #include <climits>
 
 #include "common.h"
@@ -299,34 +300,97 @@ __global__ void k_zero_upper(zd* M, int64_t ldm, int64_t n) {
 
 inline int64_t split64(int64_t n) { return ((n / 2 + NB - 1) / NB) * NB; }
 
-gevp_status chol_rec(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
-                     int* info, int64_t goff) {
-  if (n <= NB) {
-    static const bool attr = [] {
-      (void)hipFuncSetAttribute((const void*)k_potrf_block,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)POTRF_LDS);
-      return true;
-    }();
-    (void)attr;
-    hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), POTRF_LDS, c->stream, M, ldm, (int)n,
-                       Dinv, ldi, info, (int)goff);
-    GEVP_HIP_TRY(hipGetLastError());
-    return GEVP_OK;
+}  // namespace
+
+namespace {
+gevp_status panel_ctx(gevp_ctx* c, gevp_ctx** out) {
+  if (!c->panel) {
+    gevp_ctx* w = new gevp_ctx();
+    w->device = c->device;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return GEVP_ERR_HIP;
+    }
+    w->owns_stream = true;
+    c->panel = w;
   }
-  const int64_t h = split64(n);
-  GEVP_TRY(chol_rec(c, h, M, ldm, Dinv, ldi, info, goff));
-  zd* M21 = M + h;
-  GEVP_TRY(trsm_right_lower_c(c, h, n - h, M, ldm, Dinv, ldi, M21, ldm));
-  zd* M22 = M + h + h * ldm;
-  GEVP_TRY(launch_zgemm(c, 0, 1, n - h, n - h, h, -1.0, M21, ldm, M21, ldm, 1.0, M22, ldm, 0.0,
-                        nullptr, 0, nullptr, M22, ldm, nullptr, 1));
-  return chol_rec(c, n - h, M22, ldm, Dinv + h, ldi, info, goff + h);
+  for (hipEvent_t& e : c->pev)
+    if (!e) GEVP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  *out = c->panel;
+  return GEVP_OK;
+}
+
+gevp_status potrf_leaf(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi, int* info,
+                       int64_t goff) {
+  static const bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)k_potrf_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)POTRF_LDS);
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), POTRF_LDS, c->stream, M, ldm, (int)n, Dinv,
+                     ldi, info, (int)goff);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
 }
 }  // namespace
 
+// Right-looking blocked Cholesky with one block of lookahead.  Block column
+// k (64 wide) is factored on the panel stream: the diagonal block in LDS
+// (k_potrf_block, which also writes its inverse to Dinv) and the rows below
+// by an in-place product with that inverse, L21 = A21 L11^{-H}.  The main
+// stream then applies panel k to the trailing matrix: first to block column
+// k+1 alone, after which the panel stream may factor it, then to the rest of
+// the lower triangle, which overlaps that factorisation.  The critical path
+// is about sum_k max(trailing update k, factor k+1) instead of a chain of
+// every small solve of a recursive factorisation.
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
-                       int* info_dev) {
-  GEVP_TRY(chol_rec(c, n, M, ldm, Dinv, ldi, info_dev, 0));
+                       int* info_dev, hipEvent_t midpoint) {
+  if (n <= 0) {
+    if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
+    return GEVP_OK;
+  }
+  if (n <= NB) {
+    GEVP_TRY(potrf_leaf(c, n, M, ldm, Dinv, ldi, info_dev, 0));
+    if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
+  } else {
+    const int64_t half = ((n + NB - 1) / NB / 2) * NB;  // first row of the second half
+    gevp_ctx* pc = nullptr;
+    GEVP_TRY(panel_ctx(c, &pc));
+    hipEvent_t evp = c->pev[0], evn = c->pev[1];
+    // the panel stream starts after the work already queued on the main stream
+    GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
+    GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+    for (int64_t r0 = 0; r0 < n; r0 += NB) {
+      const int64_t kb = std::min<int64_t>(NB, n - r0), rest = n - r0 - kb;
+      zd* Mkk = M + r0 + r0 * ldm;
+      GEVP_TRY(potrf_leaf(pc, kb, Mkk, ldm, Dinv + r0, ldi, info_dev, r0));
+      if (rest > 0) {
+        zd* L21 = Mkk + kb;
+        GEVP_TRY(launch_zgemm(pc, 0, 1, rest, kb, kb, 1.0, L21, ldm, Dinv + r0, ldi, 0.0, nullptr, 0,
+                              0.0, nullptr, 0, nullptr, L21, ldm));
+      }
+      GEVP_HIP_TRY(hipEventRecord(evp, pc->stream));
+      GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evp, 0));
+      if (rest > 0) {
+        const int64_t kb1 = std::min<int64_t>(NB, rest);
+        const zd* L21 = Mkk + kb;
+        zd* A2 = M + (r0 + kb) + (r0 + kb) * ldm;
+        // block column k+1: A2(:, :kb1) -= L21 L21(:kb1, :)^H
+        GEVP_TRY(launch_zgemm(c, 0, 1, rest, kb1, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
+                              nullptr, 0, nullptr, A2, ldm));
+        GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
+        GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+        const int64_t rest2 = rest - kb1;
+        if (rest2 > 0) {  // the rest of the trailing lower triangle
+          zd* A3 = A2 + kb1 + kb1 * ldm;
+          GEVP_TRY(launch_zgemm(c, 0, 1, rest2, rest2, kb, -1.0, L21 + kb1, ldm, L21 + kb1, ldm, 1.0,
+                                A3, ldm, 0.0, nullptr, 0, nullptr, A3, ldm, nullptr, 1));
+        }
+      }
+      if (midpoint && r0 + NB == half) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
+    }
+  }
   if (n > 1) {
     dim3 g((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), (unsigned)n);
     hipLaunchKernelGGL(k_zero_upper, g, dim3(256), 0, c->stream, M, ldm, n);

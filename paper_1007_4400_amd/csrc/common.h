@@ -51,6 +51,9 @@ struct gevp_ctx {
   size_t skw_bytes = 0;
   // second stream of a seeded solve (own split-K buffer; created on demand)
   gevp_ctx* aux = nullptr;
+  // panel stream of the Cholesky factorisation and its two events (on demand)
+  gevp_ctx* panel = nullptr;
+  hipEvent_t pev[2] = {nullptr, nullptr};
   // per-stream sub-contexts of gevp_solve_batched (own stream and workspace)
   std::vector<gevp_ctx*> workers;
   bool owns_stream = false;
@@ -77,11 +80,13 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
                          const double* coef = nullptr, int lower = 0, int upperA = 0);
 
-// Recursive blocked Cholesky of the lower triangle; Dinv (n x 64 column-major,
-// ld = ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev
-// (device int) receives the first failing pivot (1-based) or stays 0.
+// Blocked Cholesky of the lower triangle; Dinv (n x 64 column-major, ld =
+// ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev
+// (device int) receives the first failing pivot (1-based) or stays 0.  If
+// given, `midpoint` is recorded on c->stream once half the block columns
+// are queued (from there on the factorisation leaves most compute units idle).
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
-                       int* info_dev);
+                       int* info_dev, hipEvent_t midpoint = nullptr);
 // R <- L^{-1} R (R n x m) ;  R <- L^{-H} R ;  R <- R L^{-H} (R m x n)
 gevp_status trsm_left_lower_n(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
                               const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);

@@ -259,6 +259,10 @@ void gevp_destroy(gevp_handle h) {
   h->workers.clear();
   if (h->aux) gevp_destroy(h->aux);
   h->aux = nullptr;
+  if (h->panel) gevp_destroy(h->panel);
+  h->panel = nullptr;
+  for (hipEvent_t& e : h->pev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(h->stream);
   if (h->owns_stream) (void)hipStreamDestroy(h->stream);
   if (h->ws) (void)hipFree(h->ws);
@@ -294,11 +298,12 @@ gevp_status aux_ctx(gevp_ctx* c, gevp_ctx** out) {
 // error returns included, waits for the second stream's work first: it reads
 // the caller's X0 and writes workspace the next call reuses.
 struct EventPair {
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
   hipStream_t second = nullptr;  // set once work is queued on the second stream
   ~EventPair() {
     if (second) (void)hipStreamSynchronize(second);
     if (fork) (void)hipEventDestroy(fork);
+    if (mid) (void)hipEventDestroy(mid);
     if (join) (void)hipEventDestroy(join);
   }
 };
@@ -436,11 +441,14 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // A full seed block X0 is B-orthonormal when the overlap matrix has not
   // changed; then its Rayleigh-Ritz projection needs no reduced matrix:
   // (L^H X0)^H C (L^H X0) = X0^H A X0.  The projection, its eigensolve and
-  // the norm estimates of A and B run on a second stream while B is factored
-  // and A reduced.  The projection is used if the orthonormality test of
-  // L^H X0 at the first iteration passes (the usual path runs otherwise).  The second stream writes only T, Hs,
-  // Zs, theta, norms, its Lanczos workspace and the eigensolver workspace,
-  // none of which the main stream touches before the join.
+  // the norm estimates of A and B run on a second stream: the estimates
+  // during the first half of the Cholesky factorisation, the projection
+  // from its middle on (the second half leaves most compute units idle)
+  // into the reduction.  The projection is used if the
+  // orthonormality test of L^H X0 at the first iteration passes (the usual
+  // path runs otherwise).  The second stream writes only T, Hs, Zs, theta,
+  // norms, its Lanczos workspace and the eigensolver workspace, none of
+  // which the main stream touches before the join.
   const bool spec = seeded && k0 >= nb;
   const int lzn = lz > 12 ? 12 : lz;  // norm estimates need fewer steps than the filter bound
   const double frac = std::min(1.0, (double)nb / (double)n);
@@ -449,32 +457,42 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (spec) {
     GEVP_TRY(aux_ctx(c, &ax));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.mid, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
+    // norm estimates (bandwidth-bound) overlap the first, GEMM-bound half of
+    // the factorisation
     GEVP_HIP_TRY(hipEventRecord(evs.fork, c->stream));
     GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.fork, 0));
     evs.second = ax->stream;
+    auto norms2 = [&]() -> gevp_status {
+      GEVP_TRY(lanczos_bounds(ax, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw2));
+      GEVP_TRY(lanczos_bounds(ax, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw2));
+      GEVP_TRY(launch_copy_real(ax, 1, bA + 5, norms));
+      return launch_copy_real(ax, 1, bB + 5, norms + 1);
+    };
+    GEVP_TRY(norms2());
+  }
+
+  // ---------------- Cholesky of B
+  tm.start();
+  GEVP_TRY(launch_copy2d(c, n, n, Bf, n, L, n));
+  GEVP_TRY(chol_lower(c, n, L, n, Dinv, n, flags + 1, spec ? evs.mid : nullptr));
+  tm.stop(info, GEVP_STAGE_CHOL);
+  if (spec) {  // second stream, from the Cholesky's midpoint on
+    GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.mid, 0));
     auto second = [&]() -> gevp_status {
       GEVP_TRY(launch_zgemm(ax, 0, 0, n, nb, n, 1.0, Af, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, T, n));
       GEVP_TRY(launch_zgemm(ax, 1, 0, nb, nb, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, Hs, nb));
       GEVP_TRY(launch_symmetrize(ax, nb, Hs, nb));
-      GEVP_TRY(heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw));
-      GEVP_TRY(lanczos_bounds(ax, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw2));
-      GEVP_TRY(lanczos_bounds(ax, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw2));
-      GEVP_TRY(launch_copy_real(ax, 1, bA + 5, norms));
-      return launch_copy_real(ax, 1, bB + 5, norms + 1);
+      return heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw);
     };
     const gevp_status sst = second();
     GEVP_HIP_TRY(hipEventRecord(evs.join, ax->stream));
     GEVP_TRY(sst);
   }
 
-  // ---------------- Cholesky of B
-  tm.start();
-  GEVP_TRY(launch_copy2d(c, n, n, Bf, n, L, n));
-  GEVP_TRY(chol_lower(c, n, L, n, Dinv, n, flags + 1));
-  tm.stop(info, GEVP_STAGE_CHOL);
   int hf[2];
   GEVP_HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, c->stream));
   GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
