@@ -70,7 +70,7 @@ typedef struct {
   int lanczos_steps;        /* spectral-bound Lanczos steps; 0 = 24 */
   unsigned long long seed;  /* random fill of non-seeded columns */
   int skip_final_residual;  /* 1: skip the original-basis residual check */
-  int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 4 */
+  int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 8 */
   int seed_monitor;         /* 1: with a seed X0, report how it relates to the result
                                (gevp_info seed_*; needs the final residual check) */
   int reserved[6];

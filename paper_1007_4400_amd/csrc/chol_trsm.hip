@@ -355,12 +355,15 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
     if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
   } else {
     const int64_t half = ((n + NB - 1) / NB / 2) * NB;  // first row of the second half
-    gevp_ctx* pc = nullptr;
-    GEVP_TRY(panel_ctx(c, &pc));
+    gevp_ctx* pc = c;  // without inner streams the panels run in order on c's stream
+    if (c->inner_streams) GEVP_TRY(panel_ctx(c, &pc));
+    const bool two = pc != c;
     hipEvent_t evp = c->pev[0], evn = c->pev[1];
     // the panel stream starts after the work already queued on the main stream
-    GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
-    GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+    if (two) {
+      GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
+      GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+    }
     for (int64_t r0 = 0; r0 < n; r0 += NB) {
       const int64_t kb = std::min<int64_t>(NB, n - r0), rest = n - r0 - kb;
       zd* Mkk = M + r0 + r0 * ldm;
@@ -370,8 +373,10 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
         GEVP_TRY(launch_zgemm(pc, 0, 1, rest, kb, kb, 1.0, L21, ldm, Dinv + r0, ldi, 0.0, nullptr, 0,
                               0.0, nullptr, 0, nullptr, L21, ldm));
       }
-      GEVP_HIP_TRY(hipEventRecord(evp, pc->stream));
-      GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evp, 0));
+      if (two) {
+        GEVP_HIP_TRY(hipEventRecord(evp, pc->stream));
+        GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evp, 0));
+      }
       if (rest > 0) {
         const int64_t kb1 = std::min<int64_t>(NB, rest);
         const zd* L21 = Mkk + kb;
@@ -379,8 +384,10 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
         // block column k+1: A2(:, :kb1) -= L21 L21(:kb1, :)^H
         GEVP_TRY(launch_zgemm(c, 0, 1, rest, kb1, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
                               nullptr, 0, nullptr, A2, ldm));
-        GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
-        GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+        if (two) {
+          GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
+          GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
+        }
         const int64_t rest2 = rest - kb1;
         if (rest2 > 0) {  // the rest of the trailing lower triangle
           zd* A3 = A2 + kb1 + kb1 * ldm;

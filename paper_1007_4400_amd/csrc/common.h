@@ -51,6 +51,9 @@ struct gevp_ctx {
   size_t skw_bytes = 0;
   // second stream of a seeded solve (own split-K buffer; created on demand)
   gevp_ctx* aux = nullptr;
+  // false for the worker contexts of gevp_solve_batched: problems already run
+  // concurrently there, so a solve keeps all its work on its own stream
+  bool inner_streams = true;
   // panel stream of the Cholesky factorisation and its two events (on demand)
   gevp_ctx* panel = nullptr;
   hipEvent_t pev[2] = {nullptr, nullptr};

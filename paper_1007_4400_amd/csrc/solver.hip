@@ -449,7 +449,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // path runs otherwise).  The second stream writes only T, Hs, Zs, theta,
   // norms, its Lanczos workspace and the eigensolver workspace, none of
   // which the main stream touches before the join.
-  const bool spec = seeded && k0 >= nb;
+  const bool full_seed = seeded && k0 >= nb;
+  const bool spec = full_seed && c->inner_streams;
   const int lzn = lz > 12 ? 12 : lz;  // norm estimates need fewer steps than the filter bound
   const double frac = std::min(1.0, (double)nb / (double)n);
   EventPair evs;
@@ -625,7 +626,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   for (it = 0; it < o.maxit; ++it) {
     tm.start();
     bool skipped = false;
-    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, spec && it == 0, &skipped));
+    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, full_seed && it == 0, &skipped));
     if (spec && it == 0) GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evs.join, 0));
     tm.stop(info, GEVP_STAGE_QR);
     tm.start();
@@ -766,7 +767,7 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
     return GEVP_ERR_INVALID;
   if (count == 0) return GEVP_OK;
   GEVP_HIP_TRY(hipSetDevice(h->device));
-  int streams = (opts && opts->batch_streams > 0) ? opts->batch_streams : 4;
+  int streams = (opts && opts->batch_streams > 0) ? opts->batch_streams : 8;
   if (streams > 16) streams = 16;
   if (streams > count) streams = count;
   while ((int)h->workers.size() < streams) {
@@ -777,6 +778,7 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
       return GEVP_ERR_HIP;
     }
     w->owns_stream = true;
+    w->inner_streams = false;
     h->workers.push_back(w);
   }
   // the worker streams start after the work already queued on the caller's stream
