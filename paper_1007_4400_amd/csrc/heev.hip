@@ -8,11 +8,12 @@
 //     previous reflector, so no extra grid-wide barrier is needed), and
 //     accumulates p = tau H v for reflector s on its columns.  Hermitian
 //     symmetry turns each row dot product into a contiguous column dot.
-//  2. Eigenvalues of the real tridiagonal T by bisection on Sturm counts, one
-//     thread per eigenvalue.
+//  2. Eigenvalues of the real tridiagonal T by multisection on Sturm counts,
+//     one wave per eigenvalue (64 points per round).
 //  3. Eigenvectors of T by inverse iteration (tridiagonal LU with partial
-//     pivoting), one thread per eigenvalue; members of numerically
-//     degenerate clusters are then made orthonormal by modified Gram-Schmidt.
+//     pivoting), one thread per eigenvalue, recurrences in registers; members
+//     of numerically degenerate clusters are then made orthonormal by
+//     modified Gram-Schmidt.
 //  4. Z = U Z_T by applying the reflectors in reverse order.
 #include <cfloat>
 

@@ -18,7 +18,9 @@
 // epilogue D = alpha C Y + beta Y + gamma Y_prev.  A column whose Ritz value
 // theta lies left of the interval gains a factor rho = |t| + sqrt(t^2 - 1),
 // t = (theta - c)/e, per degree relative to the damped part, so it needs
-// m = log(r / tol) / log(rho) more degrees to converge; converged wanted
+// about m = log(r / tol) / log(rho) more degrees to converge (the degree
+// chosen aims at tol / margin, one degree more, so that columns the
+// first-order model misjudges still converge in this sweep); converged wanted
 // columns get degree 0 (they stay in the basis), guard columns the largest
 // degree of the unconverged wanted ones.  Degrees are even so every column's
 // last iterate lands in the same buffer; columns are sorted by degree so the

@@ -4,13 +4,17 @@
 // One solve (the paper's fast iteration, section 2, seeded by the previous
 // iteration's eigenvectors):
 //   stage    A, B lower triangles -> full Hermitian copies; NaN/Inf scan
-//   chol     B = L L^H
-//   reduce   C = L^{-1} A L^{-H}, symmetrised
+//   chol     B = L L^H (blocked, lookahead on a panel stream)
+//   reduce   C = L^{-1} A L^{-H} (left solve, then the lower triangle of the
+//            right solve, mirrored)
 //   bounds   Lanczos on C (filter interval), on A and B (norm estimates)
-//   seed     Y0 = [L^H X0, random], or random for a cold start
+//   seed     Y0 = [L^H X0, random], or random for a cold start; a full seed's
+//            first projection X0^H A X0 and its eigensolve run on a second
+//            stream during the factorisation and reduction
 //   loop     CholQR2 -> Rayleigh-Ritz (W = C Y, H = Y^H W, H = Z T Z^H,
 //            Y <- Y Z) -> residuals -> controller -> Chebyshev filter
-//   final    X = L^{-H} Y(:, 1:kx), original-basis residuals, phase fix
+//   final    X = L^{-H} Y(:, 1:kx), original-basis residuals, phase fix,
+//            optional seed monitor
 // The only device-to-host traffic is a few status words per sweep.
 #include <algorithm>
 #include <atomic>

@@ -21,6 +21,15 @@
 //
 // The Chebyshev filter uses the epilogue with Cm = the B operand and E = the
 // previous iterate, coefficients read from device memory (`coef`).
+//
+// Split-K: a product with few output tiles and a long K (a Gram matrix
+// Y^H Y of a tall block, say) splits K over several work-groups chosen by a
+// cost model (rounds of two work-groups per compute unit times slices per
+// part, plus the reduction); each writes its raw partial tile to the
+// handle's buffer and a second kernel sums the parts in a fixed order and
+// applies the epilogue, so results do not depend on scheduling.  upperA = 1
+// declares op(A) upper triangular (L^H): a row block starts its K walk at
+// its own first row.
 #include <atomic>
 
 #include "common.h"
