@@ -23,6 +23,12 @@ Functions and the parts of the paper they follow:
                           steps: principal angles and per-vector deviation
                           angles (section 2, paragraph "Eigenvectors
                           evolution"); plain numpy, FP64.
+* ``threshold_update`` -- partial update of a Hermitian matrix between two
+                          SCF steps: only entries whose change exceeds a
+                          fraction p_t of the largest change are taken over
+                          (section 3, paragraph "Matrix generation"); plain
+                          numpy, FP64.
+* ``masked_update``    -- the same update driven by a given entry mask.
 """
 import ctypes
 import os
@@ -208,3 +214,56 @@ def seed_monitor(X0, X, B, k):
     dev = np.array([np.arccos(min(1.0, absM[best[j], j])) / (np.pi / 2) for j in range(k)])
     reindexed = int(np.sum(best != np.arange(k)))
     return sin_rms, float(dev.mean()), float(dev.max()), reindexed, dev
+
+
+def threshold_update(A_cur, A_new, p_t):
+    """Thresholded partial update (section 3, paragraph "Matrix generation").
+
+    The paper measures the change between the Hamiltonians of two adjacent
+    SCF iterations by the largest entry variation delta = max |A_new - A_cur|
+    and normalises the difference by it; entries whose normalised change
+    exceeds the threshold p_t (a fraction of delta) are the ones that need
+    recomputing, all others keep their previous value.
+
+    Readings: entries are complex, so "largest variation" is the largest
+    modulus; only the stored lower triangle (diagonal included) takes part,
+    which for a Hermitian change gives the same delta and a mask that mirrors
+    onto the upper triangle; "above threshold" is strict.  The comparison
+    |dA_ij| > p_t * delta is taken in squared form,
+        s_ij = dr*dr + di*di  >  (p_t*p_t) * max s,
+    every operation rounded on its own (numpy does not fuse), so the decision
+    is a fixed FP64 computation.  Non-finite changes never pass the test.
+
+    Returns (A_out, mask, delta, updated): A_out equals A_cur except on the
+    masked entries, which hold A_new's values (the upper triangle is A_cur's);
+    mask is a boolean n x n array, True only on updated lower entries;
+    delta = sqrt(max s); updated = mask.sum()."""
+    A_cur = np.asarray(A_cur, dtype=np.complex128)
+    A_new = np.asarray(A_new, dtype=np.complex128)
+    n = A_cur.shape[0]
+    lower = np.tril(np.ones((n, n), dtype=bool))
+    dr = A_new.real - A_cur.real
+    di = A_new.imag - A_cur.imag
+    with np.errstate(invalid="ignore", over="ignore"):
+        s = dr * dr + di * di
+    s = np.where(lower, s, 0.0)
+    finite = np.isfinite(s)
+    if not finite.all():
+        # a non-finite change disables the whole update
+        return A_cur.copy(), np.zeros((n, n), dtype=bool), float("nan"), 0
+    smax = float(s.max()) if n else 0.0
+    thr = (p_t * p_t) * smax
+    mask = lower & (s > thr)
+    A_out = np.where(mask, A_new, A_cur)
+    return A_out, mask, float(np.sqrt(smax)), int(mask.sum())
+
+
+def masked_update(A_cur, A_src, mask):
+    """Apply a precomputed entry mask: masked lower-triangle entries take
+    A_src's value, everything else keeps A_cur's (the fast iterations of
+    section 3, paragraph "Matrix generation", where only part of the entries
+    have been regenerated)."""
+    A_cur = np.asarray(A_cur, dtype=np.complex128)
+    n = A_cur.shape[0]
+    m = np.asarray(mask, dtype=bool) & np.tril(np.ones((n, n), dtype=bool))
+    return np.where(m, np.asarray(A_src, dtype=np.complex128), A_cur)

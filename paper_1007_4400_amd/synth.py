@@ -265,3 +265,120 @@ def unit_hermitian_torch(n: int, g, device="cuda", iters: int = 60):
         nrm = math.sqrt(wn)
         v = w / wn
     return H / nrm
+
+
+# ---------------------------------------------------------------------------
+# matrix-entry evolution (thresholded partial updates)
+#
+# Stand-in for the Hamiltonian differences between adjacent SCF iterations
+# that the paper studies at fixed k-point (section 3, paragraph "Matrix
+# generation", and its figure): wide areas of the difference stay below any
+# threshold, rows and columns of unchanging entries form a cross, and the
+# share of entries above a fixed threshold falls as the run settles.
+#
+# Step k >= 1 adds D_k = eps_k * (w w^T) o K_k o H_k to the Hamiltonian, where
+# * w_i = 1, except ``frozen`` on the index bands listed in ``bands`` (the
+#   rows and columns of the cross),
+# * K_k(i, j) = exp(-|i - j| / l_k), l_k = width0 * n * width_decay**(k-1)
+#   (the change reaches less far from the diagonal at later steps),
+# * H_k Hermitian with entries of modulus uniform in [1/2, 1] and uniform
+#   phase (drawn for the strict lower triangle and mirrored; real diagonal),
+# * eps_k = eps0 * decay**(k-1).
+# Step 0 is a Hermitian Gaussian matrix (or a given pencil's A).
+
+
+@dataclasses.dataclass(frozen=True)
+class UpdateWorkload:
+    name: str
+    n: int
+    steps: int  # updates after step 0
+    p_t: float  # variation threshold as a fraction of delta
+    width0: float
+    width_decay: float
+    bands: tuple  # ((start, stop), ...) as fractions of n
+    frozen: float
+    eps0: float
+    decay: float
+
+
+# at p_t = 0.1 the share of lower-triangle entries above threshold falls
+# from about 0.6 at step 1 to about 0.15 at step 12 (n = 1024 and 8192)
+UPDATE_SMALL = UpdateWorkload("update_n300_pt0.1", 300, 4, 0.1, 0.3, 0.8,
+                              ((0.30, 0.38), (0.70, 0.76)), 0.05, 1e-2, 0.85)
+UPDATE_LARGE = UpdateWorkload("update_n8192_pt0.1", 8192, 12, 0.1, 0.3, 0.8,
+                              ((0.30, 0.36), (0.62, 0.66), (0.85, 0.88)), 0.05, 1e-2, 0.85)
+
+
+def update_scaled(wl: UpdateWorkload, n: int, steps: Optional[int] = None) -> UpdateWorkload:
+    return dataclasses.replace(wl, name=f"update_n{n}_pt{wl.p_t:g}", n=n,
+                               steps=steps if steps is not None else wl.steps)
+
+
+def update_weights(wl: UpdateWorkload) -> np.ndarray:
+    w = np.ones(wl.n)
+    for a, b in wl.bands:
+        w[int(round(a * wl.n)):int(round(b * wl.n))] = wl.frozen
+    return w
+
+
+def update_envelope(wl: UpdateWorkload, k: int) -> np.ndarray:
+    """eps_k * (w w^T) o K_k as a real n x n array (k >= 1)."""
+    w = update_weights(wl)
+    ell = wl.width0 * wl.n * wl.width_decay ** (k - 1)
+    idx = np.arange(wl.n)
+    K = np.exp(-np.abs(idx[:, None] - idx[None, :]) / ell)
+    return wl.eps0 * wl.decay ** (k - 1) * (w[:, None] * w[None, :]) * K
+
+
+def _bounded_hermitian(mod: np.ndarray, phase: np.ndarray) -> np.ndarray:
+    M = np.tril(mod * np.exp(1j * phase), -1)
+    return M + M.conj().T + np.diag(mod.diagonal() * np.cos(phase.diagonal()))
+
+
+def update_sequence(wl: UpdateWorkload, seed: int, A0: Optional[np.ndarray] = None):
+    """Yields A_0, A_1, ..., A_steps (complex128, Hermitian)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    if A0 is None:
+        G = _cgauss(rng, (wl.n, wl.n))
+        A = 0.5 * (G + G.conj().T)
+    else:
+        A = np.array(A0, dtype=np.complex128)
+    yield A.copy()
+    for k in range(1, wl.steps + 1):
+        mod = rng.uniform(0.5, 1.0, size=(wl.n, wl.n))
+        phase = rng.uniform(0.0, 2.0 * math.pi, size=(wl.n, wl.n))
+        A = A + update_envelope(wl, k) * _bounded_hermitian(mod, phase)
+        yield A.copy()
+
+
+def update_sequence_torch(wl: UpdateWorkload, seed: int, device="cuda", A0=None):
+    """The same construction with a seeded torch generator on ``device``
+    (a different but deterministic random stream).  Yields torch tensors."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n = wl.n
+    if A0 is None:
+        G = torch.randn(n, n, generator=g, device=device, dtype=torch.complex128)
+        A = 0.5 * (G + G.conj().T)
+        del G
+    else:
+        A = A0.clone()
+    yield A.clone()
+    w = torch.as_tensor(update_weights(wl), device=device, dtype=torch.float64)
+    idx = torch.arange(n, device=device, dtype=torch.float64)
+    for k in range(1, wl.steps + 1):
+        ell = wl.width0 * n * wl.width_decay ** (k - 1)
+        env = torch.exp(-(idx[:, None] - idx[None, :]).abs() / ell)
+        env *= w[:, None] * w[None, :] * (wl.eps0 * wl.decay ** (k - 1))
+        mod = torch.rand(n, n, generator=g, device=device, dtype=torch.float64) * 0.5 + 0.5
+        phase = torch.rand(n, n, generator=g, device=device, dtype=torch.float64) * (2.0 * math.pi)
+        M = torch.tril(torch.polar(mod, phase), -1)
+        H = M + M.conj().T
+        del M
+        H.diagonal().copy_(mod.diagonal() * torch.cos(phase.diagonal()))
+        del mod, phase
+        A = A + env * H
+        del H, env
+        yield A.clone()
