@@ -124,7 +124,9 @@ gevp_status gevp_set_stream(gevp_handle h, void* hip_stream);
 
 /* Profiling bits: 1 = per-stage HIP event times into gevp_info.ms (adds a
  * synchronisation per stage); 2 = HIP events around every filter GEMM launch,
- * summed into gevp_info.filter_kernel_ms (no added synchronisation). */
+ * summed into gevp_info.filter_kernel_ms (no added synchronisation), and
+ * around the scan and apply kernels of gevp_update_thresholded
+ * (gevp_update_info.scan_ms, apply_ms). */
 gevp_status gevp_set_profiling(gevp_handle h, int flags);
 
 /* Free the workspace and the handle. */
@@ -242,6 +244,78 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
  * Synchronous. */
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
                         double* theta, void* Z, int64_t ldz);
+
+/* ------------------------------------------------------------------------
+ * Thresholded partial update of a Hermitian matrix between two SCF
+ * iterations (section 3, paragraph "Matrix generation").  The paper measures
+ * the change between adjacent Hamiltonians at one k-point by the largest
+ * entry variation delta and proposes updating only the entries whose change,
+ * normalised by delta, exceeds a threshold p_t; the other entries keep their
+ * previous values (and need not be regenerated).
+ *
+ * Readings: delta is the largest modulus |A_new(i,j) - A(i,j)| over the
+ * stored lower triangle (diagonal included); an entry is updated when
+ * |A_new(i,j) - A(i,j)| > p_t * delta (strict), evaluated in FP64 as
+ *   dr*dr + di*di > (p_t*p_t) * delta^2,  dr, di the real and imaginary
+ *   differences, every operation rounded separately (no fused multiply-add).
+ *
+ * Mask layout (both functions): uint32 words, column-major with leading
+ * dimension ldmask >= ceil(n/32): bit (i mod 32) of word mask[j*ldmask + i/32]
+ * is entry (i, j).  Only bits with i >= j and i < n are ever set.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  double delta;            /* max |A_new - A| over the lower triangle; NaN if non-finite */
+  int64_t entries;         /* n (n + 1) / 2 */
+  int64_t updated;         /* entries taken from A_new */
+  int64_t tiles;           /* 64 x 64 tiles of the lower triangle */
+  int64_t tiles_touched;   /* tiles with at least one updated entry */
+  int64_t tiles_copied;    /* tiles whose every entry was above threshold */
+  int nonfinite;           /* 1 when a change was NaN, Inf, or overflowed when squared */
+  int reserved;
+  double scan_ms, apply_ms; /* profiling flag 2 and info given: durations of the scan
+                               and the apply kernel (HIP events on the handle's
+                               stream); else 0 */
+} gevp_update_info;
+
+/*
+ * A <- A with every lower entry whose change exceeds p_t * delta taken from
+ * A_new.
+ *   n          order (n >= 0; n = 0 does nothing)
+ *   A, lda     device complex128 n x n, lower triangle read and updated in
+ *              place; the strict upper triangle is never written.  Loads of
+ *              the edge tiles may touch (and ignore) any entry of the n x n
+ *              storage.
+ *   A_new, ldn device complex128 n x n, the newly generated matrix (lower
+ *              triangle used); must not overlap A unless it is A itself
+ *   p_t        threshold as a fraction of delta, 0 <= p_t < inf
+ *              (p_t = 0: every changed entry; p_t >= 1: none)
+ *   mask       optional device uint32 words (layout above, ldmask words per
+ *              column): receives the updated entries; every word of rows
+ *              < n is written
+ *   info       optional host struct.  With info the call waits for the
+ *              result; without it the call is asynchronous on the handle's
+ *              stream.
+ * A non-finite change (or one whose square overflows) cancels the whole
+ * update: A and the mask's set bits are left as if nothing were above
+ * threshold, and with info the call returns GEVP_ERR_NONFINITE.
+ * Pointers must be 16-byte aligned (mask: 4-byte); otherwise, and for a bad
+ * size or p_t, GEVP_ERR_INVALID with nothing launched.  With n = 0 the
+ * pointers are not looked at.
+ */
+gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A, int64_t lda,
+                                    const void* A_new, int64_t ldn, double p_t, uint32_t* mask,
+                                    int64_t ldmask, gevp_update_info* info);
+
+/*
+ * The fast-iteration update of the same paragraph: only part of the entries
+ * of the next matrix were regenerated (those marked in `mask`, e.g. by a
+ * previous gevp_update_thresholded); they are copied from S into A, every
+ * other entry of A is left alone.  Lower-triangle bits only (i >= j); S is
+ * read only where a bit is set.  Asynchronous; A and S must not overlap.
+ * Errors as for gevp_update_thresholded.
+ */
+gevp_status gevp_update_masked(gevp_handle h, int64_t n, void* A, int64_t lda, const void* S,
+                               int64_t lds, const uint32_t* mask, int64_t ldmask);
 
 #ifdef __cplusplus
 }

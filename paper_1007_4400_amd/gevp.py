@@ -52,6 +52,18 @@ class Info(ctypes.Structure):
         return d
 
 
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [
+        ("delta", ctypes.c_double), ("entries", ctypes.c_int64), ("updated", ctypes.c_int64),
+        ("tiles", ctypes.c_int64), ("tiles_touched", ctypes.c_int64),
+        ("tiles_copied", ctypes.c_int64), ("nonfinite", ctypes.c_int), ("reserved", ctypes.c_int),
+        ("scan_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class GevpError(RuntimeError):
     def __init__(self, status: int, what: str, info: Optional[Info] = None):
         self.status = status
@@ -102,6 +114,10 @@ def load():
     lib.gevp_k_trsm.restype = I
     lib.gevp_k_heev.argtypes = [P, L, P, L, P, P, L]
     lib.gevp_k_heev.restype = I
+    lib.gevp_update_thresholded.argtypes = [P, L, P, L, P, L, D, P, L, ctypes.POINTER(UpdateInfo)]
+    lib.gevp_update_thresholded.restype = I
+    lib.gevp_update_masked.argtypes = [P, L, P, L, P, L, P, L]
+    lib.gevp_update_masked.restype = I
     _lib = lib
     return lib
 
@@ -330,6 +346,76 @@ class Handle:
         if s != GEVP_OK:
             raise GevpError(s, "gevp_k_heev")
         return th, Z
+
+
+    # ---- thresholded partial matrix update
+
+    def update_thresholded(self, A, A_new, p_t, mask=None, want_info=True):
+        """In place on A (complex128, column-major, n x n): lower entries whose
+        change exceeds p_t * delta are taken from A_new.  mask: optional int32
+        tensor from empty_mask(n) receiving the updated entries.  Returns the
+        gevp_update_info fields as a dict (with "status"), or None when
+        want_info is False (then the call is asynchronous)."""
+        n = _check_inplace(A)
+        A_new = colmajor(A_new)
+        if tuple(A_new.shape) != (n, n) or A_new.dtype != torch.complex128:
+            raise ValueError("A_new must be a complex128 n x n matrix")
+        ldm = _check_mask(mask, n)
+        inf = UpdateInfo() if want_info else None
+        self._stream()
+        s = self.lib.gevp_update_thresholded(self.h, n, _ptr(A), _ld(A), _ptr(A_new), _ld(A_new),
+                                             float(p_t), _ptr(mask), ldm,
+                                             ctypes.byref(inf) if want_info else None)
+        if s not in (GEVP_OK, GEVP_ERR_NONFINITE):
+            raise GevpError(s, "gevp_update_thresholded")
+        if not want_info:
+            return None
+        d = inf.as_dict()
+        d["status"] = s
+        return d
+
+    def update_masked(self, A, S, mask):
+        """In place on A: lower entries whose bit is set in mask (int32 words
+        from empty_mask(n)) are taken from S."""
+        n = _check_inplace(A)
+        S = colmajor(S)
+        if tuple(S.shape) != (n, n) or S.dtype != torch.complex128:
+            raise ValueError("S must be a complex128 n x n matrix")
+        if mask is None:
+            raise ValueError("mask is required")
+        ldm = _check_mask(mask, n)
+        self._stream()
+        s = self.lib.gevp_update_masked(self.h, n, _ptr(A), _ld(A), _ptr(S), _ld(S), _ptr(mask), ldm)
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_update_masked")
+
+
+def mask_words(n: int) -> int:
+    """uint32 words per column of an update mask."""
+    return (n + 31) // 32
+
+
+def empty_mask(n: int, device=None) -> torch.Tensor:
+    """Update mask storage: row j of the (n, mask_words(n)) int32 tensor holds
+    column j's bits (bit i % 32 of word i // 32 is entry (i, j))."""
+    return torch.empty((n, mask_words(n)), dtype=torch.int32, device=device)
+
+
+def _check_inplace(A) -> int:
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.complex128:
+        raise ValueError("A must be a complex128 n x n matrix")
+    if A.stride(0) != 1 and A.shape[0] > 1:
+        raise ValueError("A is updated in place and must be column-major")
+    return int(A.shape[0])
+
+
+def _check_mask(mask, n) -> int:
+    if mask is None:
+        return 1
+    if mask.dtype != torch.int32 or mask.dim() != 2 or mask.shape[0] != n or mask.stride(1) != 1 \
+            or mask.shape[1] < mask_words(n):
+        raise ValueError("mask must be an int32 tensor shaped (n, >= ceil(n/32)), rows contiguous")
+    return max(int(mask.stride(0)), mask_words(n), 1)
 
 
 class GEVPFunction(torch.autograd.Function):

@@ -1,0 +1,279 @@
+"""Thresholded partial matrix update on the GPU against the oracle (section 3,
+paragraph "Matrix generation": entries whose change between adjacent SCF
+Hamiltonians exceeds p_t * delta are updated, delta the largest change).
+
+Bar: the threshold decision is integer-valued and both sides take it in the
+same FP64 arithmetic (squared moduli, separately rounded operations), so the
+updated matrix, the mask bits, the counts and the per-tile statistics must
+agree exactly; delta = sqrt(max |dA|^2) agrees to one rounding of the square
+root (relative 2.3e-16).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1007_4400_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_1007_4400_amd import gevp
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return gevp.Handle(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).to("cuda")
+
+
+def _bits(t):
+    """Bit-exact view of a complex128 array (real and imaginary words)."""
+    a = t.cpu().numpy() if hasattr(t, "cpu") else t
+    return np.ascontiguousarray(a).view(np.int64)
+
+
+def _unpack(mask_t, n):
+    """(n, words) int32 words -> boolean n x n entry mask [i, j]."""
+    w = np.ascontiguousarray(mask_t.cpu().numpy()).view(np.uint8)
+    bits = np.unpackbits(w, axis=1, bitorder="little")[:, :n]  # [j, i]
+    return bits.T.astype(bool)
+
+
+def _tile_stats(mask, n):
+    nt = (n + 63) // 64
+    touched = copied = 0
+    for bi in range(nt):
+        for bj in range(bi + 1):
+            blk = mask[bi * 64:(bi + 1) * 64, bj * 64:(bj + 1) * 64]
+            low = np.tril(np.ones((n, n), dtype=bool))[bi * 64:(bi + 1) * 64, bj * 64:(bj + 1) * 64]
+            if blk.any():
+                touched += 1
+            if np.array_equal(blk, low):
+                copied += 1
+    return touched, copied
+
+
+def _run(h, A_cur, A_new, p_t, with_mask=True):
+    from paper_1007_4400_amd import gevp
+
+    n = A_cur.shape[0]
+    A = _dev(A_cur)
+    mask = gevp.empty_mask(n, device="cuda") if with_mask else None
+    if mask is not None:
+        mask.fill_(-1)  # every word must be written
+    info = h.update_thresholded(A, _dev(A_new), p_t, mask=mask)
+    torch.cuda.synchronize()
+    return A.cpu().numpy(), (None if mask is None else _unpack(mask, n)), info
+
+
+def _compare(oracle_mod, h, A_cur, A_new, p_t):
+    out, mask, info = _run(h, A_cur, A_new, p_t)
+    ref, mref, dref, cref = oracle_mod.threshold_update(A_cur, A_new, p_t)
+    n = A_cur.shape[0]
+    assert info["status"] == 0
+    assert np.array_equal(_bits(out), _bits(ref)), "updated matrix differs"
+    assert np.array_equal(mask, mref), "mask differs"
+    assert info["updated"] == cref
+    assert info["entries"] == n * (n + 1) // 2
+    assert info["tiles"] == ((n + 63) // 64) * ((n + 63) // 64 + 1) // 2
+    touched, copied = _tile_stats(mref, n)
+    assert info["tiles_touched"] == touched and info["tiles_copied"] == copied
+    assert abs(info["delta"] - dref) <= 2.3e-16 * dref
+    return info
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 129, 300, 700])
+@pytest.mark.parametrize("p_t", [0.0, 0.1, 0.5, 1.0])
+def test_parity_on_update_sequence(oracle_mod, h, n, p_t):
+    print(f"update parity n={n} p_t={p_t}", flush=True)
+    wl = synth.update_scaled(synth.UPDATE_SMALL, n, steps=2)
+    seq = list(synth.update_sequence(wl, 11))
+    A_cur = seq[0]
+    for A_new in seq[1:]:
+        _compare(oracle_mod, h, A_cur, A_new, p_t)
+        A_cur = oracle_mod.threshold_update(A_cur, A_new, p_t)[0]
+
+
+@pytest.mark.parametrize("n,p_t", [(9, 0.5), (130, 0.3), (200, 0.05)])
+def test_grid_and_exact_tie(oracle_mod, h, n, p_t):
+    # |A_new(i, j)| = (2i + j) / 128, exact in binary; n = 9, p_t = 0.5 puts
+    # entries exactly on the threshold
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    mag = (2 * i + j) / 128.0
+    A_new = np.where((i + j) % 2 == 0, mag + 0j, 1j * mag)
+    _compare(oracle_mod, h, np.zeros((n, n), dtype=np.complex128), A_new, p_t)
+
+
+def test_whole_tiles_copied_and_skipped(oracle_mod, h):
+    # change only a band of tiles: far tiles are skipped, the band is copied
+    n = 320
+    rng = np.random.default_rng(3)
+    A_cur = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A_new = A_cur.copy()
+    A_new[128:256, 64:192] += 1.0 + rng.uniform(0, 0.1, size=(128, 128))
+    info = _compare(oracle_mod, h, A_cur, A_new, 0.5)
+    assert info["tiles_copied"] >= 3 and info["tiles_touched"] < info["tiles"]
+
+
+def test_upper_triangle_and_padding_untouched(oracle_mod, h):
+    from paper_1007_4400_amd import gevp
+
+    n, ld = 150, 173
+    wl = synth.update_scaled(synth.UPDATE_SMALL, n, steps=1)
+    A_cur, A_new = list(synth.update_sequence(wl, 2))
+    big = np.zeros((ld, n), dtype=np.complex128)
+    big[:n] = A_cur
+    big[n:] = 7.0 + 7.0j  # padding rows
+    Abig = _dev(big)
+    A = Abig[:n]  # column-major view with lda = 173
+    assert A.stride() == (1, ld)
+    mask = torch.full((n, 11), -1, dtype=torch.int32, device="cuda")  # ldmask 11 > 5 words
+    info = h.update_thresholded(A, _dev(A_new), 0.1, mask=mask)
+    torch.cuda.synchronize()
+    ref, mref, _, cref = oracle_mod.threshold_update(A_cur, A_new, 0.1)
+    got = Abig.cpu().numpy()
+    assert np.array_equal(_bits(got[:n]), _bits(ref))
+    assert np.all(got[n:] == 7.0 + 7.0j)
+    assert info["updated"] == cref
+    m = mask.cpu().numpy()
+    assert np.all(m[:, gevp.mask_words(n):] == -1), "words beyond ceil(n/32) were written"
+    assert np.array_equal(_unpack(mask[:, :gevp.mask_words(n)], n), mref)
+
+
+def test_no_change_and_same_buffer(oracle_mod, h):
+    wl = synth.update_scaled(synth.UPDATE_SMALL, 100, steps=0)
+    (A0,) = list(synth.update_sequence(wl, 4))
+    out, mask, info = _run(h, A0, A0.copy(), 0.1)
+    assert info["updated"] == 0 and info["delta"] == 0.0 and not mask.any()
+    assert np.array_equal(_bits(out), _bits(A0))
+    A = _dev(A0)
+    info = h.update_thresholded(A, A, 0.0)
+    assert info["updated"] == 0
+    assert np.array_equal(_bits(A.cpu().numpy()), _bits(A0))
+
+
+def test_empty_matrix(h):
+    A = torch.empty((0, 0), dtype=torch.complex128, device="cuda")
+    info = h.update_thresholded(A, A, 0.1)
+    assert info["entries"] == 0 and info["updated"] == 0 and info["tiles"] == 0
+
+
+def test_nonfinite_change_cancels_update(h):
+    from paper_1007_4400_amd import gevp
+
+    n = 130
+    wl = synth.update_scaled(synth.UPDATE_SMALL, n, steps=1)
+    A_cur, A_new = list(synth.update_sequence(wl, 6))
+    for bad in (np.nan, np.inf):
+        An = A_new.copy()
+        An[100, 3] = bad
+        out, mask, info = _run(h, A_cur, An, 0.1)
+        assert info["status"] == gevp.GEVP_ERR_NONFINITE and info["nonfinite"] == 1
+        assert math.isnan(info["delta"]) and info["updated"] == 0
+        assert not mask.any()
+        assert np.array_equal(_bits(out), _bits(A_cur))
+
+
+def test_invalid_arguments(h):
+    from paper_1007_4400_amd import gevp
+
+    A = _dev(np.eye(10, dtype=np.complex128))
+    with pytest.raises(gevp.GevpError):
+        h.update_thresholded(A, A.clone(), -0.1)
+    with pytest.raises(gevp.GevpError):
+        h.update_thresholded(A, A.clone(), float("nan"))
+    lib = gevp.load()
+    # misaligned pointer: nothing is launched
+    s = lib.gevp_update_thresholded(h.h, 10, A.data_ptr() + 8, 10, A.data_ptr(), 10, 0.1, None, 1,
+                                    None)
+    assert s == gevp.GEVP_ERR_INVALID
+    s = lib.gevp_update_masked(h.h, 10, A.data_ptr(), 10, A.data_ptr(), 10, None, 1)
+    assert s == gevp.GEVP_ERR_INVALID
+
+
+def test_asynchronous_call_without_info(oracle_mod, h):
+    wl = synth.update_scaled(synth.UPDATE_SMALL, 257, steps=1)
+    A_cur, A_new = list(synth.update_sequence(wl, 8))
+    A = _dev(A_cur)
+    assert h.update_thresholded(A, _dev(A_new), 0.1, want_info=False) is None
+    torch.cuda.synchronize()
+    ref = oracle_mod.threshold_update(A_cur, A_new, 0.1)[0]
+    assert np.array_equal(_bits(A.cpu().numpy()), _bits(ref))
+
+
+def test_masked_update_matches(oracle_mod, h):
+    from paper_1007_4400_amd import gevp
+
+    n = 333
+    wl = synth.update_scaled(synth.UPDATE_SMALL, n, steps=1)
+    A_cur, A_new = list(synth.update_sequence(wl, 9))
+    # the mask from an analysis step drives a fast-iteration update
+    A1 = _dev(A_cur)
+    mask = gevp.empty_mask(n, device="cuda")
+    h.update_thresholded(A1, _dev(A_new), 0.1, mask=mask)
+    A2 = _dev(A_cur)
+    h.update_masked(A2, _dev(A_new), mask)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(A1.cpu().numpy()), _bits(A2.cpu().numpy()))
+    # random words, upper-triangle and beyond-n bits set: only lower bits count
+    rng = np.random.default_rng(10)
+    words = rng.integers(-2**31, 2**31, size=(n, gevp.mask_words(n)), dtype=np.int64).astype(np.int32)
+    mrand = torch.from_numpy(words).to("cuda")
+    A3 = _dev(A_cur)
+    h.update_masked(A3, _dev(A_new), mrand)
+    torch.cuda.synchronize()
+    ref = oracle_mod.masked_update(A_cur, A_new, _unpack(mrand, n))
+    assert np.array_equal(_bits(A3.cpu().numpy()), _bits(ref))
+
+
+def test_truncated_pencil_within_weyl_bound(oracle_mod, h):
+    """Effect on the solve: eigenvalues of the partially updated pencil stay
+    within ||E||_2 / lambda_min(B) of the fully updated one (E the skipped
+    part of the change), solved by the library on both."""
+    n, nev = 300, 16
+    pen, _ = synth.make_pencil(synth.scaled(synth.SMALL, n), 12)
+    wl = synth.update_scaled(synth.UPDATE_SMALL, n, steps=1)
+    A_cur, A_new = list(synth.update_sequence(wl, 13, A0=pen.A))
+    out, _, info = _run(h, A_cur, A_new, 0.1, with_mask=False)
+    assert 0 < info["updated"] < info["entries"]
+    lam_t = h.solve(_dev(out), _dev(pen.B), nev)[0]
+    lam_n = h.solve(_dev(A_new), _dev(pen.B), nev)[0]
+    L = np.tril(out - A_new, -1)
+    E = L + L.conj().T + np.diag((out - A_new).diagonal().real)
+    bound = np.linalg.norm(E, 2) / np.linalg.eigvalsh(pen.B).min()
+    d = np.abs(lam_t.cpu().numpy() - lam_n.cpu().numpy())
+    assert d.max() <= bound + 1e-9 * max(1.0, np.abs(lam_n.cpu().numpy()).max())
+
+
+def test_full_size_step(oracle_mod, h):
+    """One update of the 8192 x 8192 sequence (the measured workload), in the
+    launch configuration the benchmark times, against the oracle entry by
+    entry."""
+    from paper_1007_4400_amd import gevp
+
+    print("update full size n=8192", flush=True)
+    wl = synth.UPDATE_LARGE
+    seq = synth.update_sequence_torch(wl, 0, device="cuda")
+    A0 = gevp.colmajor(next(seq))
+    A1 = gevp.colmajor(next(seq))
+    A_cur = A0.cpu().numpy()
+    A_new = A1.cpu().numpy()
+    del seq
+    mask = gevp.empty_mask(wl.n, device="cuda")
+    info = h.update_thresholded(A0, A1, wl.p_t, mask=mask)
+    out = A0.cpu().numpy()
+    m = _unpack(mask, wl.n)
+    del A0, A1, mask
+    ref, mref, dref, cref = oracle_mod.threshold_update(A_cur, A_new, wl.p_t)
+    assert info["updated"] == cref
+    assert abs(info["delta"] - dref) <= 2.3e-16 * dref
+    assert np.array_equal(m, mref)
+    assert np.array_equal(_bits(out), _bits(ref))
+    assert 0.4 < cref / info["entries"] < 0.8
