@@ -256,6 +256,22 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _calibration_copy():
+    """One 1 GiB device-to-device copy (1 GiB read, 1 GiB written): the
+    reference dispatch that scales the HBM counters of a --pmc run."""
+    import torch
+
+    src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    _mark_push("calibration_copy_1GiB")
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    _mark_pop()
+    del src, dst
+
+
 def _update_apply_bytes(mask_words, n):
     """Bytes the apply kernel has to move for one update, from its mask: a
     tile with no update moves nothing, a tile updated everywhere reads A_new
@@ -303,6 +319,8 @@ def run_update(args):
     As = [gevp.colmajor(A) for A in synth.update_sequence_torch(wl, args.seed)]
     torch.cuda.synchronize()
     log(f"generated {len(As)} matrices n={wl.n} in {time.perf_counter() - t0:.1f}s")
+    if args.calibration_copy:
+        _calibration_copy()
     A_cur = As[0].clone()
     mask = gevp.empty_mask(wl.n, device="cuda")
     entries = wl.n * (wl.n + 1) // 2
@@ -448,15 +466,7 @@ def main():
     log(f"generated {nsteps} steps n={wl.n} in {time.perf_counter() - t0:.1f}s")
 
     if args.calibration_copy:
-        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev)
-        src.fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        _mark_push("calibration_copy_1GiB")
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        _mark_pop()
-        del src, dst
+        _calibration_copy()
 
     opts = gevp.make_opts(precision=args.precision)
     opts64 = gevp.make_opts(precision="fp64")

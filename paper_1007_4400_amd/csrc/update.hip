@@ -18,11 +18,14 @@
 //          traffic), copies tiles whose min is above it without re-reading A,
 //          and re-reads and updates the rest entry by entry; the mask words
 //          are wave ballots (bit r = row r of the column segment);
-//   count  (one work-group) sums the per-tile counts.
+//   count  (one work-group) sums the per-tile counts and gathers the result.
 // Addresses past the matrix edge (ragged last tile) and above the diagonal of a
 // diagonal tile are clamped into the n x n storage and their values discarded,
 // so the loads need no branches; only lower-triangle entries are ever written.
+// The scan's loads are non-temporal (each byte is read once per pass); the
+// apply keeps ordinary loads, which measured faster for the scan that follows.
 #include <cfloat>
+#include <cstring>
 
 #include "common.h"
 
@@ -40,6 +43,13 @@ __device__ __forceinline__ double sqdiff(zd a, zd b) {
   const double r2 = dr * dr;
   const double i2 = di * di;
   return r2 + i2;
+}
+
+__device__ __forceinline__ zd load_nt(const zd* p) {
+  zd v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
 }
 
 // linear lower-triangle tile index t -> (bi, bj), bi >= bj, t = bi(bi+1)/2 + bj
@@ -79,8 +89,8 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_scan(int64_t n, const zd* __re
   for (int c = 0; c < UCOLS; ++c) {
     int64_t j = bj * UT + w + 4 * c;
     j = j < n ? j : n - 1;
-    a[c] = A[ic + j * lda];
-    b[c] = An[ic + j * ldn];
+    a[c] = load_nt(A + ic + j * lda);
+    b[c] = load_nt(An + ic + j * ldn);
   }
   double mx = 0.0, mn = DBL_MAX;
   bool bad = false;
@@ -156,7 +166,9 @@ __device__ __forceinline__ void put_mask(uint32_t* mask, int64_t ldmask, int64_t
   if (l == 32 && bi * UT + 32 < n) mask[j * ldmask + 2 * bi + 1] = (uint32_t)(bits >> 32);
 }
 
-// kind[t]: 0 nothing updated, 1 entry-by-entry, 2 copied whole
+// kind[t]: 0 nothing updated, 1 entry-by-entry, 2 copied whole.  A tile below
+// the diagonal also clears the mask words of its mirror tile above the
+// diagonal (bits that are never set), so every word of rows < n is written.
 __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
     int64_t n, zd* __restrict__ A, int64_t lda, const zd* __restrict__ An, int64_t ldn,
     const double* __restrict__ tmax, const double* __restrict__ tmin, const double* __restrict__ scal,
@@ -170,6 +182,10 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
   const double thr = scal[1];
   const bool none = flag[0] != 0 || !(tmax[blockIdx.x] > thr);
   const bool all = !none && tmin[blockIdx.x] > thr;
+  if (mask && bi > bj && threadIdx.x < 2 * UT) {
+    const int64_t jm = bi * UT + (threadIdx.x >> 1);
+    if (jm < n) mask[jm * ldmask + 2 * bj + (threadIdx.x & 1)] = 0u;
+  }
   int cnt = 0;
   if (none) {
     if (mask) {
@@ -225,19 +241,13 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
   }
 }
 
-// Mask words above the diagonal tile of each column (rows < 64 * (j / 64)) are
-// cleared: those bits are never set.
-__global__ __launch_bounds__(64) void k_upd_mask_upper(int64_t n, uint32_t* __restrict__ mask,
-                                                       int64_t ldmask) {
-  const int64_t j = blockIdx.x;
-  const int64_t words = 2 * (j / UT);
-  for (int64_t k = threadIdx.x; k < words; k += 64) mask[j * ldmask + k] = 0u;
-}
-
 // out[0] = entries updated, out[1] = tiles with any update, out[2] = tiles
-// copied whole
+// copied whole, out[3] = the non-finite flag, out[4] = delta's bits: the whole
+// result in one block for a single copy to the host
 __global__ __launch_bounds__(1024) void k_upd_count(int64_t tiles, const int* __restrict__ tcnt,
                                                     const int* __restrict__ tkind,
+                                                    const double* __restrict__ scal,
+                                                    const int* __restrict__ flag,
                                                     long long* __restrict__ out) {
   __shared__ long long s0[16], s1[16], s2[16];
   long long c0 = 0, c1 = 0, c2 = 0;
@@ -269,6 +279,8 @@ __global__ __launch_bounds__(1024) void k_upd_count(int64_t tiles, const int* __
     out[0] = a;
     out[1] = b;
     out[2] = c;
+    out[3] = flag[0];
+    out[4] = __double_as_longlong(scal[2]);
   }
 }
 
@@ -322,7 +334,7 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   GEVP_HIP_TRY(hipSetDevice(h->device));
   const size_t need = 2 * ws_round(sizeof(double) * tiles) + 3 * ws_round(sizeof(int) * tiles) +
                       ws_round(sizeof(double) * 4) + ws_round(sizeof(int) * 4) +
-                      ws_round(sizeof(long long) * 4) + 256;
+                      ws_round(sizeof(long long) * 8) + 256;
   GEVP_TRY(ws_reserve(h, need));
   double* tmax = (double*)ws_take(h, sizeof(double) * tiles);
   double* tmin = (double*)ws_take(h, sizeof(double) * tiles);
@@ -331,7 +343,7 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   int* tkind = (int*)ws_take(h, sizeof(int) * tiles);
   double* scal = (double*)ws_take(h, sizeof(double) * 4);
   int* flag = (int*)ws_take(h, sizeof(int) * 4);
-  long long* out = (long long*)ws_take(h, sizeof(long long) * 4);
+  long long* out = (long long*)ws_take(h, sizeof(long long) * 8);
   zd* A = (zd*)A_;
   const zd* An = (const zd*)An_;
   // profiling flag 2: event pairs around the scan and the apply launch
@@ -346,21 +358,16 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   if (timed) GEVP_TRY(fev_mark(h));
   hipLaunchKernelGGL(k_upd_delta, dim3(1), dim3(1024), 0, h->stream, tiles, tmax, tbad, p_t, scal,
                      flag);
-  if (mask)
-    hipLaunchKernelGGL(k_upd_mask_upper, dim3((unsigned)n), dim3(64), 0, h->stream, n, mask, ldmask);
   if (timed) GEVP_TRY(fev_mark(h));
   hipLaunchKernelGGL(k_upd_apply, dim3((unsigned)tiles), dim3(UTHREADS), 0, h->stream, n, A, lda,
                      An, ldn, tmax, tmin, scal, flag, mask, ldmask, tcnt, tkind);
   GEVP_HIP_TRY(hipGetLastError());
   if (timed) GEVP_TRY(fev_mark(h));
   if (!info) return GEVP_OK;
-  hipLaunchKernelGGL(k_upd_count, dim3(1), dim3(1024), 0, h->stream, tiles, tcnt, tkind, out);
+  hipLaunchKernelGGL(k_upd_count, dim3(1), dim3(1024), 0, h->stream, tiles, tcnt, tkind, scal, flag,
+                     out);
   GEVP_HIP_TRY(hipGetLastError());
-  double hs[4];
-  int hf[4];
-  long long ho[4];
-  GEVP_HIP_TRY(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
-  GEVP_HIP_TRY(hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, h->stream));
+  long long ho[5];
   GEVP_HIP_TRY(hipMemcpyAsync(ho, out, sizeof(ho), hipMemcpyDeviceToHost, h->stream));
   GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
   if (timed) {
@@ -371,12 +378,14 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
     info->apply_ms = ms1;
     h->fev_used = 0;
   }
-  info->nonfinite = hf[0];
-  info->delta = hf[0] ? __builtin_nan("") : hs[2];
+  double delta;
+  memcpy(&delta, &ho[4], sizeof(delta));
+  info->nonfinite = (int)ho[3];
+  info->delta = ho[3] ? __builtin_nan("") : delta;
   info->updated = ho[0];
   info->tiles_touched = ho[1];
   info->tiles_copied = ho[2];
-  return hf[0] ? GEVP_ERR_NONFINITE : GEVP_OK;
+  return ho[3] ? GEVP_ERR_NONFINITE : GEVP_OK;
 }
 
 gevp_status gevp_update_masked(gevp_handle h, int64_t n, void* A_, int64_t lda, const void* S_,
