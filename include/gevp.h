@@ -51,7 +51,9 @@ typedef enum {
   GEVP_ERR_NOCONV = 3,     /* maxit reached; outputs hold the best pairs and residuals */
   GEVP_ERR_HIP = 4,        /* a HIP runtime call failed */
   GEVP_ERR_NONFINITE = 5,  /* NaN or Inf in A, B or X0 */
-  GEVP_ERR_ALLOC = 6       /* workspace allocation failed */
+  GEVP_ERR_ALLOC = 6,      /* workspace allocation failed */
+  GEVP_ERR_SINGULAR = 7    /* a shifted matrix of the contour filter had a zero or
+                              non-finite pivot */
 } gevp_status;
 
 typedef enum {
@@ -73,8 +75,22 @@ typedef struct {
   int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 8 */
   int seed_monitor;         /* 1: with a seed X0, report how it relates to the result
                                (gevp_info seed_*; needs the final residual check) */
-  int reserved[6];
+  int filter;               /* gevp_filter; default GEVP_FILTER_CHEBYSHEV */
+  int contour_points;       /* quadrature nodes of the contour filter; 0 = 16 */
+  int reserved[4];
 } gevp_opts;
+
+/* Filter of the subspace iteration.  The contour filter (section 3 names a
+ * Sakurai-Sugiura solver as a candidate for the fast iterations) applies
+ * sum_j w_j (z_j I - C)^{-1} to the block, the trapezoidal rule on a circle
+ * around the wanted eigenvalues (see gevp_k_contour_filter).  It needs the
+ * Ritz values of a seed to place the circle, so it is used for seeded solves
+ * with k0 > nev; other solves take the Chebyshev filter.  Its factorisations
+ * and solves are FP64 whatever opts.precision says. */
+typedef enum {
+  GEVP_FILTER_CHEBYSHEV = 0,
+  GEVP_FILTER_CONTOUR = 1
+} gevp_filter;
 
 /* Diagnostics, filled on return when a non-NULL pointer is passed. */
 typedef struct {
@@ -103,6 +119,12 @@ typedef struct {
   double seed_sin_rms;
   double seed_dev_mean, seed_dev_max;
   int seed_reindexed;
+  /* Contour filter (opts.filter = GEVP_FILTER_CONTOUR and used): the circle's
+     diameter [contour_a, contour_b], its nodes, and how many times the filter
+     was applied; 0 otherwise. */
+  int contour_points;
+  double contour_a, contour_b;
+  int contour_applications;
 } gevp_info;
 
 typedef enum {
@@ -244,6 +266,35 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
  * Synchronous. */
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
                         double* theta, void* Z, int64_t ldz);
+
+/* ------------------------------------------------------------------------
+ * Contour-integral filter pieces (section 3: Sakurai-Sugiura solver named as
+ * a candidate for the fast iterations; trapezoidal quadrature of the
+ * resolvent on a circle, first moment).
+ * ------------------------------------------------------------------------ */
+
+/* LU factorisation without row exchanges of z I - C, z = zr + i zi:
+ * LU (n x n, ld ldlu) receives the packed factors (L unit lower strictly
+ * below the diagonal, U on and above).  C (device complex128 n x n) is read in
+ * full.  For Hermitian C and zi != 0 every pivot is nonzero in exact
+ * arithmetic (-i (z I - C) has Hermitian part zi I); for other inputs the
+ * factorisation may break down.  Synchronous; returns GEVP_ERR_SINGULAR with
+ * *pivot = the first zero or non-finite pivot (1-based), else *pivot = 0. */
+gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t ldc, double zr,
+                              double zi, void* LU, int64_t ldlu, int64_t* pivot);
+
+/* Y = sum_j w_j (z_j I - C)^{-1} V for the nq-point trapezoidal rule on the
+ * circle with diameter [a, b] on the real axis:
+ *   z_j = gamma + rho e^{i t_j}, w_j = rho e^{i t_j} / nq,
+ *   t_j = 2 pi (j + 1/2) / nq, gamma = (a + b) / 2, rho = (b - a) / 2,
+ * so an eigenvector of a Hermitian C with eigenvalue lambda is scaled by
+ * 1 / (1 + t^nq), t = (lambda - gamma) / rho.  C: device complex128 n x n
+ * (read in full); V: n x m; Y: n x m (must not overlap V); a < b finite,
+ * 1 <= nq <= 256.  Factors every z_j I - C (workspace nq n^2 complex128).
+ * Synchronous; GEVP_ERR_SINGULAR if a factorisation broke down. */
+gevp_status gevp_k_contour_filter(gevp_handle h, int64_t n, const void* C, int64_t ldc,
+                                  const void* V, int64_t ldv, int64_t m, double a, double b, int nq,
+                                  void* Y, int64_t ldy);
 
 /* ------------------------------------------------------------------------
  * Thresholded partial update of a Hermitian matrix between two SCF

@@ -59,6 +59,8 @@ struct gevp_ctx {
   hipEvent_t pev[2] = {nullptr, nullptr};
   // per-stream sub-contexts of gevp_solve_batched (own stream and workspace)
   std::vector<gevp_ctx*> workers;
+  // streams of the contour filter's independent quadrature nodes (on demand)
+  std::vector<gevp_ctx*> qctx;
   bool owns_stream = false;
 };
 
@@ -104,6 +106,24 @@ gevp_status trsm_right_lower_c_lowerpart(gevp_ctx* c, int64_t n, const zd* L, in
 // Inverses of the 64 x 64 diagonal blocks of an already factored L.
 gevp_status diag_block_inverses(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl, zd* Dinv,
                                 int64_t ldi);
+
+// Contour-integral filter (contour.hip).  lu_nopiv: M = L U in place without
+// row exchanges (L unit lower, packed), DinvL / DinvU (n x 64, ld ldi) receive
+// the inverses of the 64 x 64 diagonal blocks of L and U, *info_dev the first
+// failing pivot.  contour_factor forms and factors z_j I - C for the nq nodes
+// of the circle with diameter [a, b] into `work` (contour_work_bytes(n, mmax,
+// nq)), *pivot = first failing pivot or 0 (waits for the result);
+// contour_apply then forms Y = sum_j w_j (z_j I - C)^{-1} V for m <= mmax
+// columns (Y must not overlap V).
+gevp_status lu_nopiv(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* DinvL, zd* DinvU,
+                     int64_t ldi, int* info_dev);
+gevp_status trsm_left_upper_n(gevp_ctx* c, int64_t n, int64_t m, const zd* U, int64_t ldu,
+                              const zd* DinvU, int64_t ldi, zd* R, int64_t ldr);
+size_t contour_work_bytes(int64_t n, int64_t mmax, int nq);
+gevp_status contour_factor(gevp_ctx* c, int64_t n, const zd* C, int64_t ldc, double a, double b,
+                           int nq, void* work, int64_t mmax, int* pivot);
+gevp_status contour_apply(gevp_ctx* c, int64_t n, int64_t m, const zd* V, int64_t ldv, zd* Y,
+                          int64_t ldy, double a, double b, int nq, void* work, int64_t mmax);
 
 // Small Hermitian eigensolver (n <= 2048): H (full storage, overwritten),
 // theta ascending, Z (n x n) unitary.  work >= heev_work_bytes(n).

@@ -1,0 +1,452 @@
+// Contour-integral filter (Sakurai-Sugiura), FP64 complex.
+//
+// The paper names a Sakurai-Sugiura eigensolver as a candidate for the fast
+// iterations (section 3) without details; this is the published method's
+// first moment with Rayleigh-Ritz extraction: for the reduced C = L^{-1} A L^{-H}
+// and a circle through a < b on the real axis, the spectral projector onto
+// the eigenvalues inside is approximated by the trapezoidal rule
+//     Y = sum_j w_j (z_j I - C)^{-1} V,
+//     z_j = gamma + rho e^{i t_j},  w_j = rho e^{i t_j} / nq,  t_j = 2 pi (j + 1/2) / nq,
+// which acts on an eigenvector with eigenvalue lambda as 1 / (1 + t^nq),
+// t = (lambda - gamma) / rho.
+//
+// Each shifted matrix M_j = z_j I - C is factored once, M_j = L_j U_j, without
+// row exchanges: -i M_j has Hermitian part Im(z_j) I, positive definite, so
+// every leading block is nonsingular and the growth stays bounded.  The
+// factorisation is right-looking with 64-wide blocks: one work-group factors a
+// diagonal block in registers and writes the inverses of its two triangles,
+// the panels are products with those inverses, and the trailing update is one
+// FP64 matrix-core GEMM per block.  The nq factorisations are independent and
+// run on up to four streams, so one factorisation's latency-bound diagonal
+// blocks overlap another's GEMMs.  Applying the filter is two triangular
+// solves per node (the existing recursive lower solve with the unit-lower
+// block inverses, and an upper solve written here), accumulated with the
+// complex weights.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+constexpr int NB = 64;
+constexpr int QSTREAMS = 4;
+
+__device__ __forceinline__ zd zmul(zd a, zd b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ zd zsub(zd a, zd b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// One 64 x 64 diagonal block (kb <= 64 rows and columns in use, the rest
+// padded with the identity): M = L U in place without row exchanges (L unit
+// lower, stored strictly below the diagonal), then inv(L) into DinvL and
+// inv(U) into DinvU (64 x 64 each, leading dimension ldi).  Thread t holds
+// row i = t % 64 at columns c = t / 64 + 4 m (m = 0..15) in registers.  Step
+// k reads the pivot row and column k from double-buffered LDS (one barrier
+// per step); the next step's row and column are published from inside the
+// unrolled update loop under a per-element test, so every register index is a
+// constant.  *info receives goff + the first failing pivot (1-based).
+__global__ __launch_bounds__(256) void k_getrf_block(zd* M, int64_t ldm, int kb, zd* DinvL,
+                                                     zd* DinvU, int64_t ldi, int* info, int goff) {
+  __shared__ zd rowb[2][NB], colb[2][NB];
+  __shared__ zd rowl[2][NB], coll[2][NB], rowu[2][NB], colu[2][NB];
+  __shared__ zd dinv[NB];
+  const int tid = threadIdx.x, i = tid & 63, cg = tid >> 6;
+  zd a[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = cg + 4 * m;
+    a[m] = (i < kb && j < kb) ? M[i + (int64_t)j * ldm] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    if (i == 0) rowb[0][j] = a[m];
+    if (j == 0) colb[0][i] = a[m];
+  }
+  // factorisation
+  for (int k = 0; k < NB; ++k) {
+    const int b = k & 1, nb = b ^ 1;
+    __syncthreads();
+    if (i > k) {
+      const zd p = rowb[b][k];
+      const double d = p.x * p.x + p.y * p.y;
+      const zd ip = make_double2(p.x / d, -p.y / d);
+      const zd l = zmul(colb[b][i], ip);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int j = cg + 4 * m;
+        if (j > k) a[m] = zsub(a[m], zmul(l, rowb[b][j]));
+        if (j == k) a[m] = l;
+        if (j == k + 1) colb[nb][i] = a[m];
+        if (i == k + 1) rowb[nb][j] = a[m];
+      }
+    }
+    if (tid == 0) {
+      const zd p = rowb[b][k];
+      const double d = p.x * p.x + p.y * p.y;
+      if (!(d > 0.0) || !isfinite(d)) atomicMin(info, goff + k + 1);
+    }
+  }
+  // store the factors; diagonal inverses of U for the backward sweep; the
+  // first step's operands of the inverse sweeps
+  zd bl[16], bu[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = cg + 4 * m;
+    if (i < kb && j < kb) M[i + (int64_t)j * ldm] = a[m];
+    if (j == i) {
+      const double d = a[m].x * a[m].x + a[m].y * a[m].y;
+      dinv[i] = make_double2(a[m].x / d, -a[m].y / d);
+    }
+    const double e = (j == i) ? 1.0 : 0.0;
+    bl[m] = make_double2(e, 0.0);
+    bu[m] = make_double2(e, 0.0);
+    if (i == 0) rowl[0][j] = bl[m];  // row 0 of inv(L)
+    if (j == 0) coll[0][i] = a[m];   // l_i0
+    if (j == NB - 1) colu[0][i] = a[m];  // u_i,63
+  }
+  __syncthreads();
+  if (i == NB - 1) {  // row 63 of inv(U)
+    const zd di = dinv[NB - 1];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      bu[m] = zmul(bu[m], di);
+      rowu[0][cg + 4 * m] = bu[m];
+    }
+  }
+  // inverses: forward sweep for L (unit lower, step k) and backward sweep for
+  // U (row ku = 63 - k) together; bl, bu hold rows of the right-hand sides I
+  for (int k = 0; k < NB; ++k) {
+    const int b = k & 1, nb = b ^ 1, ku = NB - 1 - k;
+    __syncthreads();
+    if (i > k) {
+      const zd l = coll[b][i];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) bl[m] = zsub(bl[m], zmul(l, rowl[b][cg + 4 * m]));
+    }
+    if (i < ku) {
+      const zd u = colu[b][i];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) bu[m] = zsub(bu[m], zmul(u, rowu[b][cg + 4 * m]));
+    }
+    // next step's operands: row k+1 of inv(L) is final now; row ku-1 of
+    // inv(U) is final once divided by its pivot
+    if (k + 1 < NB) {
+      const zd di = dinv[ku - 1];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int j = cg + 4 * m;
+        if (i == k + 1) rowl[nb][j] = bl[m];
+        if (i == ku - 1) {
+          bu[m] = zmul(bu[m], di);
+          rowu[nb][j] = bu[m];
+        }
+        if (j == k + 1) coll[nb][i] = a[m];
+        if (j == ku - 1) colu[nb][i] = a[m];
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = cg + 4 * m;
+    if (i < kb) {
+      DinvL[i + (int64_t)j * ldi] = bl[m];
+      DinvU[i + (int64_t)j * ldi] = bu[m];
+    }
+  }
+}
+
+// M = z I - C (n x n, both full storage)
+__global__ __launch_bounds__(256) void k_shift_neg(int64_t n, const zd* __restrict__ C, int64_t ldc,
+                                                   double zr, double zi, zd* __restrict__ M,
+                                                   int64_t ldm) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const zd c = C[i + j * ldc];
+    M[i + j * ldm] = (i == j) ? make_double2(zr - c.x, zi - c.y) : make_double2(-c.x, -c.y);
+  }
+}
+
+// Y = w T (first) or Y += w T, complex scalar w, rows x cols
+__global__ __launch_bounds__(256) void k_zaxpy_cols(int64_t rows, double wr, double wi,
+                                                    const zd* __restrict__ T, int64_t ldt,
+                                                    zd* __restrict__ Y, int64_t ldy, int first) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256) {
+    const zd t = T[i + j * ldt];
+    const zd v = make_double2(wr * t.x - wi * t.y, wr * t.y + wi * t.x);
+    if (first) {
+      Y[i + j * ldy] = v;
+    } else {
+      const zd y = Y[i + j * ldy];
+      Y[i + j * ldy] = make_double2(y.x + v.x, y.y + v.y);
+    }
+  }
+}
+
+// Y = S1 + S2 + ... (up to QSTREAMS partial sums, column-major rows x cols)
+__global__ __launch_bounds__(256) void k_sum_parts(int64_t rows, int parts, const zd* __restrict__ S,
+                                                   int64_t lds, int64_t pstride, zd* __restrict__ Y,
+                                                   int64_t ldy) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256) {
+    zd s = S[i + j * lds];
+    for (int p = 1; p < parts; ++p) {
+      const zd t = S[p * pstride + i + j * lds];
+      s.x += t.x;
+      s.y += t.y;
+    }
+    Y[i + j * ldy] = s;
+  }
+}
+
+inline dim3 grid_cols(int64_t rows, int64_t cols) {
+  int64_t gx = (rows + 255) / 256;
+  if (gx > 16) gx = 16;
+  return dim3((unsigned)gx, (unsigned)cols);
+}
+
+inline int64_t split64(int64_t n) { return ((n / 2 + NB - 1) / NB) * NB; }
+
+// quadrature stream i of the handle (created once, non-blocking, default priority)
+gevp_status quad_ctx(gevp_ctx* c, int i, gevp_ctx** out) {
+  while ((int)c->qctx.size() <= i) {
+    gevp_ctx* w = new gevp_ctx();
+    w->device = c->device;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete w;
+      return GEVP_ERR_HIP;
+    }
+    w->owns_stream = true;
+    w->inner_streams = false;
+    c->qctx.push_back(w);
+  }
+  *out = c->qctx[i];
+  return GEVP_OK;
+}
+
+// The quadrature streams start after the work queued on c's stream; every
+// exit waits for them (they write workspace the next call reuses).
+struct QuadStreams {
+  gevp_ctx* c;
+  int count = 0;
+  gevp_ctx* s[QSTREAMS] = {};
+  hipEvent_t fork = nullptr, join[QSTREAMS] = {};
+  explicit QuadStreams(gevp_ctx* ctx) : c(ctx) {}
+  gevp_status open(int want) {
+    if (!c->inner_streams || want <= 1) {
+      count = 1;
+      s[0] = c;
+      return GEVP_OK;
+    }
+    count = want < QSTREAMS ? want : QSTREAMS;
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventRecord(fork, c->stream));
+    for (int q = 0; q < count; ++q) {
+      GEVP_TRY(quad_ctx(c, q, &s[q]));
+      GEVP_HIP_TRY(hipEventCreateWithFlags(&join[q], hipEventDisableTiming));
+      GEVP_HIP_TRY(hipStreamWaitEvent(s[q]->stream, fork, 0));
+    }
+    return GEVP_OK;
+  }
+  gevp_status close() {
+    if (s[0] == c) return GEVP_OK;
+    for (int q = 0; q < count; ++q) {
+      GEVP_HIP_TRY(hipEventRecord(join[q], s[q]->stream));
+      GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, join[q], 0));
+    }
+    return GEVP_OK;
+  }
+  ~QuadStreams() {
+    if (s[0] && s[0] != c)
+      for (int q = 0; q < count; ++q) (void)hipStreamSynchronize(s[q]->stream);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+struct ContourLayout {
+  zd* LU;
+  zd* DinvL;
+  zd* DinvU;
+  zd* T;    // per stream: n x m solve buffer
+  zd* Acc;  // per stream: n x m partial sum
+  int* info;
+  size_t lu_stride, dinv_stride, blk_stride;
+};
+
+ContourLayout carve(void* work, int64_t n, int64_t m, int nq) {
+  ContourLayout L;
+  char* p = (char*)work;
+  L.lu_stride = (size_t)n * n;
+  L.dinv_stride = (size_t)n * NB;
+  L.blk_stride = (size_t)n * m;
+  L.LU = (zd*)p;
+  p += ws_round(sizeof(zd) * L.lu_stride * nq);
+  L.DinvL = (zd*)p;
+  p += ws_round(sizeof(zd) * L.dinv_stride * nq);
+  L.DinvU = (zd*)p;
+  p += ws_round(sizeof(zd) * L.dinv_stride * nq);
+  L.T = (zd*)p;
+  p += ws_round(sizeof(zd) * L.blk_stride * QSTREAMS);
+  L.Acc = (zd*)p;
+  p += ws_round(sizeof(zd) * L.blk_stride * QSTREAMS);
+  L.info = (int*)p;
+  return L;
+}
+
+void node(double a, double b, int nq, int j, zd* z, zd* w) {
+  const double gamma = 0.5 * (a + b), rho = 0.5 * (b - a);
+  const double t = 6.283185307179586476925 * (j + 0.5) / nq;
+  const double ct = std::cos(t), st = std::sin(t);
+  *z = make_double2(gamma + rho * ct, rho * st);
+  *w = make_double2(rho * ct / nq, rho * st / nq);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+gevp_status lu_nopiv(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* DinvL, zd* DinvU,
+                     int64_t ldi, int* info_dev) {
+  for (int64_t r0 = 0; r0 < n; r0 += NB) {
+    const int64_t kb = std::min<int64_t>(NB, n - r0), rest = n - r0 - kb;
+    zd* Mkk = M + r0 + r0 * ldm;
+    hipLaunchKernelGGL(k_getrf_block, dim3(1), dim3(256), 0, c->stream, Mkk, ldm, (int)kb, DinvL + r0,
+                       DinvU + r0, ldi, info_dev, (int)r0);
+    GEVP_HIP_TRY(hipGetLastError());
+    if (rest > 0) {
+      zd* A21 = Mkk + kb;
+      zd* A12 = Mkk + kb * ldm;
+      zd* A22 = Mkk + kb + kb * ldm;
+      // L21 = A21 U11^{-1}, U12 = L11^{-1} A12: in place, one 64-wide output
+      // tile side, so every tile reads its whole K range before it writes
+      GEVP_TRY(launch_zgemm(c, 0, 0, rest, kb, kb, 1.0, A21, ldm, DinvU + r0, ldi, 0.0, nullptr, 0,
+                            0.0, nullptr, 0, nullptr, A21, ldm));
+      GEVP_TRY(launch_zgemm(c, 0, 0, kb, rest, kb, 1.0, DinvL + r0, ldi, A12, ldm, 0.0, nullptr, 0,
+                            0.0, nullptr, 0, nullptr, A12, ldm));
+      GEVP_TRY(launch_zgemm(c, 0, 0, rest, rest, kb, -1.0, A21, ldm, A12, ldm, 1.0, A22, ldm, 0.0,
+                            nullptr, 0, nullptr, A22, ldm));
+    }
+  }
+  return GEVP_OK;
+}
+
+// R (n x m) <- U^{-1} R, U upper triangular (the upper part of a packed LU)
+gevp_status trsm_left_upper_n(gevp_ctx* c, int64_t n, int64_t m, const zd* U, int64_t ldu,
+                              const zd* DinvU, int64_t ldi, zd* R, int64_t ldr) {
+  if (n <= 0 || m <= 0) return GEVP_OK;
+  if (n <= NB)
+    return launch_zgemm(c, 0, 0, n, m, n, 1.0, DinvU, ldi, R, ldr, 0.0, nullptr, 0, 0.0, nullptr,
+                        0, nullptr, R, ldr);
+  const int64_t h = split64(n);
+  GEVP_TRY(trsm_left_upper_n(c, n - h, m, U + h + h * ldu, ldu, DinvU + h, ldi, R + h, ldr));
+  // R1 -= U12 R2   (U12 = U[:h, h:])
+  GEVP_TRY(launch_zgemm(c, 0, 0, h, m, n - h, -1.0, U + h * ldu, ldu, R + h, ldr, 1.0, R, ldr, 0.0,
+                        nullptr, 0, nullptr, R, ldr));
+  return trsm_left_upper_n(c, h, m, U, ldu, DinvU, ldi, R, ldr);
+}
+
+size_t contour_work_bytes(int64_t n, int64_t m, int nq) {
+  return ws_round(sizeof(zd) * (size_t)n * n * nq) + 2 * ws_round(sizeof(zd) * (size_t)n * NB * nq) +
+         2 * ws_round(sizeof(zd) * (size_t)n * m * QSTREAMS) + ws_round(sizeof(int) * 4) + 256;
+}
+
+gevp_status contour_factor(gevp_ctx* c, int64_t n, const zd* C, int64_t ldc, double a, double b,
+                           int nq, void* work, int64_t mmax, int* pivot) {
+  ContourLayout L = carve(work, n, mmax, nq);
+  const int big = 0x7fffffff;
+  GEVP_HIP_TRY(hipMemcpyAsync(L.info, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  QuadStreams qs(c);
+  GEVP_TRY(qs.open(nq));
+  for (int j = 0; j < nq; ++j) {
+    gevp_ctx* s = qs.s[j % qs.count];
+    zd z, w;
+    node(a, b, nq, j, &z, &w);
+    zd* M = L.LU + L.lu_stride * j;
+    hipLaunchKernelGGL(k_shift_neg, dim3((unsigned)((n + 255) / 256 < 16 ? (n + 255) / 256 : 16),
+                                         (unsigned)n),
+                       dim3(256), 0, s->stream, n, C, ldc, z.x, z.y, M, n);
+    GEVP_HIP_TRY(hipGetLastError());
+    GEVP_TRY(lu_nopiv(s, n, M, n, L.DinvL + L.dinv_stride * j, L.DinvU + L.dinv_stride * j, n,
+                      L.info));
+  }
+  GEVP_TRY(qs.close());
+  int f = big;
+  GEVP_HIP_TRY(hipMemcpyAsync(&f, L.info, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+  *pivot = (f == big) ? 0 : f;
+  return GEVP_OK;
+}
+
+gevp_status contour_apply(gevp_ctx* c, int64_t n, int64_t m, const zd* V, int64_t ldv, zd* Y,
+                          int64_t ldy, double a, double b, int nq, void* work, int64_t mmax) {
+  if (m <= 0) return GEVP_OK;
+  ContourLayout L = carve(work, n, mmax, nq);
+  QuadStreams qs(c);
+  GEVP_TRY(qs.open(nq));
+  std::vector<int> firsts(qs.count, 1);
+  for (int j = 0; j < nq; ++j) {
+    const int q = j % qs.count;
+    gevp_ctx* s = qs.s[q];
+    zd z, w;
+    node(a, b, nq, j, &z, &w);
+    zd* T = L.T + L.blk_stride * q;
+    zd* Acc = L.Acc + L.blk_stride * q;
+    const zd* LU = L.LU + L.lu_stride * j;
+    GEVP_TRY(launch_copy2d(s, n, m, V, ldv, T, n));
+    GEVP_TRY(trsm_left_lower_n(s, n, m, LU, n, L.DinvL + L.dinv_stride * j, n, T, n));
+    GEVP_TRY(trsm_left_upper_n(s, n, m, LU, n, L.DinvU + L.dinv_stride * j, n, T, n));
+    hipLaunchKernelGGL(k_zaxpy_cols, grid_cols(n, m), dim3(256), 0, s->stream, n, w.x, w.y, T, n,
+                       Acc, n, firsts[q]);
+    GEVP_HIP_TRY(hipGetLastError());
+    firsts[q] = 0;
+  }
+  GEVP_TRY(qs.close());
+  hipLaunchKernelGGL(k_sum_parts, grid_cols(n, m), dim3(256), 0, c->stream, n, qs.count, L.Acc, n,
+                     (int64_t)L.blk_stride, Y, ldy);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+extern "C" {
+
+gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t ldc, double zr,
+                              double zi, void* LU, int64_t ldlu, int64_t* pivot) {
+  if (!h || n < 1 || !C || ldc < n || !LU || ldlu < n || !std::isfinite(zr) || !std::isfinite(zi))
+    return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, 2 * ws_round(sizeof(zd) * n * NB) + ws_round(sizeof(int) * 4) + 256));
+  zd* DL = (zd*)ws_take(h, sizeof(zd) * n * NB);
+  zd* DU = (zd*)ws_take(h, sizeof(zd) * n * NB);
+  int* info = (int*)ws_take(h, sizeof(int) * 4);
+  const int big = 0x7fffffff;
+  GEVP_HIP_TRY(hipMemcpyAsync(info, &big, sizeof(int), hipMemcpyHostToDevice, h->stream));
+  hipLaunchKernelGGL(k_shift_neg, dim3((unsigned)((n + 255) / 256 < 16 ? (n + 255) / 256 : 16),
+                                       (unsigned)n),
+                     dim3(256), 0, h->stream, n, (const zd*)C, ldc, zr, zi, (zd*)LU, ldlu);
+  GEVP_HIP_TRY(hipGetLastError());
+  GEVP_TRY(lu_nopiv(h, n, (zd*)LU, ldlu, DL, DU, n, info));
+  int f = big;
+  GEVP_HIP_TRY(hipMemcpyAsync(&f, info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
+  if (pivot) *pivot = (f == big) ? 0 : f;
+  return (f == big) ? GEVP_OK : GEVP_ERR_SINGULAR;
+}
+
+gevp_status gevp_k_contour_filter(gevp_handle h, int64_t n, const void* C, int64_t ldc,
+                                  const void* V, int64_t ldv, int64_t m, double a, double b, int nq,
+                                  void* Y, int64_t ldy) {
+  if (!h || n < 1 || !C || ldc < n || !V || ldv < n || m < 0 || !Y || ldy < n)
+    return GEVP_ERR_INVALID;
+  if (!(a < b) || !std::isfinite(a) || !std::isfinite(b) || nq < 1 || nq > 256)
+    return GEVP_ERR_INVALID;
+  if (m == 0) return GEVP_OK;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, contour_work_bytes(n, m, nq) + 256));
+  void* work = ws_take(h, contour_work_bytes(n, m, nq));
+  int piv = 0;
+  GEVP_TRY(contour_factor(h, n, (const zd*)C, ldc, a, b, nq, work, m, &piv));
+  if (piv) return GEVP_ERR_SINGULAR;
+  GEVP_TRY(contour_apply(h, n, m, (const zd*)V, ldv, (zd*)Y, ldy, a, b, nq, work, m));
+  GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
+  return GEVP_OK;
+}
+
+}  // extern "C"

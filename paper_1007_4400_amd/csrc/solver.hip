@@ -83,6 +83,7 @@ struct Opts {
   unsigned long long seed;
   int skip_final;
   int seed_monitor;
+  int filter, nq;
 };
 
 Opts resolve(const gevp_opts* o, int64_t nev) {
@@ -103,6 +104,8 @@ Opts resolve(const gevp_opts* o, int64_t nev) {
   r.seed = o ? o->seed : 0ull;
   r.skip_final = o ? o->skip_final_residual : 0;
   r.seed_monitor = o ? o->seed_monitor : 0;
+  r.filter = o ? o->filter : 0;
+  r.nq = (o && o->contour_points > 0) ? o->contour_points : 16;
   return r;
 }
 
@@ -226,6 +229,7 @@ const char* gevp_status_string(gevp_status s) {
     case GEVP_ERR_HIP: return "HIP runtime error";
     case GEVP_ERR_NONFINITE: return "NaN or Inf in the input";
     case GEVP_ERR_ALLOC: return "workspace allocation failed";
+    case GEVP_ERR_SINGULAR: return "zero or non-finite pivot in a shifted factorisation";
   }
   return "unknown status";
 }
@@ -261,6 +265,8 @@ void gevp_destroy(gevp_handle h) {
   (void)hipSetDevice(h->device);
   for (gevp_ctx* w : h->workers) gevp_destroy(w);
   h->workers.clear();
+  for (gevp_ctx* w : h->qctx) gevp_destroy(w);
+  h->qctx.clear();
   if (h->aux) gevp_destroy(h->aux);
   h->aux = nullptr;
   if (h->panel) gevp_destroy(h->panel);
@@ -334,6 +340,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   const Opts o = resolve(opts, nev);
   if (o.precision != GEVP_FP64 && o.precision != GEVP_FP32 && o.precision != GEVP_BF16X3)
     return bad(2);
+  if (o.filter != GEVP_FILTER_CHEBYSHEV && o.filter != GEVP_FILTER_CONTOUR) return bad(2);
+  if (o.nq < 1 || o.nq > 256) return bad(2);
   const bool mixed = (o.precision != GEVP_FP64);
   const bool bf16 = (o.precision == GEVP_BF16X3);
   const int64_t nb = block_of(o, n, nev);
@@ -344,6 +352,10 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (!X_ || ldx < n) return bad(16);
   if (nb > 2048) return bad(11);  // Rayleigh-Ritz eigensolver limit
   const bool seeded = (X0_ != nullptr && k0 > 0);
+  // the contour filter places its circle from the seed's Ritz values, which
+  // needs the first unwanted one (column nev) to come from the seed
+  const bool contour = o.filter == GEVP_FILTER_CONTOUR && seeded && k0 > nev && nb > nev;
+  const bool lp = mixed && !contour;  // low-precision Chebyshev filter in use
   GEVP_HIP_TRY(hipSetDevice(h->device));
   gevp_ctx* c = h;
   c->fev_used = 0;
@@ -373,8 +385,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
   need += ws_round(sizeof(double) * 4);                  // norms
   need += ws_round(sizeof(double) * (3 * nb + 4));       // seed monitor
+  if (contour) need += contour_work_bytes(n, nb, o.nq);  // nq factorisations
   const size_t lp_elem = 8;                              // complex64
-  if (mixed) {
+  if (lp) {
     need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
     if (bf16) need += bf16_filter_work_bytes(n, nb);     // iterate planes, split-K partials
     need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
@@ -413,6 +426,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
   double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 4));  // per-column stats, then 4 results
+  void* cw = contour ? ws_take(c, contour_work_bytes(n, nb, o.nq)) : nullptr;
   void* Clp = nullptr;
   void* bfw = nullptr;  // split-BF16 filter workspace
   void* G0 = nullptr;
@@ -420,7 +434,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   void* Rlp = nullptr;
   double* rho0 = nullptr;
   double* coef2 = nullptr;
-  if (mixed) {
+  if (lp) {
     Clp = ws_take(c, bf16 ? bf16_planes_bytes(n) : lp_elem * nn);
     if (bf16) bfw = ws_take(c, bf16_filter_work_bytes(n, nb));
     G0 = ws_take(c, lp_elem * n * nb);
@@ -514,8 +528,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // C = W L^{-H} is Hermitian: only its lower triangle is formed, then mirrored
   GEVP_TRY(trsm_right_lower_c_lowerpart(c, n, L, n, Dinv, n, C, n));
   GEVP_TRY(launch_mirror_lower(c, n, C, n, C, n, flags + 3));
-  if (mixed && bf16) GEVP_TRY(launch_split_rows_bf16(c, n, C, n, Clp));
-  if (mixed && !bf16) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
+  if (lp && bf16) GEVP_TRY(launch_split_rows_bf16(c, n, C, n, Clp));
+  if (lp && !bf16) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
   tm.stop(info, GEVP_STAGE_REDUCE);
 
   // ---------------- bounds
@@ -626,7 +640,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_TRY(run_filter(hst[1], hst.data() + 4));
     tm.stop(info, GEVP_STAGE_FILTER);
   }
-  cp.mode = mixed ? 2 : 0;
+  cp.mode = lp ? 2 : 0;
+  bool cfact = false;  // contour factorisations done
+  double ca = 0.0, cb = 0.0;
   for (it = 0; it < o.maxit; ++it) {
     tm.start();
     bool skipped = false;
@@ -672,10 +688,35 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     }
     if (it + 1 == o.maxit) break;
     tm.start();
-    if (mixed)
+    if (contour) {
+      if (!cfact) {
+        // circle from the current Ritz values: its right end halfway between
+        // the last wanted and the first unwanted one, its left end below the
+        // lowest by a quarter of the width; factored once per solve
+        std::vector<double> th(nb);
+        GEVP_HIP_TRY(hipMemcpyAsync(th.data(), theta, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                    c->stream));
+        GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+        cb = 0.5 * (th[nev - 1] + th[nev]);
+        const double wdt = std::max(cb - th[0], 1e-8 * std::max(1.0, std::fabs(cb)));
+        ca = th[0] - 0.25 * wdt;
+        if (!(ca < cb) || !std::isfinite(ca) || !std::isfinite(cb)) return GEVP_ERR_NONFINITE;
+        int piv = 0;
+        GEVP_TRY(contour_factor(c, n, C, n, ca, cb, o.nq, cw, nb, &piv));
+        if (piv) return GEVP_ERR_SINGULAR;
+        cfact = true;
+        info->contour_points = o.nq;
+        info->contour_a = ca;
+        info->contour_b = cb;
+      }
+      GEVP_TRY(contour_apply(c, n, nb, P0, n, P1, n, ca, cb, o.nq, cw, nb));
+      std::swap(P0, P1);
+      ++info->contour_applications;
+    } else if (lp) {
       GEVP_TRY(run_filter_r2(hst[1], hst.data() + 4, hsd[3]));
-    else
+    } else {
       GEVP_TRY(run_filter(hst[1], hst.data() + 4));
+    }
     tm.stop(info, GEVP_STAGE_FILTER);
   }
   info->qr_fallbacks = fallbacks;

@@ -19,7 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgevp.so")
 
 GEVP_OK, GEVP_ERR_INVALID, GEVP_ERR_NOT_HPD, GEVP_ERR_NOCONV = 0, 1, 2, 3
-GEVP_ERR_HIP, GEVP_ERR_NONFINITE, GEVP_ERR_ALLOC = 4, 5, 6
+GEVP_ERR_HIP, GEVP_ERR_NONFINITE, GEVP_ERR_ALLOC, GEVP_ERR_SINGULAR = 4, 5, 6, 7
+FILTER_CHEBYSHEV, FILTER_CONTOUR = 0, 1
+FILTERS = {"chebyshev": FILTER_CHEBYSHEV, "contour": FILTER_CONTOUR}
 FP64, FP32, BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 STAGES = ("stage", "chol", "reduce", "bounds", "filter", "qr", "rr", "final")
@@ -31,7 +33,8 @@ class Opts(ctypes.Structure):
         ("deg_max", ctypes.c_int), ("maxit", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
         ("seed", ctypes.c_ulonglong), ("skip_final_residual", ctypes.c_int),
         ("batch_streams", ctypes.c_int), ("seed_monitor", ctypes.c_int),
-        ("reserved", ctypes.c_int * 6),
+        ("filter", ctypes.c_int), ("contour_points", ctypes.c_int),
+        ("reserved", ctypes.c_int * 4),
     ]
 
 
@@ -44,6 +47,8 @@ class Info(ctypes.Structure):
         ("filter_kernel_ms", ctypes.c_double), ("filter_launches", ctypes.c_int64),
         ("seed_sin_rms", ctypes.c_double), ("seed_dev_mean", ctypes.c_double),
         ("seed_dev_max", ctypes.c_double), ("seed_reindexed", ctypes.c_int),
+        ("contour_points", ctypes.c_int), ("contour_a", ctypes.c_double),
+        ("contour_b", ctypes.c_double), ("contour_applications", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -114,6 +119,10 @@ def load():
     lib.gevp_k_trsm.restype = I
     lib.gevp_k_heev.argtypes = [P, L, P, L, P, P, L]
     lib.gevp_k_heev.restype = I
+    lib.gevp_k_lu_shifted.argtypes = [P, L, P, L, D, D, P, L, ctypes.POINTER(L)]
+    lib.gevp_k_lu_shifted.restype = I
+    lib.gevp_k_contour_filter.argtypes = [P, L, P, L, P, L, L, D, D, I, P, L]
+    lib.gevp_k_contour_filter.restype = I
     lib.gevp_update_thresholded.argtypes = [P, L, P, L, P, L, D, P, L, ctypes.POINTER(UpdateInfo)]
     lib.gevp_update_thresholded.restype = I
     lib.gevp_update_masked.argtypes = [P, L, P, L, P, L, P, L]
@@ -150,8 +159,11 @@ def _ld(t: torch.Tensor) -> int:
 
 
 def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_steps=0, seed=0,
-              skip_final_residual=False, batch_streams=0, seed_monitor=False) -> Opts:
+              skip_final_residual=False, batch_streams=0, seed_monitor=False, filter="chebyshev",
+              contour_points=0) -> Opts:
     o = Opts()
+    o.filter = FILTERS[filter] if isinstance(filter, str) else int(filter)
+    o.contour_points = int(contour_points)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.nex, o.deg_init, o.deg_max, o.maxit = nex, deg_init, deg_max, maxit
     o.lanczos_steps, o.seed = lanczos_steps, seed
@@ -347,6 +359,35 @@ class Handle:
             raise GevpError(s, "gevp_k_heev")
         return th, Z
 
+
+    # ---- contour-integral filter pieces
+
+    def lu_shifted(self, C, z):
+        """Packed LU (no row exchanges) of z I - C; returns (LU, pivot) with
+        pivot = 0 or the first failing pivot (1-based)."""
+        C = colmajor(C)
+        n = C.shape[0]
+        LU = empty_colmajor(n, n, device=C.device)
+        piv = ctypes.c_int64(0)
+        self._stream()
+        s = self.lib.gevp_k_lu_shifted(self.h, n, _ptr(C), _ld(C), float(complex(z).real),
+                                       float(complex(z).imag), _ptr(LU), _ld(LU), ctypes.byref(piv))
+        if s not in (GEVP_OK, GEVP_ERR_SINGULAR):
+            raise GevpError(s, "gevp_k_lu_shifted")
+        return LU, int(piv.value)
+
+    def contour_filter(self, C, V, a, b, nq):
+        """Y = sum_j w_j (z_j I - C)^{-1} V on the circle with diameter [a, b]."""
+        C = colmajor(C)
+        V = colmajor(V)
+        n, m = V.shape
+        Y = empty_colmajor(n, m, device=V.device)
+        self._stream()
+        s = self.lib.gevp_k_contour_filter(self.h, n, _ptr(C), _ld(C), _ptr(V), _ld(V), m, float(a),
+                                           float(b), int(nq), _ptr(Y), _ld(Y))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_contour_filter")
+        return Y
 
     # ---- thresholded partial matrix update
 

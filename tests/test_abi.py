@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     from paper_1007_4400_amd import gevp
 
-    for s in range(7):
+    for s in range(8):
         assert gevp.status_string(s)
     assert "positive definite" in gevp.status_string(gevp.GEVP_ERR_NOT_HPD)
 
