@@ -76,7 +76,7 @@ typedef struct {
   int seed_monitor;         /* 1: with a seed X0, report how it relates to the result
                                (gevp_info seed_*; needs the final residual check) */
   int filter;               /* gevp_filter; default GEVP_FILTER_CHEBYSHEV */
-  int contour_points;       /* quadrature nodes of the contour filter; 0 = 16 */
+  int contour_points;       /* quadrature nodes of the contour filter; 0 = 8 */
   int reserved[4];
 } gevp_opts;
 
@@ -120,11 +120,14 @@ typedef struct {
   double seed_dev_mean, seed_dev_max;
   int seed_reindexed;
   /* Contour filter (opts.filter = GEVP_FILTER_CONTOUR and used): the circle's
-     diameter [contour_a, contour_b], its nodes, and how many times the filter
-     was applied; 0 otherwise. */
+     diameter [contour_a, contour_b], its nodes, how many times the filter was
+     applied and the block columns filtered, summed over the applications
+     (converged columns are not filtered again); 0 otherwise.  Work: nq
+     factorisations of 8 n^3 / 3 flops and 8 n^2 nq flops per filtered column. */
   int contour_points;
   double contour_a, contour_b;
   int contour_applications;
+  int64_t contour_columns;
 } gevp_info;
 
 typedef enum {

@@ -350,7 +350,7 @@ def contour_solve(A, B, nev, X0, nq=16, tol=1e-10, nex=None, maxit=20, seed=0):
        Y <- Y Z.
     3. Stop when ||C y_i - theta_i y_i|| <= tol ||C||_2 for i < nev.
     4. Contour (chosen once, from the first Ritz values): b halfway between
-       theta_{nev-1} and theta_nev, a = theta_0 - (b - theta_0) / 4.
+       theta_{nev-1} and theta_nev, a = theta_0 - (b - theta_0) / 20.
     5. Y <- contour_filter(C, Y, a, b, nq); back to 2.
     Returns (lambda[nev], X (n x nev, B-orthonormal), iterations)."""
     A = np.asarray(A, dtype=np.complex128)
@@ -381,7 +381,7 @@ def contour_solve(A, B, nev, X0, nq=16, tol=1e-10, nex=None, maxit=20, seed=0):
             break
         if ab is None:
             b = 0.5 * (theta[nev - 1] + theta[nev]) if nb > nev else theta[nev - 1] + 1.0
-            ab = (theta[0] - 0.25 * (b - theta[0]), b)
+            ab = (theta[0] - 0.05 * (b - theta[0]), b)
         Y = contour_filter(C, Y, ab[0], ab[1], nq)
     X = np.linalg.solve(L.conj().T, Y[:, :nev])
     return theta[:nev], X, it

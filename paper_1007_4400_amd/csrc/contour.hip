@@ -13,12 +13,13 @@
 // Each shifted matrix M_j = z_j I - C is factored once, M_j = L_j U_j, without
 // row exchanges: -i M_j has Hermitian part Im(z_j) I, positive definite, so
 // every leading block is nonsingular and the growth stays bounded.  The
-// factorisation is right-looking with 64-wide blocks: one work-group factors a
-// diagonal block in registers and writes the inverses of its two triangles,
-// the panels are products with those inverses, and the trailing update is one
-// FP64 matrix-core GEMM per block.  The nq factorisations are independent and
-// run on up to four streams, so one factorisation's latency-bound diagonal
-// blocks overlap another's GEMMs.  Applying the filter is two triangular
+// factorisation is right-looking by 256-wide panels: inside a panel one
+// work-group factors each 64 x 64 diagonal block in registers and writes the
+// inverses of its two triangles, the block's column and row pieces are
+// products with those inverses, and the trailing matrix gets one FP64
+// matrix-core GEMM per panel (K = 256).  The nq factorisations are
+// independent and run on four streams (the caller's and three more), so one
+// factorisation's latency-bound diagonal blocks overlap another's GEMMs.  Applying the filter is two triangular
 // solves per node (the existing recursive lower solve with the unit-lower
 // block inverses, and an upper solve written here), accumulated with the
 // complex weights.
@@ -29,6 +30,8 @@
 namespace {
 constexpr int NB = 64;
 constexpr int QSTREAMS = 4;
+constexpr int CGS = 16;       // column groups of the block LU (one per wave)
+constexpr int EPT = NB / CGS; // entries per thread
 
 __device__ __forceinline__ zd zmul(zd a, zd b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -38,56 +41,78 @@ __device__ __forceinline__ zd zsub(zd a, zd b) { return make_double2(a.x - b.x, 
 // One 64 x 64 diagonal block (kb <= 64 rows and columns in use, the rest
 // padded with the identity): M = L U in place without row exchanges (L unit
 // lower, stored strictly below the diagonal), then inv(L) into DinvL and
-// inv(U) into DinvU (64 x 64 each, leading dimension ldi).  Thread t holds
-// row i = t % 64 at columns c = t / 64 + 4 m (m = 0..15) in registers.  Step
+// inv(U) into DinvU (64 x 64 each, leading dimension ldi).  1024 threads:
+// thread t holds row i = t % 64 at columns c = t / 64 + 16 m (m = 0..3) in
+// registers, four waves per SIMD, so the latency of one wave's dependent FP64
+// chain is hidden by the others (a quarter of the threads measured 4x slower:
+// latency-bound with one wave per SIMD).  Step
 // k reads the pivot row and column k from double-buffered LDS (one barrier
 // per step); the next step's row and column are published from inside the
 // unrolled update loop under a per-element test, so every register index is a
 // constant.  *info receives goff + the first failing pivot (1-based).
-__global__ __launch_bounds__(256) void k_getrf_block(zd* M, int64_t ldm, int kb, zd* DinvL,
+__global__ __launch_bounds__(1024) void k_getrf_block(zd* M, int64_t ldm, int kb, zd* DinvL,
                                                      zd* DinvU, int64_t ldi, int* info, int goff) {
-  __shared__ zd rowb[2][NB], colb[2][NB];
+  __shared__ zd rowb[2][NB], colb[2][NB], rpiv[2];
   __shared__ zd rowl[2][NB], coll[2][NB], rowu[2][NB], colu[2][NB];
   __shared__ zd dinv[NB];
-  const int tid = threadIdx.x, i = tid & 63, cg = tid >> 6;
-  zd a[16];
+  // the column group is uniform over a wave: column tests become scalar branches
+  const int tid = threadIdx.x, i = tid & 63, cg = __builtin_amdgcn_readfirstlane(tid >> 6);
+  zd a[EPT];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int j = cg + 4 * m;
+  for (int m = 0; m < EPT; ++m) {
+    const int j = cg + CGS * m;
     a[m] = (i < kb && j < kb) ? M[i + (int64_t)j * ldm] : make_double2(i == j ? 1.0 : 0.0, 0.0);
     if (i == 0) rowb[0][j] = a[m];
     if (j == 0) colb[0][i] = a[m];
+    if (i == 0 && j == 0) {
+      const double d = a[m].x * a[m].x + a[m].y * a[m].y;
+      rpiv[0] = make_double2(a[m].x / d, -a[m].y / d);
+      if (!(d > 0.0) || !isfinite(d)) atomicMin(info, goff + 1);
+    }
   }
-  // factorisation
+  // factorisation; the reciprocal of the next pivot is published with its row
   for (int k = 0; k < NB; ++k) {
     const int b = k & 1, nb = b ^ 1;
     __syncthreads();
     if (i > k) {
-      const zd p = rowb[b][k];
-      const double d = p.x * p.x + p.y * p.y;
-      const zd ip = make_double2(p.x / d, -p.y / d);
-      const zd l = zmul(colb[b][i], ip);
+      const zd l = zmul(colb[b][i], rpiv[b]);
+      // all LDS reads first, then a branch-free update (a zero multiplier for
+      // columns j <= k), so the reads are not serialised behind branches
+      zd r[EPT];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = cg + 4 * m;
-        if (j > k) a[m] = zsub(a[m], zmul(l, rowb[b][j]));
-        if (j == k) a[m] = l;
-        if (j == k + 1) colb[nb][i] = a[m];
-        if (i == k + 1) rowb[nb][j] = a[m];
+      for (int m = 0; m < EPT; ++m) r[m] = rowb[b][cg + CGS * m];
+      const zd zero = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const int j = cg + CGS * m;
+        const zd lm = (j > k) ? l : zero;
+        const zd u = zsub(a[m], zmul(lm, r[m]));
+        a[m] = (j == k) ? l : u;
       }
-    }
-    if (tid == 0) {
-      const zd p = rowb[b][k];
-      const double d = p.x * p.x + p.y * p.y;
-      if (!(d > 0.0) || !isfinite(d)) atomicMin(info, goff + k + 1);
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const int j = cg + CGS * m;
+        if (j == k + 1) {
+          colb[nb][i] = a[m];
+          if (i == k + 1) {
+            const double d = a[m].x * a[m].x + a[m].y * a[m].y;
+            rpiv[nb] = make_double2(a[m].x / d, -a[m].y / d);
+            if (!(d > 0.0) || !isfinite(d)) atomicMin(info, goff + k + 2);
+          }
+        }
+      }
+      if (i == k + 1) {
+#pragma unroll
+        for (int m = 0; m < EPT; ++m) rowb[nb][cg + CGS * m] = a[m];
+      }
     }
   }
   // store the factors; diagonal inverses of U for the backward sweep; the
   // first step's operands of the inverse sweeps
-  zd bl[16], bu[16];
+  zd bl[EPT], bu[EPT];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int j = cg + 4 * m;
+  for (int m = 0; m < EPT; ++m) {
+    const int j = cg + CGS * m;
     if (i < kb && j < kb) M[i + (int64_t)j * ldm] = a[m];
     if (j == i) {
       const double d = a[m].x * a[m].x + a[m].y * a[m].y;
@@ -104,9 +129,9 @@ __global__ __launch_bounds__(256) void k_getrf_block(zd* M, int64_t ldm, int kb,
   if (i == NB - 1) {  // row 63 of inv(U)
     const zd di = dinv[NB - 1];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < EPT; ++m) {
       bu[m] = zmul(bu[m], di);
-      rowu[0][cg + 4 * m] = bu[m];
+      rowu[0][cg + CGS * m] = bu[m];
     }
   }
   // inverses: forward sweep for L (unit lower, step k) and backward sweep for
@@ -114,23 +139,30 @@ __global__ __launch_bounds__(256) void k_getrf_block(zd* M, int64_t ldm, int kb,
   for (int k = 0; k < NB; ++k) {
     const int b = k & 1, nb = b ^ 1, ku = NB - 1 - k;
     __syncthreads();
-    if (i > k) {
-      const zd l = coll[b][i];
+    {
+      // branch-free: rows outside the update range use a zero multiplier
+      const zd zero = make_double2(0.0, 0.0);
+      const zd l = (i > k) ? coll[b][i] : zero;
+      const zd u = (i < ku) ? colu[b][i] : zero;
+      zd rl[EPT], ru[EPT];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) bl[m] = zsub(bl[m], zmul(l, rowl[b][cg + 4 * m]));
-    }
-    if (i < ku) {
-      const zd u = colu[b][i];
+      for (int m = 0; m < EPT; ++m) {
+        rl[m] = rowl[b][cg + CGS * m];
+        ru[m] = rowu[b][cg + CGS * m];
+      }
 #pragma unroll
-      for (int m = 0; m < 16; ++m) bu[m] = zsub(bu[m], zmul(u, rowu[b][cg + 4 * m]));
+      for (int m = 0; m < EPT; ++m) {
+        bl[m] = zsub(bl[m], zmul(l, rl[m]));
+        bu[m] = zsub(bu[m], zmul(u, ru[m]));
+      }
     }
     // next step's operands: row k+1 of inv(L) is final now; row ku-1 of
     // inv(U) is final once divided by its pivot
     if (k + 1 < NB) {
       const zd di = dinv[ku - 1];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int j = cg + 4 * m;
+      for (int m = 0; m < EPT; ++m) {
+        const int j = cg + CGS * m;
         if (i == k + 1) rowl[nb][j] = bl[m];
         if (i == ku - 1) {
           bu[m] = zmul(bu[m], di);
@@ -142,8 +174,8 @@ __global__ __launch_bounds__(256) void k_getrf_block(zd* M, int64_t ldm, int kb,
     }
   }
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int j = cg + 4 * m;
+  for (int m = 0; m < EPT; ++m) {
+    const int j = cg + CGS * m;
     if (i < kb) {
       DinvL[i + (int64_t)j * ldi] = bl[m];
       DinvU[i + (int64_t)j * ldi] = bu[m];
@@ -220,8 +252,11 @@ gevp_status quad_ctx(gevp_ctx* c, int i, gevp_ctx** out) {
   return GEVP_OK;
 }
 
-// The quadrature streams start after the work queued on c's stream; every
-// exit waits for them (they write workspace the next call reuses).
+// The nodes run on c's own stream and up to QSTREAMS - 1 further streams
+// (c's stream is idle meanwhile; with four hardware queues per process, more
+// streams would share queues and serialise).  The further streams start after
+// the work queued on c's stream; every exit waits for them (they write
+// workspace the next call reuses).
 struct QuadStreams {
   gevp_ctx* c;
   int count = 0;
@@ -229,32 +264,28 @@ struct QuadStreams {
   hipEvent_t fork = nullptr, join[QSTREAMS] = {};
   explicit QuadStreams(gevp_ctx* ctx) : c(ctx) {}
   gevp_status open(int want) {
-    if (!c->inner_streams || want <= 1) {
-      count = 1;
-      s[0] = c;
-      return GEVP_OK;
-    }
-    count = want < QSTREAMS ? want : QSTREAMS;
+    s[0] = c;
+    count = (!c->inner_streams || want <= 1) ? 1 : (want < QSTREAMS ? want : QSTREAMS);
+    if (count == 1) return GEVP_OK;
     GEVP_HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventRecord(fork, c->stream));
-    for (int q = 0; q < count; ++q) {
-      GEVP_TRY(quad_ctx(c, q, &s[q]));
+    for (int q = 1; q < count; ++q) {
+      GEVP_TRY(quad_ctx(c, q - 1, &s[q]));
       GEVP_HIP_TRY(hipEventCreateWithFlags(&join[q], hipEventDisableTiming));
       GEVP_HIP_TRY(hipStreamWaitEvent(s[q]->stream, fork, 0));
     }
     return GEVP_OK;
   }
   gevp_status close() {
-    if (s[0] == c) return GEVP_OK;
-    for (int q = 0; q < count; ++q) {
+    for (int q = 1; q < count; ++q) {
       GEVP_HIP_TRY(hipEventRecord(join[q], s[q]->stream));
       GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, join[q], 0));
     }
     return GEVP_OK;
   }
   ~QuadStreams() {
-    if (s[0] && s[0] != c)
-      for (int q = 0; q < count; ++q) (void)hipStreamSynchronize(s[q]->stream);
+    for (int q = 1; q < count; ++q)
+      if (s[q]) (void)hipStreamSynchronize(s[q]->stream);
     if (fork) (void)hipEventDestroy(fork);
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
@@ -305,24 +336,45 @@ void node(double a, double b, int nq, int j, zd* z, zd* w) {
 
 gevp_status lu_nopiv(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* DinvL, zd* DinvU,
                      int64_t ldi, int* info_dev) {
-  for (int64_t r0 = 0; r0 < n; r0 += NB) {
-    const int64_t kb = std::min<int64_t>(NB, n - r0), rest = n - r0 - kb;
-    zd* Mkk = M + r0 + r0 * ldm;
-    hipLaunchKernelGGL(k_getrf_block, dim3(1), dim3(256), 0, c->stream, Mkk, ldm, (int)kb, DinvL + r0,
-                       DinvU + r0, ldi, info_dev, (int)r0);
-    GEVP_HIP_TRY(hipGetLastError());
+  // Panels of PW columns; inside a panel a right-looking LU by 64-wide blocks
+  // restricted to the panel's columns; then the panel's row block
+  // U12 = L11^{-1} A12 by the recursive lower solve, and one trailing update
+  // with K = PW (a K = 64 update per block would re-read and re-write the
+  // trailing matrix four times as often: HBM-bound at about 30 TFLOP/s).
+  constexpr int64_t PW = 256;
+  for (int64_t r0 = 0; r0 < n; r0 += PW) {
+    const int64_t kb = std::min<int64_t>(PW, n - r0);
+    const int64_t pend = r0 + kb;  // first column after the panel
+    for (int64_t s0 = r0; s0 < pend; s0 += NB) {
+      const int64_t sb = std::min<int64_t>(NB, pend - s0);
+      const int64_t below = n - s0 - sb, pc = pend - s0 - sb;
+      zd* Mss = M + s0 + s0 * ldm;
+      hipLaunchKernelGGL(k_getrf_block, dim3(1), dim3(1024), 0, c->stream, Mss, ldm, (int)sb,
+                         DinvL + s0, DinvU + s0, ldi, info_dev, (int)s0);
+      GEVP_HIP_TRY(hipGetLastError());
+      zd* A21 = Mss + sb;
+      zd* A12 = Mss + sb * ldm;
+      // L21 = A21 U11^{-1} and U12 = L11^{-1} A12 in place (one 64-wide
+      // output tile side: every tile reads its whole K range before it writes)
+      if (below > 0)
+        GEVP_TRY(launch_zgemm(c, 0, 0, below, sb, sb, 1.0, A21, ldm, DinvU + s0, ldi, 0.0, nullptr,
+                              0, 0.0, nullptr, 0, nullptr, A21, ldm));
+      if (pc > 0) {
+        GEVP_TRY(launch_zgemm(c, 0, 0, sb, pc, sb, 1.0, DinvL + s0, ldi, A12, ldm, 0.0, nullptr, 0,
+                              0.0, nullptr, 0, nullptr, A12, ldm));
+        if (below > 0)
+          GEVP_TRY(launch_zgemm(c, 0, 0, below, pc, sb, -1.0, A21, ldm, A12, ldm, 1.0, Mss + sb + sb * ldm,
+                                ldm, 0.0, nullptr, 0, nullptr, Mss + sb + sb * ldm, ldm));
+      }
+    }
+    const int64_t rest = n - pend;
     if (rest > 0) {
-      zd* A21 = Mkk + kb;
-      zd* A12 = Mkk + kb * ldm;
-      zd* A22 = Mkk + kb + kb * ldm;
-      // L21 = A21 U11^{-1}, U12 = L11^{-1} A12: in place, one 64-wide output
-      // tile side, so every tile reads its whole K range before it writes
-      GEVP_TRY(launch_zgemm(c, 0, 0, rest, kb, kb, 1.0, A21, ldm, DinvU + r0, ldi, 0.0, nullptr, 0,
-                            0.0, nullptr, 0, nullptr, A21, ldm));
-      GEVP_TRY(launch_zgemm(c, 0, 0, kb, rest, kb, 1.0, DinvL + r0, ldi, A12, ldm, 0.0, nullptr, 0,
-                            0.0, nullptr, 0, nullptr, A12, ldm));
-      GEVP_TRY(launch_zgemm(c, 0, 0, rest, rest, kb, -1.0, A21, ldm, A12, ldm, 1.0, A22, ldm, 0.0,
-                            nullptr, 0, nullptr, A22, ldm));
+      zd* Mrr = M + r0 + r0 * ldm;
+      zd* A12 = Mrr + kb * ldm;
+      GEVP_TRY(trsm_left_lower_n(c, kb, rest, Mrr, ldm, DinvL + r0, ldi, A12, ldm));
+      GEVP_TRY(launch_zgemm(c, 0, 0, rest, rest, kb, -1.0, Mrr + kb, ldm, A12, ldm, 1.0,
+                            Mrr + kb + kb * ldm, ldm, 0.0, nullptr, 0, nullptr, Mrr + kb + kb * ldm,
+                            ldm));
     }
   }
   return GEVP_OK;

@@ -105,7 +105,7 @@ Opts resolve(const gevp_opts* o, int64_t nev) {
   r.skip_final = o ? o->skip_final_residual : 0;
   r.seed_monitor = o ? o->seed_monitor : 0;
   r.filter = o ? o->filter : 0;
-  r.nq = (o && o->contour_points > 0) ? o->contour_points : 16;
+  r.nq = (o && o->contour_points > 0) ? o->contour_points : 8;
   return r;
 }
 
@@ -692,14 +692,15 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       if (!cfact) {
         // circle from the current Ritz values: its right end halfway between
         // the last wanted and the first unwanted one, its left end below the
-        // lowest by a quarter of the width; factored once per solve
+        // lowest by a twentieth of the width (a small radius separates the
+        // wanted from the unwanted faster); factored once per solve
         std::vector<double> th(nb);
         GEVP_HIP_TRY(hipMemcpyAsync(th.data(), theta, sizeof(double) * nb, hipMemcpyDeviceToHost,
                                     c->stream));
         GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
         cb = 0.5 * (th[nev - 1] + th[nev]);
         const double wdt = std::max(cb - th[0], 1e-8 * std::max(1.0, std::fabs(cb)));
-        ca = th[0] - 0.25 * wdt;
+        ca = th[0] - 0.05 * wdt;
         if (!(ca < cb) || !std::isfinite(ca) || !std::isfinite(cb)) return GEVP_ERR_NONFINITE;
         int piv = 0;
         GEVP_TRY(contour_factor(c, n, C, n, ca, cb, o.nq, cw, nb, &piv));
@@ -709,8 +710,14 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
         info->contour_a = ca;
         info->contour_b = cb;
       }
-      GEVP_TRY(contour_apply(c, n, nb, P0, n, P1, n, ca, cb, o.nq, cw, nb));
-      std::swap(P0, P1);
+      // only the columns the controller still filters (degree-sorted: the
+      // first hst[4] have converged and are kept as they are)
+      const int64_t s0 = hst[4];
+      GEVP_TRY(launch_gather_cols(c, n, nb, P0, n, perm, P1, n));
+      if (s0 > 0) GEVP_TRY(launch_copy2d(c, n, s0, P1, n, P0, n));
+      if (s0 < nb)
+        GEVP_TRY(contour_apply(c, n, nb - s0, P1 + s0 * n, n, P0 + s0 * n, n, ca, cb, o.nq, cw, nb));
+      info->contour_columns += nb - s0;
       ++info->contour_applications;
     } else if (lp) {
       GEVP_TRY(run_filter_r2(hst[1], hst.data() + 4, hsd[3]));

@@ -49,6 +49,7 @@ class Info(ctypes.Structure):
         ("seed_dev_max", ctypes.c_double), ("seed_reindexed", ctypes.c_int),
         ("contour_points", ctypes.c_int), ("contour_a", ctypes.c_double),
         ("contour_b", ctypes.c_double), ("contour_applications", ctypes.c_int),
+        ("contour_columns", ctypes.c_int64),
     ]
 
     def as_dict(self):

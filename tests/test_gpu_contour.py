@@ -132,9 +132,10 @@ def test_seeded_solve_with_contour_filter(oracle_mod, h, n, base):
     for A, B in seq[1:]:
         lam, X, _, info = h.solve(_dev(A), _dev(B), wl.nev, X0=X, kx=kx, opts=oc)
         _check(oracle_mod, A, B, lam, X, wl.nev)
-        assert info["contour_points"] == 16 and info["contour_applications"] >= 1
+        assert info["contour_points"] == 8 and info["contour_applications"] >= 1
+        assert info["contour_columns"] >= wl.nev
         assert info["contour_a"] < lam[0].item() and info["contour_b"] > lam[wl.nev - 1].item()
-        assert info["outer_iters"] <= 4
+        assert info["outer_iters"] <= 6
 
 
 def test_contour_option_without_seed_uses_chebyshev(oracle_mod, h):
