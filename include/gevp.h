@@ -114,7 +114,11 @@ typedef struct {
        seed_sin_rms   = sqrt(max(0, k - ||M||_F^2) / k), the RMS sine of those angles;
        seed_dev_mean, seed_dev_max: per result column j, the deviation angle
                         arccos(max_i |M(i, j)|) / (pi/2) (1 = orthogonal), mean and max;
-       seed_reindexed = columns j whose best-matching seed column is not j.
+       seed_reindexed = columns j matched to a seed column other than j;
+       seed_dev_std  = standard deviation of the deviation angles.
+     The matching minimises the summed deviation angles over permutations: each
+     column's largest overlap when those are distinct (then optimal), else a
+     linear assignment on arccos|M| solved on the host in O(k^3).
      -1 (and 0) when not computed. */
   double seed_sin_rms;
   double seed_dev_mean, seed_dev_max;
@@ -128,6 +132,7 @@ typedef struct {
   double contour_a, contour_b;
   int contour_applications;
   int64_t contour_columns;
+  double seed_dev_std;    /* see the seed monitor fields above */
 } gevp_info;
 
 typedef enum {
@@ -267,6 +272,14 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
 /* Eigen-decomposition of a small Hermitian matrix (n <= 2048) on the GPU:
  * H = Z diag(theta) Z^H, theta ascending.  H (lower read) is overwritten.
  * Synchronous. */
+/* Seed monitor of a k x k cross-overlap M = X0^H B X of two B-orthonormal
+ * blocks (device complex128, 1 <= k <= 2048): stats (host double[5]) receives
+ * sin_rms, dev_mean, dev_max, reindexed and dev_std as in gevp_info, match
+ * (optional host int[k]) the seed column matched to each column.
+ * Synchronous. */
+gevp_status gevp_k_seed_monitor(gevp_handle h, int64_t k, const void* M, int64_t ldm, double* stats,
+                                int* match);
+
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
                         double* theta, void* Z, int64_t ldz);
 

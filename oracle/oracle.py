@@ -19,10 +19,12 @@ Functions and the parts of the paper they follow:
 * ``bisect``           -- k-th eigenvalue by bisection on inertia counts.
 * ``inverse_iteration``-- eigenvector at a given eigenvalue estimate.
 * ``grad``             -- gradient of sum_i w_i lambda_i with respect to A, B.
-* ``seed_monitor``     -- how far a block of eigenvectors moved between two SCF
+* ``seed_monitor``, ``seed_monitor_from_overlap``
+                       -- how far a block of eigenvectors moved between two SCF
                           steps: principal angles and per-vector deviation
-                          angles (section 2, paragraph "Eigenvectors
-                          evolution"); plain numpy, FP64.
+                          angles after an angle-minimising re-indexing
+                          (section 2, paragraph "Eigenvectors evolution");
+                          plain numpy/scipy, FP64.
 * ``threshold_update`` -- partial update of a Hermitian matrix between two
                           SCF steps: only entries whose change exceeds a
                           fraction p_t of the largest change are taken over
@@ -200,26 +202,42 @@ def cholesky(B):
     return np.array(L)
 
 
-def seed_monitor(X0, X, B, k):
-    """Seed monitor of two B-orthonormal blocks (section 2, paragraph
-    "Eigenvectors evolution": deviation angles between corresponding
-    eigenvectors of adjacent iterations, here matched by largest overlap).
+def seed_monitor_from_overlap(M):
+    """Seed monitor statistics of a k x k cross-overlap M = X0^H B X of two
+    B-orthonormal blocks (section 2, paragraph "Eigenvectors evolution":
+    deviation angles between corresponding eigenvectors of adjacent
+    iterations, the eigenvectors re-indexed by an angle-minimising match).
 
-    With M = X0[:, :k]^H B X[:, :k], the singular values of M are the cosines
-    of the principal angles between the two spans, so sum sin^2 = k - ||M||_F^2.
-    Returns (sin_rms, dev_mean, dev_max, reindexed, dev) where dev[j] =
-    arccos(min(1, max_i |M[i, j]|)) / (pi/2) and reindexed counts the columns
-    j whose largest |M[i, j]| is not at i = j (the lowest such i on ties)."""
+    The singular values of M are the cosines of the principal angles between
+    the two spans, so sum sin^2 = k - ||M||_F^2.  The match pi (result column j
+    <- seed column pi(j)) minimises the summed deviation angles
+    sum_j arccos(min(1, |M[pi(j), j]|)) over permutations (a linear assignment,
+    solved by scipy).  Returns (sin_rms, dev_mean, dev_max, reindexed, dev_std,
+    dev, pi) with dev[j] = arccos(min(1, |M[pi(j), j]|)) / (pi/2), reindexed =
+    #{j: pi(j) != j} and dev_std the population standard deviation."""
+    from scipy.optimize import linear_sum_assignment
+
+    M = np.asarray(M, dtype=np.complex128)
+    k = M.shape[0]
+    absM = np.abs(M)
+    sin_rms = float(np.sqrt(max(0.0, k - float(np.sum(absM ** 2))) / k))
+    cost = np.arccos(np.minimum(1.0, absM)).T  # cost[j, i]: result column j <- seed column i
+    rows, pi = linear_sum_assignment(cost)
+    assert np.array_equal(rows, np.arange(k))
+    dev = np.array([np.arccos(min(1.0, absM[pi[j], j])) / (np.pi / 2) for j in range(k)])
+    reindexed = int(np.sum(pi != np.arange(k)))
+    return sin_rms, float(dev.mean()), float(dev.max()), reindexed, float(dev.std()), dev, pi
+
+
+def seed_monitor(X0, X, B, k):
+    """seed_monitor_from_overlap of M = X0[:, :k]^H B X[:, :k]; returns
+    (sin_rms, dev_mean, dev_max, reindexed, dev) for the first k columns."""
     X0 = np.asarray(X0, dtype=np.complex128)[:, :k]
     X = np.asarray(X, dtype=np.complex128)[:, :k]
     B = np.asarray(B, dtype=np.complex128)
     M = X0.conj().T @ (B @ X)
-    absM = np.abs(M)
-    sin_rms = float(np.sqrt(max(0.0, k - float(np.sum(absM ** 2))) / k))
-    best = np.array([int(np.argmax(absM[:, j])) for j in range(k)])
-    dev = np.array([np.arccos(min(1.0, absM[best[j], j])) / (np.pi / 2) for j in range(k)])
-    reindexed = int(np.sum(best != np.arange(k)))
-    return sin_rms, float(dev.mean()), float(dev.max()), reindexed, dev
+    r = seed_monitor_from_overlap(M)
+    return r[0], r[1], r[2], r[3], r[5]
 
 
 def threshold_update(A_cur, A_new, p_t):

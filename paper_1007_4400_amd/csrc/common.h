@@ -146,9 +146,14 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
                               const zd* V, int64_t ldv, const double* theta, double* out);
 gevp_status launch_colnorms(gevp_ctx* c, int64_t rows, int64_t cols, const zd* V, int64_t ldv,
                             double* out);
-// seed monitor of a k x k cross-overlap M (stat: 3k doubles; out: 4 doubles)
+// seed monitor of a k x k cross-overlap M, k <= 2048 (stat: 3k doubles; out:
+// 6 doubles).  seed_monitor_stats also completes it on the host and waits:
+// res = sin_rms, dev_mean, dev_max, reindexed, dev_std under the
+// angle-minimising matching, match[j] = matched seed column (may be null).
 gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
                                 double* out);
+gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
+                               double* out, double res[5], int* match);
 gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                                const int* perm, zd* D, int64_t ldd);
 gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx);

@@ -326,7 +326,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   gevp_info dummy;
   if (!info) info = &dummy;
   std::memset(info, 0, sizeof(*info));
-  info->seed_sin_rms = info->seed_dev_mean = info->seed_dev_max = -1.0;
+  info->seed_sin_rms = info->seed_dev_mean = info->seed_dev_max = info->seed_dev_std = -1.0;
   auto bad = [&](int arg) {
     info->lapack_info = -arg;
     return GEVP_ERR_INVALID;
@@ -384,7 +384,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
   need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
   need += ws_round(sizeof(double) * 4);                  // norms
-  need += ws_round(sizeof(double) * (3 * nb + 4));       // seed monitor
+  need += ws_round(sizeof(double) * (3 * nb + 8));       // seed monitor
   if (contour) need += contour_work_bytes(n, nb, o.nq);  // nq factorisations
   const size_t lp_elem = 8;                              // complex64
   if (lp) {
@@ -425,7 +425,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   int* flags = (int*)ws_take(c, sizeof(int) * 8);
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
-  double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 4));  // per-column stats, then 4 results
+  double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 8));  // per-column stats, then 6 results
   void* cw = contour ? ws_take(c, contour_work_bytes(n, nb, o.nq)) : nullptr;
   void* Clp = nullptr;
   void* bfw = nullptr;  // split-BF16 filter workspace
@@ -748,12 +748,11 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     // seed monitor: M = X0(:, :k)^H (B X)(:, :k), B X is T
     const int64_t km = std::min<int64_t>(nev, k0);
     const bool monitor = seeded && o.seed_monitor && km > 0;
-    double hm[4] = {-1.0, -1.0, -1.0, 0.0};
+    double hm[5] = {-1.0, -1.0, -1.0, 0.0, -1.0};
     if (monitor) {
       GEVP_TRY(launch_zgemm(c, 1, 0, km, km, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
                             nullptr, Hs, km));
-      GEVP_TRY(launch_seed_monitor(c, km, Hs, km, mon, mon + 3 * nb));
-      GEVP_HIP_TRY(hipMemcpyAsync(hm, mon + 3 * nb, sizeof(hm), hipMemcpyDeviceToHost, c->stream));
+      GEVP_TRY(seed_monitor_stats(c, km, Hs, km, mon, mon + 3 * nb, hm, nullptr));
     }
     std::vector<double> hr(kx);
     GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kx, hipMemcpyDeviceToHost, c->stream));
@@ -763,6 +762,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       info->seed_dev_mean = hm[1];
       info->seed_dev_max = hm[2];
       info->seed_reindexed = (int)hm[3];
+      info->seed_dev_std = hm[4];
     }
     double mx = 0.0;
     for (int64_t i = 0; i < nev; ++i) mx = std::max(mx, hr[i]);
@@ -952,6 +952,15 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
   if (left && !conj) return trsm_left_lower_n(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
   if (left && conj) return trsm_left_lower_c(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
   return trsm_right_lower_c(h, n, m, Lc, n, Dinv, n, (zd*)R, ldr);
+}
+
+gevp_status gevp_k_seed_monitor(gevp_handle h, int64_t k, const void* M, int64_t ldm, double* stats,
+                                int* match) {
+  if (!h || k < 1 || k > 2048 || !M || ldm < k || !stats) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, ws_round(sizeof(double) * (3 * k + 8)) + 256));
+  double* w = (double*)ws_take(h, sizeof(double) * (3 * k + 8));
+  return seed_monitor_stats(h, k, (const zd*)M, ldm, w, w + 3 * k, stats, match);
 }
 
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh, double* theta, void* Z,

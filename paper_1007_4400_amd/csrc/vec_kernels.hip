@@ -2,6 +2,10 @@
 // column norms and residual norms (wave64 reductions), column gathers,
 // counter-based random fill, phase normalisation, Hermitian matrix-vector
 // products for the Lanczos bounds.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "common.h"
 
 namespace {
@@ -207,21 +211,35 @@ __global__ __launch_bounds__(256) void k_seed_cols(int k, const zd* M, int64_t l
 
 // out[0] = sqrt(max(0, k - ||M||_F^2) / k), out[1] / out[2] = mean / max of
 // acos(min(1, max_i |M(i,j)|)) / (pi/2), out[3] = columns whose best row is not j
+// Seed monitor totals.  out[0] sin_rms, out[1] mean and out[2] max of the
+// per-column deviation angles (best match per column), out[3] columns whose
+// best match is not their own index, out[4] standard deviation of the angles,
+// out[5] = 1 when two columns share a best match (the per-column matches are
+// then no permutation and the host solves the assignment).  k <= 2048.
 __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, double* out) {
-  __shared__ double sf[256], sd[256], sx[256], sr[256];
+  __shared__ double sf[256], sd[256], sx[256], sr[256], sq[256];
+  __shared__ int hits[2048];
+  __shared__ int clash;
   const int t = threadIdx.x;
-  double f = 0.0, d = 0.0, x = 0.0, r = 0.0;
+  for (int i = t; i < k; i += 256) hits[i] = 0;
+  if (t == 0) clash = 0;
+  __syncthreads();
+  double f = 0.0, d = 0.0, x = 0.0, r = 0.0, q = 0.0;
   for (int j = t; j < k; j += 256) {
     f += stat[3 * j];
     const double dev = acos(fmin(1.0, stat[3 * j + 1])) * 0.63661977236758134;  // / (pi/2)
     d += dev;
+    q += dev * dev;
     x = fmax(x, dev);
-    r += ((int)stat[3 * j + 2] != j) ? 1.0 : 0.0;
+    const int best = (int)stat[3 * j + 2];
+    r += (best != j) ? 1.0 : 0.0;
+    if (atomicAdd(&hits[best], 1) > 0) clash = 1;
   }
   sf[t] = f;
   sd[t] = d;
   sx[t] = x;
   sr[t] = r;
+  sq[t] = q;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
@@ -229,14 +247,18 @@ __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, 
       sd[t] += sd[t + w];
       sx[t] = fmax(sx[t], sx[t + w]);
       sr[t] += sr[t + w];
+      sq[t] += sq[t + w];
     }
     __syncthreads();
   }
   if (t == 0) {
+    const double mean = sd[0] / (double)k;
     out[0] = sqrt(fmax(0.0, (double)k - sf[0]) / (double)k);
-    out[1] = sd[0] / (double)k;
+    out[1] = mean;
     out[2] = sx[0];
     out[3] = sr[0];
+    out[4] = sqrt(fmax(0.0, sq[0] / (double)k - mean * mean));
+    out[5] = clash ? 1.0 : 0.0;
   }
 }
 
@@ -425,10 +447,108 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
 gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
                                 double* out) {
   if (k <= 0) return GEVP_OK;
+  if (k > 2048) return GEVP_ERR_INVALID;
   hipLaunchKernelGGL(k_seed_cols, dim3((unsigned)k), dim3(256), 0, c->stream, (int)k, M, ldm, stat);
   GEVP_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_seed_finish, dim3(1), dim3(256), 0, c->stream, (int)k, stat, out);
   GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+namespace {
+// Minimum-cost assignment of an n x n cost matrix (row r, column c at
+// a[r * n + c]) by shortest augmenting paths with row and column potentials
+// (Kuhn-Munkres, O(n^3)); returns col_of_row.
+std::vector<int> min_cost_assignment(const std::vector<double>& a, int n) {
+  const double inf = 1e300;
+  std::vector<double> u(n + 1, 0.0), v(n + 1, 0.0), minv(n + 1);
+  std::vector<int> row_of(n + 1, 0), way(n + 1, 0);  // 1-based; column 0 is a sentinel
+  std::vector<char> used(n + 1);
+  for (int r = 1; r <= n; ++r) {
+    row_of[0] = r;
+    int c0 = 0;
+    std::fill(minv.begin(), minv.end(), inf);
+    std::fill(used.begin(), used.end(), 0);
+    do {
+      used[c0] = 1;
+      const int r0 = row_of[c0];
+      double delta = inf;
+      int c1 = 0;
+      for (int c = 1; c <= n; ++c) {
+        if (used[c]) continue;
+        const double cur = a[(size_t)(r0 - 1) * n + (c - 1)] - u[r0] - v[c];
+        if (cur < minv[c]) {
+          minv[c] = cur;
+          way[c] = c0;
+        }
+        if (minv[c] < delta) {
+          delta = minv[c];
+          c1 = c;
+        }
+      }
+      for (int c = 0; c <= n; ++c) {
+        if (used[c]) {
+          u[row_of[c]] += delta;
+          v[c] -= delta;
+        } else {
+          minv[c] -= delta;
+        }
+      }
+      c0 = c1;
+    } while (row_of[c0] != 0);
+    do {  // flip the augmenting path
+      const int c1 = way[c0];
+      row_of[c0] = row_of[c1];
+      c0 = c1;
+    } while (c0 != 0);
+  }
+  std::vector<int> col_of(n, 0);
+  for (int c = 1; c <= n; ++c) col_of[row_of[c] - 1] = c - 1;
+  return col_of;
+}
+}  // namespace
+
+gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
+                               double* out, double res[5], int* match) {
+  GEVP_TRY(launch_seed_monitor(c, k, M, ldm, stat, out));
+  double h[6];
+  std::vector<double> st(3 * k);
+  GEVP_HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  GEVP_HIP_TRY(hipMemcpyAsync(st.data(), stat, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, c->stream));
+  GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 5; ++i) res[i] = h[i];
+  std::vector<int> best(k);
+  for (int64_t j = 0; j < k; ++j) best[j] = (int)st[3 * j + 2];
+  if (h[5] != 0.0) {
+    // two columns share a best match: the angle-minimising matching is a
+    // linear assignment on the deviation angles (host, O(k^3))
+    std::vector<zd> hm((size_t)k * k);
+    GEVP_HIP_TRY(hipMemcpy2DAsync(hm.data(), sizeof(zd) * k, M, sizeof(zd) * ldm, sizeof(zd) * k, k,
+                                  hipMemcpyDeviceToHost, c->stream));
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    std::vector<double> cost((size_t)k * k);  // row: result column j, column: seed column i
+    for (int64_t j = 0; j < k; ++j)
+      for (int64_t i = 0; i < k; ++i) {
+        const zd m = hm[(size_t)j * k + i];
+        cost[(size_t)j * k + i] = std::acos(std::min(1.0, std::sqrt(m.x * m.x + m.y * m.y)));
+      }
+    best = min_cost_assignment(cost, (int)k);
+    double sum = 0.0, sq = 0.0, mx = 0.0, re = 0.0;
+    for (int64_t j = 0; j < k; ++j) {
+      const double dv = cost[(size_t)j * k + best[j]] * 0.63661977236758134;  // / (pi/2)
+      sum += dv;
+      sq += dv * dv;
+      mx = std::max(mx, dv);
+      re += (best[j] != j) ? 1.0 : 0.0;
+    }
+    const double mean = sum / (double)k;
+    res[1] = mean;
+    res[2] = mx;
+    res[3] = re;
+    res[4] = std::sqrt(std::max(0.0, sq / (double)k - mean * mean));
+  }
+  if (match)
+    for (int64_t j = 0; j < k; ++j) match[j] = best[j];
   return GEVP_OK;
 }
 

@@ -49,7 +49,7 @@ class Info(ctypes.Structure):
         ("seed_dev_max", ctypes.c_double), ("seed_reindexed", ctypes.c_int),
         ("contour_points", ctypes.c_int), ("contour_a", ctypes.c_double),
         ("contour_b", ctypes.c_double), ("contour_applications", ctypes.c_int),
-        ("contour_columns", ctypes.c_int64),
+        ("contour_columns", ctypes.c_int64), ("seed_dev_std", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -120,6 +120,8 @@ def load():
     lib.gevp_k_trsm.restype = I
     lib.gevp_k_heev.argtypes = [P, L, P, L, P, P, L]
     lib.gevp_k_heev.restype = I
+    lib.gevp_k_seed_monitor.argtypes = [P, L, P, L, ctypes.POINTER(D), ctypes.POINTER(I)]
+    lib.gevp_k_seed_monitor.restype = I
     lib.gevp_k_lu_shifted.argtypes = [P, L, P, L, D, D, P, L, ctypes.POINTER(L)]
     lib.gevp_k_lu_shifted.restype = I
     lib.gevp_k_contour_filter.argtypes = [P, L, P, L, P, L, L, D, D, I, P, L]
@@ -360,6 +362,19 @@ class Handle:
             raise GevpError(s, "gevp_k_heev")
         return th, Z
 
+
+    def seed_monitor(self, M):
+        """Seed monitor of a k x k cross-overlap M: returns (sin_rms, dev_mean,
+        dev_max, reindexed, dev_std, match)."""
+        M = colmajor(M)
+        k = M.shape[0]
+        st = (ctypes.c_double * 5)()
+        match = (ctypes.c_int * k)()
+        self._stream()
+        s = self.lib.gevp_k_seed_monitor(self.h, k, _ptr(M), _ld(M), st, match)
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_seed_monitor")
+        return st[0], st[1], st[2], int(st[3]), st[4], list(match)
 
     # ---- contour-integral filter pieces
 

@@ -118,6 +118,8 @@ def test_seed_monitor_matches_oracle(h, oracle_mod, precision):
         assert abs(info["seed_sin_rms"] - s) <= 1e-9
         assert abs(info["seed_dev_mean"] - dm) <= 1e-7 and abs(info["seed_dev_max"] - dx) <= 1e-7
         assert info["seed_reindexed"] == r
+        M = X0.cpu().numpy()[:, :wl.nev].conj().T @ B @ X.cpu().numpy()[:, :wl.nev]
+        assert abs(info["seed_dev_std"] - oracle_mod.seed_monitor_from_overlap(M)[4]) <= 1e-7
         assert 0.0 < s < 0.5  # a perturbed step moves the subspace, but not far
         X0 = X
     _, _, _, info_off = h.solve(_dev(seq[1][0]), _dev(B), wl.nev, X0=X0, tol=TOL, kx=kx)
@@ -175,3 +177,40 @@ def test_backward_matches_oracle_gradient(h, oracle_mod):
     lam_o, X_o = oracle_mod.solve(p.A, p.B, wl.nev)
     GA_o, _ = oracle_mod.grad(X_o, lam_o, f)
     assert np.linalg.norm(dA - GA_o) <= 1e-6 * np.linalg.norm(GA_o)
+
+
+def _unitary(k, rng):
+    F = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+    Q, R = np.linalg.qr(F)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+@pytest.mark.parametrize("k,kind", [(3, "mix"), (6, "mix"), (40, "mix"), (300, "near"),
+                                    (64, "identity"), (1, "identity")])
+def test_seed_monitor_entry_matches_oracle(h, oracle_mod, k, kind):
+    """gevp_k_seed_monitor on constructed overlaps: random unitary mixings
+    (the per-column best matches collide, the host assignment runs), a
+    near-permutation (a permuted identity rotated by small angles) and the
+    identity, against the oracle's assignment."""
+    rng = np.random.default_rng(k)
+    if kind == "mix":
+        M = _unitary(k, rng)
+    elif kind == "near":
+        P = np.eye(k)[rng.permutation(k)]
+        M = P.astype(np.complex128)
+        # small rotations between neighbouring pairs
+        for j in range(0, k - 1, 2):
+            t = rng.uniform(0.0, 0.3)
+            G = np.eye(k, dtype=np.complex128)
+            G[j, j], G[j, j + 1], G[j + 1, j], G[j + 1, j + 1] = np.cos(t), np.sin(t), -np.sin(t), np.cos(t)
+            M = M @ G
+    else:
+        M = np.eye(k, dtype=np.complex128)
+    s, m, x, r, sd, match = h.seed_monitor(_dev(M.astype(np.complex128)))
+    so, mo, xo, ro, sdo, _, pio = oracle_mod.seed_monitor_from_overlap(M)
+    # sin_rms of equal spans is the square root of a rounding-level
+    # difference k - ||M||_F^2: agreement to sqrt(k eps) only
+    assert abs(s - so) <= 2e-7
+    assert abs(m - mo) <= 1e-9 and abs(x - xo) <= 1e-9
+    assert abs(sd - sdo) <= 1e-9
+    assert r == ro and list(pio) == match

@@ -308,3 +308,52 @@ def test_seed_monitor_identity_and_orthogonal(oracle_mod):
     assert s < 1e-7 and x < 1e-6 and r == 0
     s, m, x, r, _ = oracle_mod.seed_monitor(X0, Y, B, 5)
     assert abs(s - 1.0) < 1e-12 and abs(m - 1.0) < 1e-6 and abs(x - 1.0) < 1e-6
+
+
+def _unitary(k, rng):
+    F = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+    Q, R = np.linalg.qr(F)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+def test_seed_monitor_assignment_brute_force(oracle_mod):
+    """The re-indexing minimises the summed deviation angles over all
+    permutations: checked by enumerating every permutation for k <= 6 on
+    random unitary mixings X = X0 U (so M = U), including cases where the
+    per-column largest overlaps collide (a per-column argmax is no
+    permutation there)."""
+    import itertools
+
+    rng = np.random.default_rng(21)
+    collisions = 0
+    for k in (3, 4, 5, 6):
+        for _ in range(6):
+            U = _unitary(k, rng)
+            absU = np.abs(U)
+            if len(set(np.argmax(absU, axis=0))) < k:
+                collisions += 1
+            best, bestp = None, None
+            for p in itertools.permutations(range(k)):
+                c = sum(np.arccos(min(1.0, absU[p[j], j])) for j in range(k))
+                if best is None or c < best - 1e-12:
+                    best, bestp = c, p
+            s, m, x, r, sd, dev, pi = oracle_mod.seed_monitor_from_overlap(U)
+            assert abs(m * k * (np.pi / 2) - best) < 1e-10
+            assert tuple(pi) == bestp
+            assert r == sum(1 for j in range(k) if bestp[j] != j)
+            assert abs(s) < 1e-7  # same span
+            assert abs(sd - np.std(dev)) < 1e-15
+    assert collisions >= 3
+
+
+def test_seed_monitor_std_of_constructed_angles(oracle_mod):
+    """sigma of the deviation angles (the statistic of Fig. 1 next to the mean)
+    for the constructed angles t_j: std(t / (pi/2))."""
+    rng = np.random.default_rng(11)
+    n, k = 40, 7
+    B, X0, Y = _b_orthonormal_pair(rng, n, k)
+    t = np.array([0.0, 0.01, 0.05, 0.2, 0.4, 0.7, 1.0])
+    X = X0 * np.cos(t) + Y * np.sin(t)
+    M = X0.conj().T @ B @ X
+    r = oracle_mod.seed_monitor_from_overlap(M)
+    assert abs(r[4] - np.std(t / (np.pi / 2))) < 1e-7
