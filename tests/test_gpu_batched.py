@@ -62,3 +62,27 @@ def test_batched_seeded_sequence(h, oracle_mod):
             ln = lam.cpu().numpy()[: wl.nev]
             assert np.max(np.abs(ln - lam_ref) / np.maximum(np.abs(lam_ref), 1)) <= TOL
             X[i] = Xi
+
+
+def test_batched_seeded_with_contour_filter(h, oracle_mod):
+    """The contour filter inside the batched solver's workers (one stream per
+    worker: the quadrature nodes run in order there)."""
+    from paper_1007_4400_amd import gevp
+
+    wls = synth.batched_workloads(count=3, nmin=120, nmax=200, seed=7, steps=2)
+    opts = gevp.make_opts(precision="fp64", filter="contour", batch_streams=3)
+    seqs = [list(synth.sequence(wl, s)) for wl, s in wls]
+    X = [None] * len(wls)
+    for k in range(2):
+        probs = [{"A": _dev(seq[k][0]), "B": _dev(seq[k][1]), "nev": wl.nev, "X0": X[i],
+                  "kx": h.block_size(wl.n, wl.nev, opts)} for i, ((wl, _), seq) in enumerate(zip(wls, seqs))]
+        out = h.solve_batched(probs, tol=TOL, opts=opts)
+        for i, ((lam, Xi, res, info), (wl, _), seq) in enumerate(zip(out, wls, seqs)):
+            A, B = seq[k]
+            lam_ref, _ = oracle_mod.solve(A, B, wl.nev)
+            ln = lam.cpu().numpy()[: wl.nev]
+            assert np.max(np.abs(ln - lam_ref) / np.maximum(np.abs(lam_ref), 1)) <= TOL
+            r, orth = oracle_mod.residuals(A, B, ln, Xi.cpu().numpy()[:, : wl.nev])
+            assert r.max() <= TOL * np.linalg.norm(A, 2) and orth <= 1e-9
+            assert (info["contour_applications"] >= 1) == (k > 0)
+            X[i] = Xi
