@@ -85,7 +85,7 @@ typedef struct {
  * sum_j w_j (z_j I - C)^{-1} to the block, the trapezoidal rule on a circle
  * around the wanted eigenvalues (see gevp_k_contour_filter).  It needs the
  * Ritz values of a seed to place the circle, so it is used for seeded solves
- * with k0 > nev; other solves take the Chebyshev filter.  Its factorisations
+ * with k0 > nev (and n <= 65535); other solves take the Chebyshev filter.  Its factorisations
  * and solves are FP64 whatever opts.precision says. */
 typedef enum {
   GEVP_FILTER_CHEBYSHEV = 0,
@@ -294,7 +294,7 @@ gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
  * below the diagonal, U on and above).  C (device complex128 n x n) is read in
  * full.  For Hermitian C and zi != 0 every pivot is nonzero in exact
  * arithmetic (-i (z I - C) has Hermitian part zi I); for other inputs the
- * factorisation may break down.  Synchronous; returns GEVP_ERR_SINGULAR with
+ * factorisation may break down.  n <= 65535.  Synchronous; returns GEVP_ERR_SINGULAR with
  * *pivot = the first zero or non-finite pivot (1-based), else *pivot = 0. */
 gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t ldc, double zr,
                               double zi, void* LU, int64_t ldlu, int64_t* pivot);
@@ -306,7 +306,7 @@ gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t l
  * so an eigenvector of a Hermitian C with eigenvalue lambda is scaled by
  * 1 / (1 + t^nq), t = (lambda - gamma) / rho.  C: device complex128 n x n
  * (read in full); V: n x m; Y: n x m (must not overlap V); a < b finite,
- * 1 <= nq <= 256.  Factors every z_j I - C (workspace nq n^2 complex128).
+ * 1 <= nq <= 256, n and m <= 65535.  Factors every z_j I - C (workspace nq n^2 complex128).
  * Synchronous; GEVP_ERR_SINGULAR if a factorisation broke down. */
 gevp_status gevp_k_contour_filter(gevp_handle h, int64_t n, const void* C, int64_t ldc,
                                   const void* V, int64_t ldv, int64_t m, double a, double b, int nq,

@@ -30,6 +30,7 @@
 namespace {
 constexpr int NB = 64;
 constexpr int QSTREAMS = 4;
+constexpr int64_t GRID_Y_MAX = 65535;  // column kernels put the column index in grid.y
 constexpr int CGS = 16;       // column groups of the block LU (one per wave)
 constexpr int EPT = NB / CGS; // entries per thread
 
@@ -461,7 +462,8 @@ extern "C" {
 
 gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t ldc, double zr,
                               double zi, void* LU, int64_t ldlu, int64_t* pivot) {
-  if (!h || n < 1 || !C || ldc < n || !LU || ldlu < n || !std::isfinite(zr) || !std::isfinite(zi))
+  if (!h || n < 1 || n > GRID_Y_MAX || !C || ldc < n || !LU || ldlu < n || !std::isfinite(zr) ||
+      !std::isfinite(zi))
     return GEVP_ERR_INVALID;
   GEVP_HIP_TRY(hipSetDevice(h->device));
   GEVP_TRY(ws_reserve(h, 2 * ws_round(sizeof(zd) * n * NB) + ws_round(sizeof(int) * 4) + 256));
@@ -485,7 +487,8 @@ gevp_status gevp_k_lu_shifted(gevp_handle h, int64_t n, const void* C, int64_t l
 gevp_status gevp_k_contour_filter(gevp_handle h, int64_t n, const void* C, int64_t ldc,
                                   const void* V, int64_t ldv, int64_t m, double a, double b, int nq,
                                   void* Y, int64_t ldy) {
-  if (!h || n < 1 || !C || ldc < n || !V || ldv < n || m < 0 || !Y || ldy < n)
+  if (!h || n < 1 || n > GRID_Y_MAX || !C || ldc < n || !V || ldv < n || m < 0 ||
+      m > GRID_Y_MAX || !Y || ldy < n)
     return GEVP_ERR_INVALID;
   if (!(a < b) || !std::isfinite(a) || !std::isfinite(b) || nq < 1 || nq > 256)
     return GEVP_ERR_INVALID;

@@ -354,7 +354,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   const bool seeded = (X0_ != nullptr && k0 > 0);
   // the contour filter places its circle from the seed's Ritz values, which
   // needs the first unwanted one (column nev) to come from the seed
-  const bool contour = o.filter == GEVP_FILTER_CONTOUR && seeded && k0 > nev && nb > nev;
+  const bool contour =
+      o.filter == GEVP_FILTER_CONTOUR && seeded && k0 > nev && nb > nev && n <= 65535;
   const bool lp = mixed && !contour;  // low-precision Chebyshev filter in use
   GEVP_HIP_TRY(hipSetDevice(h->device));
   gevp_ctx* c = h;
