@@ -272,12 +272,14 @@ def _calibration_copy():
     del src, dst
 
 
-def _update_apply_bytes(mask_words, n):
+def _update_apply_bytes(mask_words, n, rechecked):
     """Bytes the apply kernel has to move for one update, from its mask: a
-    tile with no update moves nothing, a tile updated everywhere reads A_new
-    and writes A (32 bytes per lower entry), any other tile re-reads both
-    matrices (32 bytes per lower entry) and writes its updated entries (16
-    bytes each); every mask word of the n columns is written (4 bytes)."""
+    tile with no update moves nothing; a tile updated everywhere reads A_new
+    and writes A (32 bytes per lower entry); any other tile reads the scan's
+    2-byte code per entry, A_new and A for every taken entry (16 + 16 bytes),
+    and A and A_new for every entry whose code tied with the threshold's
+    (`rechecked`, 32 bytes); every mask word of the n columns is written (4
+    bytes)."""
     import numpy as np
 
     words = mask_words.shape[1]
@@ -294,7 +296,8 @@ def _update_apply_bytes(mask_words, n):
     low = np.tril(np.ones((nt, nt), dtype=bool))
     full = low & (u == e)
     part = low & (u > 0) & (u < e)
-    return int(32 * e[full].sum() + 32 * e[part].sum() + 16 * u[part].sum() + 4 * n * words)
+    return int(32 * e[full].sum() + 2 * e[part].sum() + 32 * u[part].sum() + 32 * rechecked +
+               4 * n * words)
 
 
 def run_update(args):
@@ -346,7 +349,7 @@ def run_update(args):
     for k in range(args.warmup + 1, nsteps + 1):
         inf = h.update_thresholded(A_chk, As[k], wl.p_t, mask=mask)
         assert inf["updated"] == infos[k - args.warmup - 1]["updated"]
-        apply_bytes.append(_update_apply_bytes(mask.cpu().numpy(), wl.n))
+        apply_bytes.append(_update_apply_bytes(mask.cpu().numpy(), wl.n, inf["rechecked"]))
     same = bool(torch.equal(torch.view_as_real(A_chk), torch.view_as_real(A_cur)))
     del A_chk
     for i, inf in enumerate(infos):
@@ -355,7 +358,7 @@ def run_update(args):
             f"scan {inf['scan_ms']:.3f} ms apply {inf['apply_ms']:.3f} ms")
     scan_ms = sum(i["scan_ms"] for i in infos)
     apply_ms = sum(i["apply_ms"] for i in infos)
-    scan_bytes = 32.0 * entries  # both matrices' lower triangles, once
+    scan_bytes = 34.0 * entries  # both matrices' lower triangles read once, a 2-byte code written
     k_scan = {"kernel": "k_upd_scan", "avg_launch_ms": scan_ms / len(infos),
               "bytes_per_launch": scan_bytes,
               "achieved": scan_bytes * len(infos) / (scan_ms * 1e-3) / 1e9 if scan_ms > 0 else 0.0}
@@ -378,14 +381,16 @@ def run_update(args):
             "traffic": committed_traffic(dom["kernel"], tag),
             "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
             "avg_launch_ms": dom["avg_launch_ms"], "bytes_per_launch": dom["bytes_per_launch"],
-            "algorithmic_bytes_per_unit": ("scan: 32 per lower-triangle entry (A and A_new read); "
-                                           "apply: per tile, 0 / 32 per entry / 32 per entry + 16 "
-                                           "per updated entry, plus 4 per mask word"),
+            "algorithmic_bytes_per_unit": ("scan: 34 per lower-triangle entry (A and A_new read, "
+                                           "code written); apply: per tile, 0 / 32 per entry / 2 per "
+                                           "entry + 32 per taken or re-checked entry, plus 4 per "
+                                           "mask word"),
         },
         "kernels": {"scan": k_scan, "apply": k_apply},
         "updated_fraction": [i["updated"] / entries for i in infos],
         "tiles_touched": [i["tiles_touched"] for i in infos],
         "tiles_copied": [i["tiles_copied"] for i in infos],
+        "rechecked": [i["rechecked"] for i in infos],
         "replay_identical": same,
     }
     if not args.no_cpu_baseline:

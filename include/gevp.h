@@ -342,6 +342,9 @@ typedef struct {
   double scan_ms, apply_ms; /* profiling flag 2 and info given: durations of the scan
                                and the apply kernel (HIP events on the handle's
                                stream); else 0 */
+  int64_t rechecked;       /* entries whose 16-bit code of |dA|^2 tied with the
+                              threshold's and were decided by re-reading both
+                              matrices */
 } gevp_update_info;
 
 /*

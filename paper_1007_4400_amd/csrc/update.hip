@@ -11,13 +11,20 @@
 // four waves per tile, one wave instruction per column segment (64 complex
 // entries = 1 KiB contiguous), 16 columns per wave with all loads issued before
 // the first use.  The passes are HBM-bound:
-//   scan   reads A and A_new (32 bytes per entry) and keeps per-tile max and
-//          min of |dA|^2 plus a non-finite flag;
+//   scan   reads A and A_new (32 bytes per entry), keeps per-tile max and
+//          min of |dA|^2 plus a non-finite flag, and writes a 16-bit code per
+//          entry: the top 16 bits of the IEEE pattern of |dA|^2, monotone in
+//          the value (non-negative doubles order like their bit patterns);
 //   delta  (one work-group) reduces the tile maxima to the threshold;
 //   apply  skips tiles whose max is at or below the threshold (no matrix
 //          traffic), copies tiles whose min is above it without re-reading A,
-//          and re-reads and updates the rest entry by entry; the mask words
-//          are wave ballots (bit r = row r of the column segment);
+//          and decides the rest from the codes: a code above the threshold's
+//          code means above threshold, below means not, and only entries whose
+//          code ties are re-read (both matrices) and compared exactly, so the
+//          decisions are those of the plain comparison bit for bit while a
+//          mixed tile reads 2 bytes per entry plus A_new where it is taken;
+//          the mask words are wave ballots (bit r = row r of the column
+//          segment);
 //   count  (one work-group) sums the per-tile counts and gathers the result.
 // Addresses past the matrix edge (ragged last tile) and above the diagonal of a
 // diagonal tile are clamped into the n x n storage and their values discarded,
@@ -61,6 +68,12 @@ __device__ __forceinline__ void tile_of(int64_t t, int64_t& bi, int64_t& bj) {
   bj = t - r * (r + 1) / 2;
 }
 
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -72,11 +85,17 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+__device__ __forceinline__ unsigned code_of(double s) {
+  return (unsigned)((unsigned long long)__double_as_longlong(s) >> 48);
+}
+
 __global__ __launch_bounds__(UTHREADS) void k_upd_scan(int64_t n, const zd* __restrict__ A,
                                                        int64_t lda, const zd* __restrict__ An,
                                                        int64_t ldn, double* __restrict__ tmax,
                                                        double* __restrict__ tmin,
-                                                       int* __restrict__ tbad) {
+                                                       int* __restrict__ tbad,
+                                                       uint16_t* __restrict__ code) {
+  uint16_t* tc = code + (size_t)blockIdx.x * UT * UT;
   __shared__ double smx[4], smn[4];
   __shared__ int sbad[4];
   int64_t bi, bj;
@@ -97,6 +116,7 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_scan(int64_t n, const zd* __re
 #pragma unroll
   for (int c = 0; c < UCOLS; ++c) {
     const int64_t j = bj * UT + w + 4 * c;
+    unsigned cd = 0;
     if (i < n && j <= i) {
       const double s = sqdiff(a[c], b[c]);
       if (!(s <= DBL_MAX)) {
@@ -104,8 +124,10 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_scan(int64_t n, const zd* __re
       } else {
         mx = fmax(mx, s);
         mn = fmin(mn, s);
+        cd = code_of(s);
       }
     }
+    tc[(w + 4 * c) * UT + l] = (uint16_t)cd;
   }
   mx = wave_max(mx);
   mn = wave_min(mn);
@@ -173,8 +195,8 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
     int64_t n, zd* __restrict__ A, int64_t lda, const zd* __restrict__ An, int64_t ldn,
     const double* __restrict__ tmax, const double* __restrict__ tmin, const double* __restrict__ scal,
     const int* __restrict__ flag, uint32_t* __restrict__ mask, int64_t ldmask, int* __restrict__ tcnt,
-    int* __restrict__ tkind) {
-  __shared__ int scnt[4];
+    int* __restrict__ tkind, const uint16_t* __restrict__ code, int* __restrict__ tamb) {
+  __shared__ int scnt[4], samb[4];
   int64_t bi, bj;
   tile_of(blockIdx.x, bi, bj);
   const int l = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -186,7 +208,7 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
     const int64_t jm = bi * UT + (threadIdx.x >> 1);
     if (jm < n) mask[jm * ldmask + 2 * bj + (threadIdx.x & 1)] = 0u;
   }
-  int cnt = 0;
+  int cnt = 0, amb = 0;
   if (none) {
     if (mask) {
 #pragma unroll 4
@@ -214,73 +236,98 @@ __global__ __launch_bounds__(UTHREADS) void k_upd_apply(
       if (mask && j < n) put_mask(mask, ldmask, n, bi, j, bits, l);
     }
   } else {
+    // decide from the codes; loads only where needed (A_new when the code is
+    // at or above the threshold's, A as well on a tie); lanes that need no
+    // entry read the tile's first one, a single shared address
+    const uint16_t* tc = code + (size_t)blockIdx.x * UT * UT;
+    const unsigned ct = code_of(thr);
     const int64_t ic = i < n ? i : n - 1;
+    const int64_t safe_a = bi * UT + bj * UT * lda, safe_n = bi * UT + bj * UT * ldn;
+    unsigned cd[UCOLS];
+#pragma unroll
+    for (int c = 0; c < UCOLS; ++c) cd[c] = tc[(w + 4 * c) * UT + l];
     zd a[UCOLS], b[UCOLS];
 #pragma unroll
     for (int c = 0; c < UCOLS; ++c) {
       int64_t j = bj * UT + w + 4 * c;
+      const bool valid = i < n && j <= i;
       j = j < n ? j : n - 1;
-      a[c] = A[ic + j * lda];
-      b[c] = An[ic + j * ldn];
+      b[c] = An[(valid && cd[c] >= ct) ? ic + j * ldn : safe_n];
+      a[c] = A[(valid && cd[c] == ct) ? ic + j * lda : safe_a];
     }
 #pragma unroll
     for (int c = 0; c < UCOLS; ++c) {
       const int64_t j = bj * UT + w + 4 * c;
-      const bool ok = i < n && j <= i && sqdiff(a[c], b[c]) > thr;
+      const bool valid = i < n && j <= i;
+      const bool tie = valid && cd[c] == ct;
+      const bool ok = valid && (cd[c] > ct || (tie && sqdiff(a[c], b[c]) > thr));
+      amb += tie ? 1 : 0;
       if (ok) A[i + j * lda] = b[c];
       const uint64_t bits = __ballot(ok);
       cnt += __popcll(bits);
       if (mask && j < n) put_mask(mask, ldmask, n, bi, j, bits, l);
     }
   }
-  if (l == 0) scnt[w] = cnt;
+  amb = (int)wave_sum_int(amb);
+  if (l == 0) {
+    scnt[w] = cnt;
+    samb[w] = amb;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     tcnt[blockIdx.x] = scnt[0] + scnt[1] + scnt[2] + scnt[3];
     tkind[blockIdx.x] = none ? 0 : (all ? 2 : 1);
+    tamb[blockIdx.x] = samb[0] + samb[1] + samb[2] + samb[3];
   }
 }
 
 // out[0] = entries updated, out[1] = tiles with any update, out[2] = tiles
-// copied whole, out[3] = the non-finite flag, out[4] = delta's bits: the whole
-// result in one block for a single copy to the host
+// copied whole, out[3] = the non-finite flag, out[4] = delta's bits, out[5] =
+// entries decided by an exact re-check: the whole result in one block for a
+// single copy to the host
 __global__ __launch_bounds__(1024) void k_upd_count(int64_t tiles, const int* __restrict__ tcnt,
                                                     const int* __restrict__ tkind,
+                                                    const int* __restrict__ tamb,
                                                     const double* __restrict__ scal,
                                                     const int* __restrict__ flag,
                                                     long long* __restrict__ out) {
-  __shared__ long long s0[16], s1[16], s2[16];
-  long long c0 = 0, c1 = 0, c2 = 0;
+  __shared__ long long s0[16], s1[16], s2[16], s3[16];
+  long long c0 = 0, c1 = 0, c2 = 0, c3 = 0;
   for (int64_t t = threadIdx.x; t < tiles; t += 1024) {
     c0 += tcnt[t];
     c1 += tcnt[t] > 0;
     c2 += tkind[t] == 2;
+    c3 += tamb[t];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     c0 += __shfl_xor(c0, o, 64);
     c1 += __shfl_xor(c1, o, 64);
     c2 += __shfl_xor(c2, o, 64);
+    c3 += __shfl_xor(c3, o, 64);
   }
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (l == 0) {
     s0[w] = c0;
     s1[w] = c1;
     s2[w] = c2;
+    s3[w] = c3;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long a = 0, b = 0, c = 0;
+    long long a = 0, b = 0, c = 0, d = 0;
     for (int k = 0; k < 16; ++k) {
       a += s0[k];
       b += s1[k];
       c += s2[k];
+      d += s3[k];
     }
     out[0] = a;
     out[1] = b;
     out[2] = c;
     out[3] = flag[0];
     out[4] = __double_as_longlong(scal[2]);
+    out[5] = d;
   }
 }
 
@@ -332,7 +379,8 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   if (mask && (ldmask < words || ((uintptr_t)mask & 3))) return GEVP_ERR_INVALID;
   if (tiles > INT32_MAX || n > INT32_MAX) return GEVP_ERR_INVALID;
   GEVP_HIP_TRY(hipSetDevice(h->device));
-  const size_t need = 2 * ws_round(sizeof(double) * tiles) + 3 * ws_round(sizeof(int) * tiles) +
+  const size_t need = 2 * ws_round(sizeof(double) * tiles) + 4 * ws_round(sizeof(int) * tiles) +
+                      ws_round(sizeof(uint16_t) * UT * UT * (size_t)tiles) +
                       ws_round(sizeof(double) * 4) + ws_round(sizeof(int) * 4) +
                       ws_round(sizeof(long long) * 8) + 256;
   GEVP_TRY(ws_reserve(h, need));
@@ -341,6 +389,8 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   int* tbad = (int*)ws_take(h, sizeof(int) * tiles);
   int* tcnt = (int*)ws_take(h, sizeof(int) * tiles);
   int* tkind = (int*)ws_take(h, sizeof(int) * tiles);
+  int* tamb = (int*)ws_take(h, sizeof(int) * tiles);
+  uint16_t* code = (uint16_t*)ws_take(h, sizeof(uint16_t) * UT * UT * (size_t)tiles);
   double* scal = (double*)ws_take(h, sizeof(double) * 4);
   int* flag = (int*)ws_take(h, sizeof(int) * 4);
   long long* out = (long long*)ws_take(h, sizeof(long long) * 8);
@@ -353,21 +403,21 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
     GEVP_TRY(fev_mark(h));
   }
   hipLaunchKernelGGL(k_upd_scan, dim3((unsigned)tiles), dim3(UTHREADS), 0, h->stream, n, A, lda,
-                     An, ldn, tmax, tmin, tbad);
+                     An, ldn, tmax, tmin, tbad, code);
   GEVP_HIP_TRY(hipGetLastError());
   if (timed) GEVP_TRY(fev_mark(h));
   hipLaunchKernelGGL(k_upd_delta, dim3(1), dim3(1024), 0, h->stream, tiles, tmax, tbad, p_t, scal,
                      flag);
   if (timed) GEVP_TRY(fev_mark(h));
   hipLaunchKernelGGL(k_upd_apply, dim3((unsigned)tiles), dim3(UTHREADS), 0, h->stream, n, A, lda,
-                     An, ldn, tmax, tmin, scal, flag, mask, ldmask, tcnt, tkind);
+                     An, ldn, tmax, tmin, scal, flag, mask, ldmask, tcnt, tkind, code, tamb);
   GEVP_HIP_TRY(hipGetLastError());
   if (timed) GEVP_TRY(fev_mark(h));
   if (!info) return GEVP_OK;
-  hipLaunchKernelGGL(k_upd_count, dim3(1), dim3(1024), 0, h->stream, tiles, tcnt, tkind, scal, flag,
-                     out);
+  hipLaunchKernelGGL(k_upd_count, dim3(1), dim3(1024), 0, h->stream, tiles, tcnt, tkind, tamb, scal,
+                     flag, out);
   GEVP_HIP_TRY(hipGetLastError());
-  long long ho[5];
+  long long ho[6];
   GEVP_HIP_TRY(hipMemcpyAsync(ho, out, sizeof(ho), hipMemcpyDeviceToHost, h->stream));
   GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
   if (timed) {
@@ -385,6 +435,7 @@ gevp_status gevp_update_thresholded(gevp_handle h, int64_t n, void* A_, int64_t 
   info->updated = ho[0];
   info->tiles_touched = ho[1];
   info->tiles_copied = ho[2];
+  info->rechecked = ho[5];
   return ho[3] ? GEVP_ERR_NONFINITE : GEVP_OK;
 }
 

@@ -64,6 +64,7 @@ class UpdateInfo(ctypes.Structure):
         ("tiles", ctypes.c_int64), ("tiles_touched", ctypes.c_int64),
         ("tiles_copied", ctypes.c_int64), ("nonfinite", ctypes.c_int), ("reserved", ctypes.c_int),
         ("scan_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
+        ("rechecked", ctypes.c_int64),
     ]
 
     def as_dict(self):
