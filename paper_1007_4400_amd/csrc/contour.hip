@@ -19,10 +19,11 @@
 // products with those inverses, and the trailing matrix gets one FP64
 // matrix-core GEMM per panel (K = 256).  The nq factorisations are
 // independent and run on four streams (the caller's and three more), so one
-// factorisation's latency-bound diagonal blocks overlap another's GEMMs.  Applying the filter is two triangular
-// solves per node (the existing recursive lower solve with the unit-lower
-// block inverses, and an upper solve written here), accumulated with the
-// complex weights.
+// factorisation's latency-bound diagonal blocks overlap another's GEMMs.
+// Applying the filter is two triangular solves per node (the existing
+// recursive lower solve with the unit-lower block inverses, and an upper solve
+// written here), accumulated with the complex weights into one partial sum per
+// stream.
 #include <cmath>
 
 #include "common.h"
