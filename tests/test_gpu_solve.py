@@ -214,3 +214,34 @@ def test_seed_monitor_entry_matches_oracle(h, oracle_mod, k, kind):
     assert abs(m - mo) <= 1e-9 and abs(x - xo) <= 1e-9
     assert abs(sd - sdo) <= 1e-9
     assert r == ro and list(pio) == match
+
+
+def _rand_pencil(n, seed, cond_b=10.0):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = 0.5 * (G + G.conj().T)
+    F = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(F)
+    B = (Q * np.geomspace(1.0, cond_b, n)) @ Q.conj().T
+    return A, 0.5 * (B + B.conj().T)
+
+
+@pytest.mark.parametrize("n,nev,precision", [(1, 1, "fp64"), (2, 1, "fp64"), (2, 2, "fp64"),
+                                             (17, 17, "fp64"), (64, 48, "fp64"), (65, 1, "fp64"),
+                                             (65, 64, "bf16x3"), (130, 7, "fp32"),
+                                             (129, 100, "bf16x3")])
+def test_edge_sizes(h, oracle_mod, n, nev, precision):
+    """Degenerate and ragged shapes: n = 1 and 2, the whole spectrum
+    (nev = n), a block capped at n, sizes just past one 64-wide tile, every
+    precision; cold and then seeded from the cold result."""
+    from paper_1007_4400_amd import gevp
+
+    print(f"edge n={n} nev={nev} {precision}", flush=True)
+    A, B = _rand_pencil(n, 1000 + n + nev)
+    o = gevp.make_opts(precision=precision)
+    kx = h.block_size(n, nev, o)
+    assert nev <= kx <= n
+    lam, X, _, info = h.solve(_dev(A), _dev(B), nev, tol=TOL, kx=kx, opts=o)
+    _check(oracle_mod, A, B, lam, X, nev)
+    lam2, X2, _, info2 = h.solve(_dev(A), _dev(B), nev, X0=X, tol=TOL, kx=kx, opts=o)
+    _check(oracle_mod, A, B, lam2, X2, nev)
