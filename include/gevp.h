@@ -85,8 +85,11 @@ typedef struct {
  * sum_j w_j (z_j I - C)^{-1} to the block, the trapezoidal rule on a circle
  * around the wanted eigenvalues (see gevp_k_contour_filter).  It needs the
  * Ritz values of a seed to place the circle, so it is used for seeded solves
- * with k0 > nev (and n <= 65535); other solves take the Chebyshev filter.  Its factorisations
- * and solves are FP64 whatever opts.precision says. */
+ * with k0 > nev (and n <= 65535); other solves take the Chebyshev filter.  With
+ * opts.precision = GEVP_FP64 its factorisations and solves are FP64; with
+ * GEVP_FP32 or GEVP_BF16X3 they are FP32 and act only on the Ritz residuals
+ * (residual-correction form: (z I - C)^{-1} q = [q + (z I - C)^{-1} r] / (z - theta)
+ * for a Ritz pair), so the result still reaches FP64 residuals. */
 typedef enum {
   GEVP_FILTER_CHEBYSHEV = 0,
   GEVP_FILTER_CONTOUR = 1

@@ -5,9 +5,11 @@
 //
 // with per-column coefficients (device float64 arrays, one entry per active
 // column).  C is the FP32 copy of the reduced matrix, G the current iterate,
-// P the previous one (D may alias P) and R the FP32 residual block.  Same
-// tiling, LDS staging and XCD-aware tile order as the FP64 kernel; the
-// accumulators are FP32.
+// P the previous one (D may alias P) and R the FP32 residual block.  With
+// beta_j = 0 the G term is not read, so the kernel also serves general
+// products D = alpha A G + gamma P (A of m rows, G of k rows).  Same tiling,
+// LDS staging and XCD-aware tile order as the FP64 kernel; the accumulators
+// are FP32.
 #include "common.h"
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -136,8 +138,12 @@ __global__ __launch_bounds__(NTHR, 2) void k_cgemm32_filter(CgemmParams p) {
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wr * 32 + i * 16 + 4 * lg + r;
         if (row >= p.M) continue;
-        const zf g = p.B[row + (int64_t)col * p.ldb];
-        float vr = al * accR[i][j][r] + be * g.x, vi = al * accI[i][j][r] + be * g.y;
+        float vr = al * accR[i][j][r], vi = al * accI[i][j][r];
+        if (be != 0.f) {  // G(row, col) exists only for square products (the filter's)
+          const zf g = p.B[row + (int64_t)col * p.ldb];
+          vr += be * g.x;
+          vi += be * g.y;
+        }
         if (ga != 0.f) {
           const zf q = p.P[row + (int64_t)col * p.ldp];
           vr += ga * q.x;

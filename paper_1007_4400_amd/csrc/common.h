@@ -124,6 +124,21 @@ gevp_status contour_factor(gevp_ctx* c, int64_t n, const zd* C, int64_t ldc, dou
                            int nq, void* work, int64_t mmax, int* pivot);
 gevp_status contour_apply(gevp_ctx* c, int64_t n, int64_t m, const zd* V, int64_t ldv, zd* Y,
                           int64_t ldy, double a, double b, int nq, void* work, int64_t mmax);
+// FP32 form (residual correction): contour_factor32 factors the nq shifted
+// matrices in complex64 into `work` (contour32_work_bytes); contour_residual
+// forms R(:, j) = W(:, perm[j]) - theta[perm[j]] Qp(:, j) and thp[j] =
+// theta[perm[j]] for j in [s0, nb) (Qp: the degree-sorted Ritz vectors);
+// contour_apply32 then forms Y = f(theta) Q + sum_j w_j (z_j I - C)^{-1} R
+// diag(1 / (z_j - theta)) for m columns, the solves in FP32.
+size_t contour32_work_bytes(int64_t n, int64_t mmax, int nq);
+gevp_status contour_factor32(gevp_ctx* c, int64_t n, const zd* C, int64_t ldc, double a, double b,
+                             int nq, void* work, int64_t mmax, int* pivot);
+gevp_status contour_residual(gevp_ctx* c, int64_t n, int64_t nb, int64_t s0, const int* perm,
+                             const zd* W, int64_t ldw, const double* theta, const zd* Qp, int64_t ldq,
+                             zd* R, int64_t ldr, double* thp);
+gevp_status contour_apply32(gevp_ctx* c, int64_t n, int64_t m, const zd* Q, int64_t ldq, const zd* R,
+                            int64_t ldr, const double* theta, zd* Y, int64_t ldy, double a, double b,
+                            int nq, void* work, int64_t mmax);
 
 // Small Hermitian eigensolver (n <= 2048): H (full storage, overwritten),
 // theta ascending, Z (n x n) unitary.  work >= heev_work_bytes(n).

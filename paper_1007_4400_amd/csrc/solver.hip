@@ -357,6 +357,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   const bool contour =
       o.filter == GEVP_FILTER_CONTOUR && seeded && k0 > nev && nb > nev && n <= 65535;
   const bool lp = mixed && !contour;  // low-precision Chebyshev filter in use
+  const bool c32 = contour && mixed;  // contour filter in FP32, residual-correction form
   GEVP_HIP_TRY(hipSetDevice(h->device));
   gevp_ctx* c = h;
   c->fev_used = 0;
@@ -386,7 +387,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
   need += ws_round(sizeof(double) * 4);                  // norms
   need += ws_round(sizeof(double) * (3 * nb + 8));       // seed monitor
-  if (contour) need += contour_work_bytes(n, nb, o.nq);  // nq factorisations
+  if (contour)  // nq factorisations
+    need += c32 ? contour32_work_bytes(n, nb, o.nq) : contour_work_bytes(n, nb, o.nq);
   const size_t lp_elem = 8;                              // complex64
   if (lp) {
     need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
@@ -427,7 +429,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
   double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 8));  // per-column stats, then 6 results
-  void* cw = contour ? ws_take(c, contour_work_bytes(n, nb, o.nq)) : nullptr;
+  void* cw = contour ? ws_take(c, c32 ? contour32_work_bytes(n, nb, o.nq)
+                                       : contour_work_bytes(n, nb, o.nq))
+                     : nullptr;
   void* Clp = nullptr;
   void* bfw = nullptr;  // split-BF16 filter workspace
   void* G0 = nullptr;
@@ -704,7 +708,10 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
         ca = th[0] - 0.05 * wdt;
         if (!(ca < cb) || !std::isfinite(ca) || !std::isfinite(cb)) return GEVP_ERR_NONFINITE;
         int piv = 0;
-        GEVP_TRY(contour_factor(c, n, C, n, ca, cb, o.nq, cw, nb, &piv));
+        if (c32)
+          GEVP_TRY(contour_factor32(c, n, C, n, ca, cb, o.nq, cw, nb, &piv));
+        else
+          GEVP_TRY(contour_factor(c, n, C, n, ca, cb, o.nq, cw, nb, &piv));
         if (piv) return GEVP_ERR_SINGULAR;
         cfact = true;
         info->contour_points = o.nq;
@@ -716,8 +723,15 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       const int64_t s0 = hst[4];
       GEVP_TRY(launch_gather_cols(c, n, nb, P0, n, perm, P1, n));
       if (s0 > 0) GEVP_TRY(launch_copy2d(c, n, s0, P1, n, P0, n));
-      if (s0 < nb)
+      if (s0 < nb && c32) {
+        // residuals of the active Ritz pairs (W = C P0 from the Rayleigh-Ritz
+        // step) into T, their Ritz values into fres (free until the final stage)
+        GEVP_TRY(contour_residual(c, n, nb, s0, perm, W, n, theta, P1, n, T, n, fres));
+        GEVP_TRY(contour_apply32(c, n, nb - s0, P1 + s0 * n, n, T + s0 * n, n, fres + s0,
+                                 P0 + s0 * n, n, ca, cb, o.nq, cw, nb));
+      } else if (s0 < nb) {
         GEVP_TRY(contour_apply(c, n, nb - s0, P1 + s0 * n, n, P0 + s0 * n, n, ca, cb, o.nq, cw, nb));
+      }
       info->contour_columns += nb - s0;
       ++info->contour_applications;
     } else if (lp) {

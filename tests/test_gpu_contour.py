@@ -116,15 +116,19 @@ def _check(oracle_mod, A, B, lam, X, nev):
     assert orth <= 1e-9
 
 
-@pytest.mark.parametrize("n,base", [(300, "small"), (640, "medium")])
-def test_seeded_solve_with_contour_filter(oracle_mod, h, n, base):
+@pytest.mark.parametrize("n,base,precision", [(300, "small", "fp64"), (640, "medium", "fp64"),
+                                              (300, "small", "fp32"), (640, "medium", "fp32"),
+                                              (257, "medium", "bf16x3")])
+def test_seeded_solve_with_contour_filter(oracle_mod, h, n, base, precision):
+    """FP64 factorisations, or FP32 ones in the residual-correction form
+    (fp32 and bf16x3 options), to the same parity bar."""
     from paper_1007_4400_amd import gevp
 
-    print(f"contour solve n={n}", flush=True)
+    print(f"contour solve n={n} {precision}", flush=True)
     wl = synth.scaled(synth.SMALL if base == "small" else synth.MEDIUM, n, steps=3)
     seq = list(synth.sequence(wl, 21))
     o64 = gevp.make_opts(precision="fp64")
-    oc = gevp.make_opts(precision="fp64", filter="contour")
+    oc = gevp.make_opts(precision=precision, filter="contour")
     kx = h.block_size(n, wl.nev, o64)
     A0, B = seq[0]
     lam, X, _, info = h.solve(_dev(A0), _dev(B), wl.nev, kx=kx, opts=o64)
