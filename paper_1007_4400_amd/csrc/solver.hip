@@ -848,6 +848,9 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
     w->inner_streams = false;
     h->workers.push_back(w);
   }
+  // event timing of the filter launches (profiling flag 2) carries over; the
+  // per-stage timer (flag 1) would synchronise the workers and is not passed on
+  for (int w = 0; w < streams; ++w) h->workers[w]->profiling = h->profiling & 2;
   // the worker streams start after the work already queued on the caller's stream
   hipEvent_t ready;
   GEVP_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
