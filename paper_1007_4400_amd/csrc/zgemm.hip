@@ -72,10 +72,10 @@ struct ZgemmParams {
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
 
-// FILTER only names the kernel differently for the Chebyshev filter launches
-// (coefficients from device memory), so profiles separate them.
-template <int FILTER>
-__global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
+// One output tile; the operand forms are compile-time constants, so each
+// kernel below carries only its own load and LDS-store pattern.
+template <int OPA, int OPB>
+__device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
   __shared__ zd As[2][KT][PADA];
   __shared__ zd Bs[2][KT][PADB];
 
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
     }
 
   zd ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // next slice, in registers
-  const int opA = p.opA, opB = p.opB;
+  constexpr int opA = OPA, opB = OPB;
 
   // A col-major M x K: thread -> (m = tid%64, k = tid/64 + 4i); A stored K x M
   // ('C'): op(A)(m,k) = conj(A[k + m lda]), k fastest.  B col-major K x N: k
@@ -264,6 +264,16 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) {
     }
 }
 
+// Both operands as stored.  FILTER only names the kernel differently for the
+// Chebyshev filter launches (coefficients from device memory), so profiles
+// separate them.
+template <int FILTER>
+__global__ __launch_bounds__(NTHR, 2) void k_zgemm(ZgemmParams p) { zgemm_tile<0, 0>(p); }
+// op(B) = B^H, op(A) = A^H, both conjugate-transposed
+__global__ __launch_bounds__(NTHR, 2) void k_zgemm_nc(ZgemmParams p) { zgemm_tile<0, 1>(p); }
+__global__ __launch_bounds__(NTHR, 2) void k_zgemm_cn(ZgemmParams p) { zgemm_tile<1, 0>(p); }
+__global__ __launch_bounds__(NTHR, 2) void k_zgemm_cc(ZgemmParams p) { zgemm_tile<1, 1>(p); }
+
 // Split-K: sum of the partial tiles in split order, then the epilogue; one
 // thread per output element, consecutive threads on consecutive rows.
 __global__ __launch_bounds__(256) void k_zgemm_splitk_reduce(ZgemmParams p) {
@@ -387,10 +397,19 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   const int64_t blocks = total * p.splits;
   p.total = (int)blocks;
   p.remap = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
-  if (coef)
-    hipLaunchKernelGGL(k_zgemm<1>, dim3((unsigned)blocks), dim3(NTHR), 0, c->stream, p);
-  else
-    hipLaunchKernelGGL(k_zgemm<0>, dim3((unsigned)blocks), dim3(NTHR), 0, c->stream, p);
+  const dim3 grid((unsigned)blocks), thr(NTHR);
+  if (opA == 0 && opB == 0) {
+    if (coef)
+      hipLaunchKernelGGL(k_zgemm<1>, grid, thr, 0, c->stream, p);
+    else
+      hipLaunchKernelGGL(k_zgemm<0>, grid, thr, 0, c->stream, p);
+  } else if (opA == 0) {
+    hipLaunchKernelGGL(k_zgemm_nc, grid, thr, 0, c->stream, p);
+  } else if (opB == 0) {
+    hipLaunchKernelGGL(k_zgemm_cn, grid, thr, 0, c->stream, p);
+  } else {
+    hipLaunchKernelGGL(k_zgemm_cc, grid, thr, 0, c->stream, p);
+  }
   GEVP_HIP_TRY(hipGetLastError());
   if (p.splits > 1) {
     const int64_t elems = total * BM * BN;
