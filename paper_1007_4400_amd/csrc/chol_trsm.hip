@@ -431,17 +431,22 @@ gevp_status trsm_left_lower_n(gevp_ctx* c, int64_t n, int64_t m, const zd* L, in
 
 // R (n x m) <- L^{-H} R
 gevp_status trsm_left_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
-                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr) {
+                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr, int lhu) {
   if (n <= 0 || m <= 0) return GEVP_OK;
   if (n <= NB)
     return launch_zgemm(c, 1, 0, n, m, n, 1.0, Dinv, ldi, R, ldr, 0.0, nullptr, 0, 0.0, nullptr,
                         0, nullptr, R, ldr);
   const int64_t h = split64(n);
-  GEVP_TRY(trsm_left_lower_c(c, n - h, m, L + h + h * ldl, ldl, Dinv + h, ldi, R + h, ldr));
-  // R1 -= L21^H R2   (L21 is (n-h) x h)
-  GEVP_TRY(launch_zgemm(c, 1, 0, h, m, n - h, -1.0, L + h, ldl, R + h, ldr, 1.0, R, ldr, 0.0,
-                        nullptr, 0, nullptr, R, ldr));
-  return trsm_left_lower_c(c, h, m, L, ldl, Dinv, ldi, R, ldr);
+  GEVP_TRY(trsm_left_lower_c(c, n - h, m, L + h + h * ldl, ldl, Dinv + h, ldi, R + h, ldr, lhu));
+  // R1 -= L21^H R2   (L21 is (n-h) x h; with lhu its conjugate transpose is the
+  // block above the diagonal, read as stored)
+  if (lhu)
+    GEVP_TRY(launch_zgemm(c, 0, 0, h, m, n - h, -1.0, L + h * ldl, ldl, R + h, ldr, 1.0, R, ldr,
+                          0.0, nullptr, 0, nullptr, R, ldr));
+  else
+    GEVP_TRY(launch_zgemm(c, 1, 0, h, m, n - h, -1.0, L + h, ldl, R + h, ldr, 1.0, R, ldr, 0.0,
+                          nullptr, 0, nullptr, R, ldr));
+  return trsm_left_lower_c(c, h, m, L, ldl, Dinv, ldi, R, ldr, lhu);
 }
 
 // R (m x n) <- R L^{-H}
@@ -462,7 +467,8 @@ gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, i
 namespace {
 // rows [c0, n) of columns [c0, c0 + nn) of R <- R L^{-H}
 gevp_status trsm_rlc_lower_rec(gevp_ctx* c, int64_t n, int64_t c0, int64_t nn, const zd* L,
-                               int64_t ldl, const zd* Dinv, int64_t ldi, zd* R, int64_t ldr) {
+                               int64_t ldl, const zd* Dinv, int64_t ldi, zd* R, int64_t ldr,
+                               int lhu) {
   const zd* Lb = L + c0 + c0 * ldl;
   zd* Rb = R + c0 + c0 * ldr;
   const int64_t rows = n - c0;
@@ -470,16 +476,22 @@ gevp_status trsm_rlc_lower_rec(gevp_ctx* c, int64_t n, int64_t c0, int64_t nn, c
     return launch_zgemm(c, 0, 1, rows, nn, nn, 1.0, Rb, ldr, Dinv + c0, ldi, 0.0, nullptr, 0, 0.0,
                         nullptr, 0, nullptr, Rb, ldr);
   const int64_t h = split64(nn);
-  GEVP_TRY(trsm_rlc_lower_rec(c, n, c0, h, L, ldl, Dinv, ldi, R, ldr));
+  GEVP_TRY(trsm_rlc_lower_rec(c, n, c0, h, L, ldl, Dinv, ldi, R, ldr, lhu));
   // R[c0+h:, c0+h : c0+nn] -= R[c0+h:, c0 : c0+h] L21^H,  L21 = L[c0+h : c0+nn, c0 : c0+h]
-  GEVP_TRY(launch_zgemm(c, 0, 1, n - c0 - h, nn - h, h, -1.0, Rb + h, ldr, Lb + h, ldl, 1.0,
-                        Rb + h + h * ldr, ldr, 0.0, nullptr, 0, nullptr, Rb + h + h * ldr, ldr));
-  return trsm_rlc_lower_rec(c, n, c0 + h, nn - h, L, ldl, Dinv, ldi, R, ldr);
+  // (with lhu, L21^H = L[c0 : c0+h, c0+h : c0+nn] as stored)
+  if (lhu)
+    GEVP_TRY(launch_zgemm(c, 0, 0, n - c0 - h, nn - h, h, -1.0, Rb + h, ldr, Lb + h * ldl, ldl,
+                          1.0, Rb + h + h * ldr, ldr, 0.0, nullptr, 0, nullptr, Rb + h + h * ldr,
+                          ldr));
+  else
+    GEVP_TRY(launch_zgemm(c, 0, 1, n - c0 - h, nn - h, h, -1.0, Rb + h, ldr, Lb + h, ldl, 1.0,
+                          Rb + h + h * ldr, ldr, 0.0, nullptr, 0, nullptr, Rb + h + h * ldr, ldr));
+  return trsm_rlc_lower_rec(c, n, c0 + h, nn - h, L, ldl, Dinv, ldi, R, ldr, lhu);
 }
 }  // namespace
 
 gevp_status trsm_right_lower_c_lowerpart(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl,
-                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr) {
+                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr, int lhu) {
   if (n <= 0) return GEVP_OK;
-  return trsm_rlc_lower_rec(c, n, 0, n, L, ldl, Dinv, ldi, R, ldr);
+  return trsm_rlc_lower_rec(c, n, 0, n, L, ldl, Dinv, ldi, R, ldr, lhu);
 }

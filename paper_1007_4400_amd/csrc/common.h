@@ -93,16 +93,19 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
                        int* info_dev, hipEvent_t midpoint = nullptr);
 // R <- L^{-1} R (R n x m) ;  R <- L^{-H} R ;  R <- R L^{-H} (R m x n)
+// lhu = 1: the strictly upper triangle of L holds L^H (see launch_mirror_lower),
+// and the off-diagonal products read those blocks as stored instead of
+// conjugate-transposing the blocks below the diagonal
 gevp_status trsm_left_lower_n(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
                               const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
 gevp_status trsm_left_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
-                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+                              const zd* Dinv, int64_t ldi, zd* R, int64_t ldr, int lhu = 0);
 gevp_status trsm_right_lower_c(gevp_ctx* c, int64_t n, int64_t m, const zd* L, int64_t ldl,
                                const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
 // Lower triangle only of R <- R L^{-H} for square n x n R: rows below each
 // column block's start are all that is computed (the Hermitian C = W L^{-H}).
 gevp_status trsm_right_lower_c_lowerpart(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl,
-                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr);
+                                         const zd* Dinv, int64_t ldi, zd* R, int64_t ldr, int lhu = 0);
 // Inverses of the 64 x 64 diagonal blocks of an already factored L.
 gevp_status diag_block_inverses(gevp_ctx* c, int64_t n, const zd* L, int64_t ldl, zd* Dinv,
                                 int64_t ldi);

@@ -4,7 +4,8 @@
 // One solve (the paper's fast iteration, section 2, seeded by the previous
 // iteration's eigenvectors):
 //   stage    A, B lower triangles -> full Hermitian copies; NaN/Inf scan
-//   chol     B = L L^H (blocked, lookahead on a panel stream)
+//   chol     B = L L^H (blocked, lookahead on a panel stream); L^H X0 for a
+//            seeded solve, then L^H copied into L's upper triangle
 //   reduce   C = L^{-1} A L^{-H} (left solve, then the lower triangle of the
 //            right solve, mirrored)
 //   bounds   Lanczos on C (filter interval), on A and B (norm estimates)
@@ -526,12 +527,21 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     return GEVP_ERR_NOT_HPD;
   }
 
+  // C-space seed y = L^H x, while L's upper triangle is still zero (the
+  // product skips only the zero tiles of L^H)
+  if (seeded)
+    GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, P0, n, nullptr, 0, 1));
+
   // ---------------- reduction to standard form
   tm.start();
+  // from here on the upper triangle of L holds L^H, so the solves with L^H
+  // multiply blocks as stored (the faster operand form of the GEMM)
+  GEVP_TRY(launch_mirror_lower(c, n, L, n, L, n, flags + 3));
   GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
   GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
   // C = W L^{-H} is Hermitian: only its lower triangle is formed, then mirrored
-  GEVP_TRY(trsm_right_lower_c_lowerpart(c, n, L, n, Dinv, n, C, n));
+  GEVP_TRY(trsm_right_lower_c_lowerpart(c, n, L, n, Dinv, n, C, n, 1));
   GEVP_TRY(launch_mirror_lower(c, n, C, n, C, n, flags + 3));
   if (lp && bf16) GEVP_TRY(launch_split_rows_bf16(c, n, C, n, Clp));
   if (lp && !bf16) GEVP_TRY(launch_to_c32(c, n, n, C, n, Clp, n));
@@ -549,11 +559,6 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   tm.stop(info, GEVP_STAGE_BOUNDS);
 
   // ---------------- initial block
-  if (seeded) {
-    // C-space seed: y = L^H x
-    GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, P0, n, nullptr, 0, 1));
-  }
   const int64_t kseed = seeded ? k0 : 0;
   GEVP_TRY(launch_randn(c, n, nb - kseed, P0 + kseed * n, n, kseed, o.seed));
 
@@ -747,7 +752,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // ---------------- back-transform and final residuals
   tm.start();
   GEVP_TRY(launch_copy2d(c, n, kx, P0, n, X, ldx));
-  GEVP_TRY(trsm_left_lower_c(c, n, kx, L, n, Dinv, n, X, ldx));
+  GEVP_TRY(trsm_left_lower_c(c, n, kx, L, n, Dinv, n, X, ldx, 1));
   GEVP_TRY(launch_phase_normalize(c, n, kx, X, ldx));
   GEVP_TRY(launch_copy_real(c, kx, theta, lambda));
   double hn[2] = {0.0, 0.0};
