@@ -1,8 +1,8 @@
 // Cholesky factorisation and triangular solves, FP64 complex.
 //
-// The factorisation is right-looking and blocked by 64 with one block of
-// lookahead on a second stream (see chol_lower); each 64 x 64 diagonal block
-// is factored and inverted by one work-group in LDS.  The triangular solves
+// The factorisation is right-looking in panels of 384 columns with one panel
+// of lookahead on a second stream (see chol_lower); each 64 x 64 diagonal
+// block is factored and inverted by one work-group in LDS.  The triangular solves
 // recurse: every level splits the triangle in two halves (rounded to the
 // 64-wide block), so the off-diagonal work is one large GEMM on the FP64
 // matrix cores per level, and the base case applies a diagonal block's
@@ -335,17 +335,51 @@ gevp_status potrf_leaf(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
 }
 }  // namespace
 
-// Right-looking blocked Cholesky with one block of lookahead.  Block column
-// k (64 wide) is factored on the panel stream: the diagonal block in LDS
-// (k_potrf_block, which also writes its inverse to Dinv) and the rows below
-// by an in-place product with that inverse, L21 = A21 L11^{-H}.  The main
-// stream then applies panel k to the trailing matrix: first to block column
-// k+1 alone, after which the panel stream may factor it, then to the rest of
-// the lower triangle, which overlaps that factorisation.  The critical path
-// is about sum_k max(trailing update k, factor k+1) instead of a chain of
-// every small solve of a recursive factorisation.
+namespace {
+// out (k x m) = in^H, in (m x k): 32 x 32 tiles through LDS, both sides coalesced
+__global__ __launch_bounds__(256) void k_copy_ct(const zd* in, int64_t ldin, zd* out, int64_t ldout,
+                                                 int64_t m, int64_t k) {
+  __shared__ zd t[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;  // tile of `in`: rows bi, columns bj
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+    if (i < m && j < k) t[r][tx] = in[i + j * ldin];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {  // out(j, i) = conj(in(i, j)): j = bj*32 + tx, i = bi*32 + r
+    const int64_t j = bj * 32 + tx, i = bi * 32 + r;
+    if (i < m && j < k) {
+      const zd v = t[tx][r];
+      out[j + i * ldout] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
+gevp_status copy_ct(gevp_ctx* c, int64_t m, int64_t k, const zd* in, int64_t ldin, zd* out,
+                    int64_t ldout) {
+  if (m <= 0 || k <= 0) return GEVP_OK;
+  hipLaunchKernelGGL(k_copy_ct, dim3((unsigned)((m + 31) / 32), (unsigned)((k + 31) / 32)),
+                     dim3(256), 0, c->stream, in, ldin, out, ldout, m, k);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+}  // namespace
+
+// Right-looking blocked Cholesky in 384-wide panels with one panel of
+// lookahead.  A panel is factored on the panel stream, 64 columns at a time:
+// the diagonal block in LDS (k_potrf_block, which also writes its inverse to
+// Dinv), the rows below by an in-place product with that inverse,
+// L21 = A21 L11^{-H}, and the panel's remaining columns by a rank-64 update.
+// The panel's conjugate transpose is then copied into the upper block row
+// (space the factor does not use until it is zeroed at the end), so the
+// rank-384 trailing updates multiply both operands as stored.  The main
+// stream applies the panel first to the next panel's columns, after which
+// the panel stream may factor that panel, then to the rest of the lower
+// triangle, which overlaps the factorisation.
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
                        int* info_dev, hipEvent_t midpoint) {
+  constexpr int64_t PW = 6 * NB;  // measured at n = 8192: 30 ms; 128: 31, 256: 32, 512: 33
   if (n <= 0) {
     if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
     return GEVP_OK;
@@ -355,6 +389,7 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
     if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
   } else {
     const int64_t half = ((n + NB - 1) / NB / 2) * NB;  // first row of the second half
+    bool mid_done = false;
     gevp_ctx* pc = c;  // without inner streams the panels run in order on c's stream
     if (c->inner_streams) GEVP_TRY(panel_ctx(c, &pc));
     const bool two = pc != c;
@@ -364,38 +399,53 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
       GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
       GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
     }
-    for (int64_t r0 = 0; r0 < n; r0 += NB) {
-      const int64_t kb = std::min<int64_t>(NB, n - r0), rest = n - r0 - kb;
-      zd* Mkk = M + r0 + r0 * ldm;
-      GEVP_TRY(potrf_leaf(pc, kb, Mkk, ldm, Dinv + r0, ldi, info_dev, r0));
-      if (rest > 0) {
+    for (int64_t p0 = 0; p0 < n; p0 += PW) {
+      const int64_t pw = std::min<int64_t>(PW, n - p0), pend = p0 + pw;
+      // factor the panel (columns p0 .. pend-1, all rows below p0)
+      for (int64_t r0 = p0; r0 < pend; r0 += NB) {
+        const int64_t kb = std::min<int64_t>(NB, pend - r0), rest = n - r0 - kb;
+        zd* Mkk = M + r0 + r0 * ldm;
+        GEVP_TRY(potrf_leaf(pc, kb, Mkk, ldm, Dinv + r0, ldi, info_dev, r0));
+        if (rest <= 0) continue;
         zd* L21 = Mkk + kb;
         GEVP_TRY(launch_zgemm(pc, 0, 1, rest, kb, kb, 1.0, L21, ldm, Dinv + r0, ldi, 0.0, nullptr, 0,
                               0.0, nullptr, 0, nullptr, L21, ldm));
+        const int64_t w = pend - r0 - kb;  // panel columns right of this block
+        if (w > 0) {
+          zd* A2 = M + (r0 + kb) + (r0 + kb) * ldm;
+          GEVP_TRY(launch_zgemm(pc, 0, 1, rest, w, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
+                                nullptr, 0, nullptr, A2, ldm));
+        }
       }
+      const int64_t rest = n - pend;
+      const zd* Lp = M + pend + p0 * ldm;  // rest x pw, below the panel's diagonal block
+      zd* LpH = M + p0 + pend * ldm;       // pw x rest, the upper block row
+      if (rest > 0) GEVP_TRY(copy_ct(pc, rest, pw, Lp, ldm, LpH, ldm));
       if (two) {
         GEVP_HIP_TRY(hipEventRecord(evp, pc->stream));
         GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evp, 0));
       }
       if (rest > 0) {
-        const int64_t kb1 = std::min<int64_t>(NB, rest);
-        const zd* L21 = Mkk + kb;
-        zd* A2 = M + (r0 + kb) + (r0 + kb) * ldm;
-        // block column k+1: A2(:, :kb1) -= L21 L21(:kb1, :)^H
-        GEVP_TRY(launch_zgemm(c, 0, 1, rest, kb1, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
+        const int64_t pw1 = std::min<int64_t>(PW, rest);
+        zd* A2 = M + pend + pend * ldm;
+        // next panel's columns: A2(:, :pw1) -= Lp LpH(:, :pw1)
+        GEVP_TRY(launch_zgemm(c, 0, 0, rest, pw1, pw, -1.0, Lp, ldm, LpH, ldm, 1.0, A2, ldm, 0.0,
                               nullptr, 0, nullptr, A2, ldm));
         if (two) {
           GEVP_HIP_TRY(hipEventRecord(evn, c->stream));
           GEVP_HIP_TRY(hipStreamWaitEvent(pc->stream, evn, 0));
         }
-        const int64_t rest2 = rest - kb1;
+        const int64_t rest2 = rest - pw1;
         if (rest2 > 0) {  // the rest of the trailing lower triangle
-          zd* A3 = A2 + kb1 + kb1 * ldm;
-          GEVP_TRY(launch_zgemm(c, 0, 1, rest2, rest2, kb, -1.0, L21 + kb1, ldm, L21 + kb1, ldm, 1.0,
-                                A3, ldm, 0.0, nullptr, 0, nullptr, A3, ldm, nullptr, 1));
+          zd* A3 = A2 + pw1 + pw1 * ldm;
+          GEVP_TRY(launch_zgemm(c, 0, 0, rest2, rest2, pw, -1.0, Lp + pw1, ldm, LpH + pw1 * ldm,
+                                ldm, 1.0, A3, ldm, 0.0, nullptr, 0, nullptr, A3, ldm, nullptr, 1));
         }
       }
-      if (midpoint && r0 + NB == half) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
+      if (midpoint && !mid_done && pend >= half) {
+        GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
+        mid_done = true;
+      }
     }
   }
   if (n > 1) {
