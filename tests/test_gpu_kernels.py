@@ -64,7 +64,8 @@ def test_zgemm_plain_and_inplace_beta(h):
     assert np.allclose(_np(Dd), C - A @ B, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333, 1000])
+# panel boundaries of the factorisation (384-wide panels of 64-wide blocks)
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333, 383, 384, 385, 769, 1000])
 def test_potrf(h, n):
     print(f"potrf n={n}", flush=True)
     rng = np.random.default_rng(n)
@@ -77,12 +78,12 @@ def test_potrf(h, n):
     assert np.max(np.abs(_np(L) - Lr)) <= 1e-12 * np.max(np.abs(Lr))
 
 
-def test_potrf_not_hpd_reports_pivot(h):
-    n = 150
+@pytest.mark.parametrize("n,bad", [(150, 97), (900, 700)])
+def test_potrf_not_hpd_reports_pivot(h, n, bad):
     M = np.eye(n, dtype=complex)
-    M[97, 97] = -2.0
+    M[bad, bad] = -2.0
     _, piv = h.potrf(_dev(M))
-    assert piv == 98
+    assert piv == bad + 1
 
 
 @pytest.mark.parametrize("side,trans", [("L", "N"), ("L", "C"), ("R", "C")])
