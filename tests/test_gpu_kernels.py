@@ -103,7 +103,7 @@ def test_trsm(h, side, trans, n, m):
     assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 130, 301])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 127, 128, 129, 130, 193, 301, 948])
 def test_heev_vs_oracle(h, n, oracle_mod):
     print(f"heev n={n}", flush=True)
     rng = np.random.default_rng(n)
@@ -119,12 +119,12 @@ def test_heev_vs_oracle(h, n, oracle_mod):
     assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10
 
 
-def test_heev_degenerate(h, oracle_mod):
+@pytest.mark.parametrize("n", [40, 300])
+def test_heev_degenerate(h, oracle_mod, n):
     # repeated eigenvalues: an invariant subspace, not unique vectors
-    n = 40
     rng = np.random.default_rng(1)
     Q, _ = np.linalg.qr(_cn(rng, n, n))
-    ev = np.repeat(np.arange(8, dtype=float), 5)
+    ev = np.repeat(np.arange(n // 5, dtype=float), 5)
     H = (Q * ev) @ Q.conj().T
     H = 0.5 * (H + H.conj().T)
     th, Z = h.heev(_dev(H))
