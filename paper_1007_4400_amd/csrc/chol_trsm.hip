@@ -97,16 +97,21 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
   zd* S = reinterpret_cast<zd*>(potrf_lds);  // L, S[c * SLD + r]
   zd* X = S + NB * SLD;                      // inv(L), same layout
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & (NB - 1), c = e >> 6;
-    zd v = make_double2(0.0, 0.0);
-    if (r < n && c < n) {
-      if (r >= c) v = M[r + (int64_t)c * ldm];
-    } else if (r == c) {
-      v = make_double2(1.0, 0.0);
+  {
+    // all sixteen loads in flight before the first LDS store
+    zd v[NB * NB / 256];
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + 256 * q, r = e & (NB - 1), c = e >> 6;
+      v[q] = make_double2((r == c && (r >= n || c >= n)) ? 1.0 : 0.0, 0.0);
+      if (r < n && c < n && r >= c) v[q] = M[r + (int64_t)c * ldm];
     }
-    S[c * SLD + r] = v;
-    X[c * SLD + r] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < NB * NB / 256; ++q) {
+      const int e = tid + 256 * q, r = e & (NB - 1), c = e >> 6;
+      S[c * SLD + r] = v[q];
+      X[c * SLD + r] = make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   for (int p0 = 0; p0 < NB; p0 += PB) {

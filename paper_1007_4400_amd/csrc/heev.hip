@@ -318,7 +318,7 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
   // registers; the loads it needs do not depend on the recurrence and are
   // issued IB steps at a time, so a pass costs n / IB memory latencies.
   auto at = [&](double* A, int k) -> double& { return A[(int64_t)k * n + j]; };
-  constexpr int IB = 16;
+  constexpr int IB = 32;
   // LU with partial pivoting of T - lam I; working row k: (al, be) on columns (k, k+1)
   double al = d[0] - lam, be = (n > 1) ? e[0] : 0.0;
   for (int k = 0; k < n - 1; ++k) {
@@ -350,10 +350,14 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
     const uint64_t r = hmix(((uint64_t)j << 32) ^ (uint64_t)i ^ 0x5DEECE66Dull);
     at(Zt, i) = ((double)(r >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
   }
-  double nrm = 0.0;
+  // Two sweeps of inverse iteration.  The growth of the first sweep is removed
+  // by a power-of-two factor folded into the second sweep's loads (exact, no
+  // extra pass); the second sweep's backward pass also accumulates the sum of
+  // squares, so one final pass normalises.
+  double sc = 1.0, ssq = 0.0, mx = 0.0;
   for (int it = 0; it < 2; ++it) {
     // forward: apply the row swaps and multipliers; c is the current y_k
-    double c = at(Zt, 0);
+    double c = at(Zt, 0) * sc;
     for (int k0 = 0; k0 < n - 1; k0 += IB) {
       double lv[IB], sv[IB], av[IB];
 #pragma unroll
@@ -369,19 +373,22 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
       for (int q = 0; q < IB; ++q) {
         const int k = k0 + q;
         if (k < n - 1) {
+          const double a = av[q] * sc;
           if (sv[q] != 0.0) {  // rows k, k+1 swapped
-            at(Zt, k) = av[q];
-            c = c - lv[q] * av[q];
+            at(Zt, k) = a;
+            c = c - lv[q] * a;
           } else {
             at(Zt, k) = c;
-            c = av[q] - lv[q] * c;
+            c = a - lv[q] * c;
           }
         }
       }
     }
     at(Zt, n - 1) = c;
     // backward: U x = y with U upper triangular, bandwidth 3
-    double x1 = 0.0, x2 = 0.0, mx = 0.0;
+    double x1 = 0.0, x2 = 0.0;
+    mx = 0.0;
+    ssq = 0.0;
     for (int k0 = n - 1; k0 >= 0; k0 -= IB) {
       double yv[IB], vv[IB], wv[IB], uv[IB];
 #pragma unroll
@@ -406,11 +413,21 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
           x2 = x1;
           x1 = x;
           mx = fmax(mx, fabs(x));
+          ssq += x * x;
         }
       }
     }
-    const double sc = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
-    nrm = 0.0;
+    int ex = 0;
+    (void)frexp(mx, &ex);
+    sc = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ex) : 1.0;
+  }
+  // normalise: from the sum of squares when it is finite, else after scaling
+  // by the power of two (a second pass, only for extreme growth)
+  double inv;
+  if (ssq > 0.0 && isfinite(ssq)) {
+    inv = 1.0 / sqrt(ssq);
+  } else {
+    double nrm = 0.0;
     for (int k0 = 0; k0 < n; k0 += IB) {
       double zv[IB];
 #pragma unroll
@@ -418,14 +435,10 @@ __global__ __launch_bounds__(64) void k_tri_invit(const double* dg, const double
         if (k0 + q < n) zv[q] = at(Zt, k0 + q);
 #pragma unroll
       for (int q = 0; q < IB; ++q)
-        if (k0 + q < n) {
-          const double v = zv[q] * sc;
-          at(Zt, k0 + q) = v;
-          nrm += v * v;
-        }
+        if (k0 + q < n) nrm += (zv[q] * sc) * (zv[q] * sc);
     }
+    inv = (nrm > 0.0 && isfinite(nrm)) ? sc / sqrt(nrm) : 0.0;
   }
-  const double inv = (nrm > 0.0) ? 1.0 / sqrt(nrm) : 0.0;
   for (int k0 = 0; k0 < n; k0 += IB) {
     double zv[IB];
 #pragma unroll
