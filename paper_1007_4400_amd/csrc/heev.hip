@@ -501,12 +501,17 @@ __global__ __launch_bounds__(256) void k_zt_to_complex(const double* Zt, int n, 
 
 // Z <- G_0 G_1 ... G_{n-2} Z, reflectors applied last to first.  Each
 // work-group owns `cols` columns of Z (one per wave) held in LDS for the whole
-// sweep and stages each reflector through LDS, so Z never leaves the CU.
+// sweep, so Z never leaves the CU.  Reflectors go through two LDS slots: the
+// next one is loaded into registers while the current one is applied, then
+// stored into the other slot, so each step has one barrier and no exposed
+// global load.
+constexpr int RQ = 8;  // rows per thread of a staged reflector: n <= RQ * 256
 __global__ __launch_bounds__(256) void k_apply_reflectors(int n, int cols, zd* Z, int64_t ldz,
                                                           const zd* V, int64_t ldv, const zd* tau) {
   extern __shared__ zd sm2[];
-  zd* sv = sm2;          // n
-  zd* sz = sm2 + n;      // cols x n
+  zd* sv0 = sm2;          // n
+  zd* sv1 = sm2 + n;      // n
+  zd* sz = sm2 + 2 * n;   // cols x n
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = blockIdx.x * cols;
   for (int q = 0; q < cols; ++q) {
@@ -514,18 +519,26 @@ __global__ __launch_bounds__(256) void k_apply_reflectors(int n, int cols, zd* Z
     for (int i = tid; i < n; i += 256)
       sz[q * n + i] = (col < n) ? Z[i + (int64_t)col * ldz] : make_double2(0.0, 0.0);
   }
+  for (int i = n - 1 + tid; i < n; i += 256) sv0[i] = V[i + (int64_t)(n - 2) * ldv];
+  __syncthreads();
   const bool active = wave < cols && (c0 + wave) < n;
   zd* z = sz + wave * n;
+  zd t = tau[n - 2];
   for (int s = n - 2; s >= 0; --s) {
-    const zd t = tau[s];
-    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
-    __syncthreads();
-    for (int i = s + 1 + tid; i < n; i += 256) sv[i] = V[i + (int64_t)s * ldv];
-    __syncthreads();
-    if (active) {
+    zd* cur = ((n - 2 - s) & 1) ? sv1 : sv0;
+    zd* nxt = ((n - 2 - s) & 1) ? sv0 : sv1;
+    // the next reflector (s - 1) covers rows s .. n-1
+    zd r[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = s + tid + 256 * q;
+      r[q] = (s >= 1 && i < n) ? V[i + (int64_t)(s - 1) * ldv] : make_double2(0.0, 0.0);
+    }
+    const zd tn = (s >= 1) ? tau[s - 1] : make_double2(0.0, 0.0);
+    if (active && !(t.x == 0.0 && t.y == 0.0)) {
       double sr = 0.0, si = 0.0;
       for (int i = s + 1 + lane; i < n; i += 64) {
-        const zd v = sv[i], x = z[i];  // conj(v) x
+        const zd v = cur[i], x = z[i];  // conj(v) x
         sr += v.x * x.x + v.y * x.y;
         si += v.x * x.y - v.y * x.x;
       }
@@ -533,13 +546,20 @@ __global__ __launch_bounds__(256) void k_apply_reflectors(int n, int cols, zd* Z
       si = wsum(si);
       const zd f = cmul(t, make_double2(sr, si));
       for (int i = s + 1 + lane; i < n; i += 64) {
-        const zd fv = cmul(f, sv[i]);
+        const zd fv = cmul(f, cur[i]);
         z[i].x -= fv.x;
         z[i].y -= fv.y;
       }
     }
+    // the other slot was last read in the previous step, before its barrier
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+      const int i = s + tid + 256 * q;
+      if (s >= 1 && i < n) nxt[i] = r[q];
+    }
+    t = tn;
+    __syncthreads();
   }
-  __syncthreads();
   for (int q = 0; q < cols; ++q) {
     const int col = c0 + q;
     if (col >= n) break;
@@ -558,6 +578,8 @@ __global__ void k_tri_norm(const double* d, const double* e, int n, double* out)
 
 // work-groups of a tridiagonalisation step: one wave per trailing column
 // while n - 1 <= 4 G, at most one work-group per compute unit
+constexpr int64_t APPLY_LDS = 131072;  // LDS budget of the reflector sweep (bytes)
+
 inline int trd_groups(int64_t n) { return (int)(n - 1 < 256 ? (n > 1 ? n - 1 : 1) : 256); }
 
 size_t heev_work_bytes(int64_t n) {
@@ -610,6 +632,8 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   static const bool attr = [&]() {
     (void)hipFuncSetAttribute((const void*)k_hetrd_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(3 * sizeof(zd) * 2048));
+    (void)hipFuncSetAttribute((const void*)k_apply_reflectors,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)APPLY_LDS);
     return true;
   }();
   (void)attr;
@@ -643,12 +667,13 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
   GEVP_HIP_TRY(hipGetLastError());
   if (n > 1) {
-    // columns per work-group so that v_s plus the columns fit 64 KB of LDS
-    int cols = (int)((65536 - (int64_t)shv) / (int64_t)shv);
+    // columns per work-group so that two reflector slots plus the columns fit
+    // APPLY_LDS bytes
+    int cols = (int)((APPLY_LDS - 2 * (int64_t)shv) / (int64_t)shv);
     if (cols > 4) cols = 4;
     if (cols < 1) return GEVP_ERR_INVALID;  // n > 2048 is not supported here
     hipLaunchKernelGGL(k_apply_reflectors, dim3((n + cols - 1) / cols), dim3(256),
-                       shv * (1 + cols), c->stream, n, cols, Z, ldz, a.V, a.ldv, a.tau);
+                       shv * (2 + cols), c->stream, n, cols, Z, ldz, a.V, a.ldv, a.tau);
     GEVP_HIP_TRY(hipGetLastError());
   }
   return GEVP_OK;
