@@ -408,17 +408,17 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
       const int64_t pw = std::min<int64_t>(PW, n - p0), pend = p0 + pw;
       // factor the panel (columns p0 .. pend-1, all rows below p0)
       for (int64_t r0 = p0; r0 < pend; r0 += NB) {
-        const int64_t kb = std::min<int64_t>(NB, pend - r0), rest = n - r0 - kb;
+        const int64_t kb = std::min<int64_t>(NB, pend - r0), below = n - r0 - kb;
         zd* Mkk = M + r0 + r0 * ldm;
         GEVP_TRY(potrf_leaf(pc, kb, Mkk, ldm, Dinv + r0, ldi, info_dev, r0));
-        if (rest <= 0) continue;
+        if (below <= 0) continue;
         zd* L21 = Mkk + kb;
-        GEVP_TRY(launch_zgemm(pc, 0, 1, rest, kb, kb, 1.0, L21, ldm, Dinv + r0, ldi, 0.0, nullptr, 0,
-                              0.0, nullptr, 0, nullptr, L21, ldm));
+        GEVP_TRY(launch_zgemm(pc, 0, 1, below, kb, kb, 1.0, L21, ldm, Dinv + r0, ldi, 0.0, nullptr,
+                              0, 0.0, nullptr, 0, nullptr, L21, ldm));
         const int64_t w = pend - r0 - kb;  // panel columns right of this block
         if (w > 0) {
           zd* A2 = M + (r0 + kb) + (r0 + kb) * ldm;
-          GEVP_TRY(launch_zgemm(pc, 0, 1, rest, w, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
+          GEVP_TRY(launch_zgemm(pc, 0, 1, below, w, kb, -1.0, L21, ldm, L21, ldm, 1.0, A2, ldm, 0.0,
                                 nullptr, 0, nullptr, A2, ldm));
         }
       }
