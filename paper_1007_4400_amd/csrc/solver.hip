@@ -163,13 +163,17 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
     GEVP_TRY(launch_colnorm_scale(c, n, m, P, ldp));
     GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
                           nullptr, w.G, m));
-    if (pass == 0 && try_skip) {
+    // An orthonormal seed needs no pass at all, and a first pass that already
+    // left the block orthonormal to 5e-13 needs no second one: the Gram
+    // matrix is formed either way, and the check replaces the host read of
+    // the Cholesky's status.
+    if ((pass == 0 && try_skip) || pass == 1) {
       double dev = 1.0;
       GEVP_TRY(launch_max_offident(c, m, w.G, m, w.shift + 1));
       GEVP_HIP_TRY(hipMemcpyAsync(&dev, w.shift + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
       if (dev <= 5e-13) {
-        if (skipped) *skipped = true;
+        if (skipped && pass == 0) *skipped = true;
         return GEVP_OK;
       }
     }

@@ -352,15 +352,18 @@ __global__ void k_copy_real(int64_t n, const double* s, double* d) {
 }
 
 // out[0] = max_ij |M(i,j) - delta_ij| (one work-group)
+// max |M - I| over all entries; a non-finite entry gives +inf (fmax alone
+// would drop a NaN), so a block with NaN never passes a tolerance test
 __global__ __launch_bounds__(1024) void k_max_offident(int64_t n, const zd* M, int64_t ldm, double* out) {
   __shared__ double sh[1024];
   double mx = 0.0;
-  for (int64_t e = threadIdx.x; e < n * n; e += 1024) {
-    const int64_t i = e % n, j = e / n;
-    zd v = M[i + j * ldm];
-    if (i == j) v.x -= 1.0;
-    mx = fmax(mx, hypot(v.x, v.y));
-  }
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+      zd v = M[i + j * ldm];
+      if (i == j) v.x -= 1.0;
+      const double h = hypot(v.x, v.y);
+      mx = (h != h) ? INFINITY : fmax(mx, h);
+    }
   sh[threadIdx.x] = mx;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
