@@ -179,7 +179,10 @@ int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev);
  *            optional seed block (device complex128 n x k0, k0 <= block), the
  *            previous SCF iteration's eigenvectors in the original basis;
  *            X0 = NULL or k0 = 0 is a cold start.  Columns beyond k0 are
- *            filled from a counter-based random generator (opts->seed).
+ *            filled from a counter-based random generator (opts->seed); an
+ *            all-zero seed column is replaced by a fixed pseudo-random one,
+ *            and linearly dependent ones are handled by the orthonormalisation
+ *            (shifted CholQR when needed).
  *   nev      wanted pairs, 1 <= nev <= n
  *   tol      convergence: ||A x_i - lambda_i B x_i||_2 <= tol ||A||_2 for
  *            every i < nev (tol > 0; 1e-10 is typical)

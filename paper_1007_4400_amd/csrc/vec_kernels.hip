@@ -131,13 +131,28 @@ __global__ void k_randn(int64_t rows, zd* V, int64_t ldv, int64_t col_offset, ui
   }
 }
 
-// one work-group per column: v <- v / ||v||  (zero columns left as they are)
+// one work-group per column: v <- v / ||v|| (an all-zero column becomes a unit
+// pseudo-random one)
 __global__ __launch_bounds__(256) void k_colnorm_scale(int64_t rows, zd* V, int64_t ldv) {
   __shared__ double sh[4];
   zd* v = V + blockIdx.x * ldv;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < rows; i += 256) s += v[i].x * v[i].x + v[i].y * v[i].y;
   s = block_sum256(s, sh);
+  if (s == 0.0) {
+    // an all-zero column can never be orthonormalised (the shifted Cholesky
+    // keeps it zero): replace it by a fixed pseudo-random direction, as a
+    // missing seed vector is replaced in subspace iteration
+    const uint64_t key = mix64(0x5EEDC01Dull ^ mix64((uint64_t)blockIdx.x * 0x100000001B3ull));
+    for (int64_t i = threadIdx.x; i < rows; i += 256) {
+      const uint64_t r1 = mix64(key ^ (uint64_t)i), r2 = mix64(key ^ (uint64_t)i ^ 0xD1B54A32D192ED03ull);
+      const zd z = make_double2((r1 >> 11) * (1.0 / 9007199254740992.0) - 0.5,
+                                (r2 >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+      v[i] = z;
+      s += z.x * z.x + z.y * z.y;
+    }
+    s = block_sum256(s, sh);
+  }
   if (s > 0.0) {
     const double inv = 1.0 / sqrt(s);
     for (int64_t i = threadIdx.x; i < rows; i += 256) v[i] = make_double2(v[i].x * inv, v[i].y * inv);

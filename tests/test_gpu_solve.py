@@ -245,3 +245,46 @@ def test_edge_sizes(h, oracle_mod, n, nev, precision):
     _check(oracle_mod, A, B, lam, X, nev)
     lam2, X2, _, info2 = h.solve(_dev(A), _dev(B), nev, X0=X, tol=TOL, kx=kx, opts=o)
     _check(oracle_mod, A, B, lam2, X2, nev)
+
+
+def test_degenerate_seed(h, oracle_mod):
+    """A seed block with a zero column and a repeated column: the zero column
+    is replaced by a pseudo-random direction (a zero column stays zero under
+    any Cholesky-based orthonormalisation), the repeated one is handled by
+    CholQR or its shifted fallback, and the solve still meets the parity bar
+    (it used to end without convergence after eight fallbacks)."""
+    print("degenerate seed", flush=True)
+    wl = synth.scaled(synth.MEDIUM, 300)
+    seq = list(synth.sequence(wl, 4, steps=2))
+    kx = h.block_size(wl.n, wl.nev)
+    _, X0, _, _ = h.solve(_dev(seq[0][0]), _dev(seq[0][1]), wl.nev, tol=TOL, kx=kx)
+    X0 = X0.clone()
+    X0[:, 3] = 0
+    X0[:, 7] = X0[:, 6]
+    A1, B = seq[1]
+    lam, X, _, info = h.solve(_dev(A1), _dev(B), wl.nev, X0=X0, tol=TOL, kx=kx)
+    print("qr fallbacks", info["qr_fallbacks"], "outer", info["outer_iters"], flush=True)
+    _check(oracle_mod, A1, B, lam, X, wl.nev)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 2.5])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_degenerate_spectrum(h, oracle_mod, sigma, precision):
+    """A = sigma B: every eigenvalue equals sigma, the filter's damped
+    interval has zero width and any B-orthonormal block is an answer.  Only
+    what is unique is compared: the eigenvalues, the residuals and the
+    B-orthonormality of the returned block."""
+    from paper_1007_4400_amd import gevp
+
+    print(f"degenerate spectrum sigma={sigma} {precision}", flush=True)
+    n, nev = 100, 10
+    _, B = _rand_pencil(n, 77)
+    A = sigma * B
+    o = gevp.make_opts(precision=precision)
+    lam, X, _, info = h.solve(_dev(A), _dev(B), nev, tol=TOL, opts=o)
+    lam = lam.cpu().numpy()[:nev]
+    Xn = X.cpu().numpy()[:, :nev]
+    assert np.max(np.abs(lam - sigma)) <= TOL * max(abs(sigma), 1.0)
+    res, orth = oracle_mod.residuals(A, B, lam, Xn)
+    assert res.max() <= TOL * max(np.linalg.norm(A, 2), 1.0)
+    assert orth <= 1e-9
