@@ -15,6 +15,9 @@ Functions and the parts of the paper they follow:
                           the "full data" direct iteration of section 2).
 * ``residuals``        -- ||A x_i - lambda_i B x_i||_2 and max |X^H B X - I|.
 * ``pair_residual``    -- the same for one pair, O(n^2): for sampled checks.
+* ``norm2_lower``      -- a lower bound of ||A||_2 by power iteration (for
+                          residual checks that must not borrow the solver's
+                          own norm estimate).
 * ``inertia``          -- number of eigenvalues below sigma (Sylvester).
 * ``bisect``           -- k-th eigenvalue by bisection on inertia counts.
 * ``inverse_iteration``-- eigenvector at a given eigenvalue estimate.
@@ -28,7 +31,7 @@ Functions and the parts of the paper they follow:
 * ``threshold_update`` -- partial update of a Hermitian matrix between two
                           SCF steps: only entries whose change exceeds a
                           fraction p_t of the largest change are taken over
-                          (section 3, paragraph "Matrix generation"); plain
+                          (section 2, paragraph "Matrix generation"); plain
                           numpy, FP64.
 * ``masked_update``    -- the same update driven by a given entry mask.
 * ``contour_points``, ``contour_filter``, ``lu_nopivot``, ``contour_solve``
@@ -152,6 +155,32 @@ def pair_residual(A, B, lam_i, x):
     return float(r[0]), float(q[0])
 
 
+def norm2_lower(A, iters=40, seed=0):
+    """Lower bound of the spectral norm of the Hermitian matrix whose lower
+    triangle is A's (the diagonal's real part is used).  Power iteration:
+    for any v != 0, ||A v|| / ||v|| <= ||A||_2, and the largest quotient seen
+    over ``iters`` steps is returned; it converges to ||A||_2 at the rate
+    (|lambda_2| / |lambda_1|)^(2k) for a dominant eigenvalue of multiplicity
+    one.  Memory: one lower-triangular copy of A."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    Lo = np.tril(A, -1)
+    dg = np.real(np.diagonal(A)).copy()
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    best = 0.0
+    for _ in range(int(iters)):
+        # (L + D + L^H) v with L the strict lower triangle
+        w = Lo @ v + dg * v + np.conj(Lo.T @ np.conj(v))
+        nw = float(np.linalg.norm(w))
+        best = max(best, nw)
+        if nw == 0.0:
+            break
+        v = w / nw
+    return best
+
+
 def inertia(A, B, sigma):
     lib = _load()
     A = _colmajor(A)
@@ -231,17 +260,26 @@ def seed_monitor_from_overlap(M):
 
 def seed_monitor(X0, X, B, k):
     """seed_monitor_from_overlap of M = X0[:, :k]^H B X[:, :k]; returns
-    (sin_rms, dev_mean, dev_max, reindexed, dev) for the first k columns."""
+    (sin_rms, dev_mean, dev_max, reindexed, dev) for the first k columns.
+
+    Here sin_rms comes from the projection residual instead of k - ||M||_F^2,
+    which cancels to rounding noise once the angles fall below about 1e-8:
+    with X B-orthonormal, R = X0 - X (X^H B X0) = X0 - X M^H is the part of
+    X0 B-orthogonal to span(X), and sum of sin^2 of the principal angles is
+    trace(R^H B R) (both blocks B-orthonormal with k columns)."""
     X0 = np.asarray(X0, dtype=np.complex128)[:, :k]
     X = np.asarray(X, dtype=np.complex128)[:, :k]
     B = np.asarray(B, dtype=np.complex128)
     M = X0.conj().T @ (B @ X)
     r = seed_monitor_from_overlap(M)
-    return r[0], r[1], r[2], r[3], r[5]
+    R = X0 - X @ M.conj().T
+    s2 = float(np.real(np.sum(R.conj() * (B @ R))))
+    sin_rms = float(np.sqrt(max(0.0, s2) / k))
+    return sin_rms, r[1], r[2], r[3], r[5]
 
 
 def threshold_update(A_cur, A_new, p_t):
-    """Thresholded partial update (section 3, paragraph "Matrix generation").
+    """Thresholded partial update (section 2, paragraph "Matrix generation").
 
     The paper measures the change between the Hamiltonians of two adjacent
     SCF iterations by the largest entry variation delta = max |A_new - A_cur|
@@ -285,7 +323,7 @@ def threshold_update(A_cur, A_new, p_t):
 def masked_update(A_cur, A_src, mask):
     """Apply a precomputed entry mask: masked lower-triangle entries take
     A_src's value, everything else keeps A_cur's (the fast iterations of
-    section 3, paragraph "Matrix generation", where only part of the entries
+    section 2, paragraph "Matrix generation", where only part of the entries
     have been regenerated)."""
     A_cur = np.asarray(A_cur, dtype=np.complex128)
     n = A_cur.shape[0]

@@ -299,13 +299,26 @@ def test_seed_monitor_constructed_angles(oracle_mod):
     assert r2 == 5 and np.max(np.abs(d2 - dev[perm])) < 1e-12
 
 
+def test_seed_monitor_resolves_tiny_angles(oracle_mod):
+    """Angles of 1e-9 .. 1e-6 (a settled SCF run): sin_rms is their RMS to
+    six digits, far below where k - ||M||_F^2 leaves only rounding noise."""
+    rng = np.random.default_rng(13)
+    n, k = 60, 6
+    B, X0, Y = _b_orthonormal_pair(rng, n, k)
+    t = np.array([1e-9, 3e-9, 1e-8, 5e-8, 2e-7, 1e-6])
+    X = X0 * np.cos(t) + Y * np.sin(t)
+    sin_rms = oracle_mod.seed_monitor(X0, X, B, k)[0]
+    want = np.sqrt(np.mean(np.sin(t) ** 2))
+    assert abs(sin_rms - want) <= 1e-6 * want
+
+
 def test_seed_monitor_identity_and_orthogonal(oracle_mod):
     """Same block: every angle 0; a B-orthogonal block: sin_rms 1 and every
     deviation angle pi/2 (normalised to 1)."""
     rng = np.random.default_rng(12)
     B, X0, Y = _b_orthonormal_pair(rng, 30, 5)
     s, m, x, r, _ = oracle_mod.seed_monitor(X0, X0 * np.exp(0.3j), B, 5)
-    assert s < 1e-7 and x < 1e-6 and r == 0
+    assert s < 1e-14 and x < 1e-6 and r == 0
     s, m, x, r, _ = oracle_mod.seed_monitor(X0, Y, B, 5)
     assert abs(s - 1.0) < 1e-12 and abs(m - 1.0) < 1e-6 and abs(x - 1.0) < 1e-6
 
@@ -357,3 +370,19 @@ def test_seed_monitor_std_of_constructed_angles(oracle_mod):
     M = X0.conj().T @ B @ X
     r = oracle_mod.seed_monitor_from_overlap(M)
     assert abs(r[4] - np.std(t / (np.pi / 2))) < 1e-7
+
+
+def test_stored_sequence_fixture_step0_is_the_constructed_spectrum():
+    """The n = 4096 fixture (oracle eigenvalues for every step of the
+    seeded sequence, written by tests/golden/make_oracle_sequence.py) starts
+    from the constructed pencil, whose lowest eigenvalues are known in closed
+    form: its step-0 values must be those, which also pins the input
+    generator to the same pencil the fixture was made from."""
+    path = os.path.join(HERE, "golden", "oracle_seq_n4096_nev410_steps4_seed0.json")
+    d = json.load(open(path))
+    wl = synth.scaled(synth.LARGE, d["n"], steps=d["steps"])
+    rng = np.random.Generator(np.random.PCG64(d["seed"]))
+    lam = np.sort(synth.spectrum(wl, rng))[: d["nev"]]
+    got = np.array(d["eigenvalues"][0])
+    assert np.max(np.abs(got - lam) / np.maximum(np.abs(lam), 1.0)) <= 1e-11
+    assert all(np.all(np.diff(np.array(e)) > 0) for e in d["eigenvalues"])
