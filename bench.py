@@ -22,6 +22,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -35,28 +36,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample=2048, n_target=8192):
-    """Oracle (plain FP64 CPU solver) on one pencil of the same construction at
-    n_sample, scaled by (n_target / n_sample)^3 to the target size."""
-    import numpy as np  # noqa: F401
-
+def cpu_baseline(n_target=8192, sizes=(2048, 4096)):
+    """The oracle (plain FP64 CPU solver, all host threads) on one pencil of
+    the same construction at each of `sizes`; the value is the largest
+    sample scaled by (n_target / n)^3, the solver's dense O(n^3) cost, with
+    the exponent measured between the two samples reported beside it."""
     from oracle import oracle
     from paper_1007_4400_amd import synth
 
-    wl = synth.scaled(synth.LARGE, n_sample)
-    p, _ = synth.make_pencil(wl, 0)
-    t0 = time.perf_counter()
-    oracle.solve(p.A, p.B, wl.nev)
-    t = time.perf_counter() - t0
+    times = {}
+    for n in sizes:
+        wl = synth.scaled(synth.LARGE, n)
+        p, _ = synth.make_pencil(wl, 0)
+        t0 = time.perf_counter()
+        oracle.solve(p.A, p.B, wl.nev)
+        times[n] = time.perf_counter() - t0
+        log(f"cpu baseline: oracle solve n={n} nev={wl.nev}: {times[n]:.1f} s")
+    n1, n2 = sizes[0], sizes[-1]
+    expo = math.log(times[n2] / times[n1]) / math.log(n2 / n1) if n2 != n1 else 3.0
+    scale = (n_target / n2) ** 3
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    scale = (n_target / n_sample) ** 3
     return {
-        "value": t * scale,
+        "value": times[n2] * scale,
         "unit": "s/step",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"one oracle solve at n={n_sample}, nev={wl.nev} of the same construction "
-                  f"({t:.2f} s), scaled by (n/{n_sample})^3 = {scale:.0f} to n={n_target}",
+        "sample": f"one oracle solve of a pencil of the same construction at n={n2}, "
+                  f"nev={round(0.1 * n2)} ({times[n2]:.1f} s) scaled by (n/{n2})^3 = {scale:.0f} "
+                  f"to n={n_target}; at n={n1} it took {times[n1]:.1f} s, a measured exponent of "
+                  f"{expo:.2f} between the two (with that exponent: "
+                  f"{times[n2] * (n_target / n2) ** expo:.0f} s)",
+        "samples_s": {str(k): v for k, v in times.items()},
+        "measured_exponent": expo,
     }
 
 
@@ -149,18 +160,31 @@ def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="time
         for name, cnt, tot, avg in rows[:30]:
             lines.append(f"{tot / 1e6:10.2f} {cnt:7d} {avg / 1e6:9.4f}  {name[:110]}")
     reg = _regions(cur)
-    sel = cur.execute("select start, end from kernels where name like ?",
-                      ("%" + kernel_substr + "%",)).fetchall()
     lines.append("")
-    if sel:
+    # kernel_substr may list several kernels separated by '|' (a family whose
+    # launches bench.py times together); the first ones are the launches, a
+    # trailing '+name' is a helper kernel counted in the time but not the launches
+    fam_total, fam_count = 0.0, 0
+    for alt in kernel_substr.split("|"):
+        helper = alt.startswith("+")
+        name = alt.lstrip("+")
+        sel = cur.execute("select start, end from kernels where name like ?",
+                          ("%" + name + "%",)).fetchall()
+        if not sel:
+            continue
         d = [e - s for s, e in sel]
-        lines.append(f"{kernel_substr}: all launches {len(d)}, avg {sum(d) / len(d) / 1e6:.4f} ms")
+        lines.append(f"{name}: all launches {len(d)}, avg {sum(d) / len(d) / 1e6:.4f} ms")
         if region in reg:
             w0, w1 = reg[region]
             dw = [e - s for s, e in sel if s >= w0 and e <= w1]
             if dw:
-                lines.append(f"{kernel_substr}: launches inside roctx range '{region}' {len(dw)}, "
+                lines.append(f"{name}: launches inside roctx range '{region}' {len(dw)}, "
                              f"avg {sum(dw) / len(dw) / 1e6:.4f} ms, total {sum(dw) / 1e6:.1f} ms")
+                fam_total += sum(dw)
+                fam_count += 0 if helper else len(dw)
+    if "|" in kernel_substr and fam_count:
+        lines.append(f"family inside '{region}': {fam_count} launches, total {fam_total / 1e6:.1f} ms, "
+                     f"avg per launch (helpers included) {fam_total / fam_count / 1e6:.4f} ms")
     # counters (pmc runs)
     try:
         pmc = cur.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
@@ -346,7 +370,7 @@ def _update_apply_bytes(mask_words, n, rechecked):
 
 
 def run_update(args):
-    """Thresholded partial matrix update (the paper's section 3, paragraph
+    """Thresholded partial matrix update (the paper's section 2, paragraph
     "Matrix generation"): a 12-step sequence of n = 8192 Hermitian
     Hamiltonians whose changes have the structure the paper describes (wide
     unchanged areas, a cross of frozen rows and columns, a share above
@@ -524,11 +548,290 @@ def _report_contour(args, wl, nsteps, kx, t_total, per_step, infos, cold_mean, p
     print(json.dumps(out), flush=True)
 
 
+GEMM_FAMILY = "k_zgemm<0>, k_zgemm_nc, k_zgemm_cn, k_zgemm_cc (+ k_zgemm_splitk_reduce)"
+
+
+def _roofline_gemm(infos):
+    ms = sum(i["gemm_kernel_ms"] for i in infos)
+    fl = sum(i["gemm_flops"] for i in infos)
+    la = sum(i["gemm_launches"] for i in infos)
+    achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    peak = PEAK_TFLOPS["f64"]
+    return {
+        "bound": "mfma", "kernel": "FP64 complex GEMM family: " + GEMM_FAMILY,
+        "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        "traffic": None,
+        "traffic_note": "no HBM counter summary for this family (MFMA-bound products; K >= 948)",
+        "launches": la, "avg_launch_ms": ms / max(la, 1), "flops_per_launch": fl / max(la, 1),
+        "kernel_ms_per_step": ms / max(len(infos), 1),
+        "algorithmic_flops_per_unit": "8 flops per complex multiply-add: 8 m n k for a dense product, "
+                                      "half where only one triangle of the output or of op(A) is involved",
+    }
+
+
+def _roofline_filter(infos, precision):
+    ms = sum(i["filter_kernel_ms"] for i in infos)
+    fl = sum(i["filter_flops"] for i in infos)
+    la = sum(i["filter_launches"] for i in infos)
+    dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}[precision]
+    kname = FILTER_KERNELS[precision]
+    achieved = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    peak = PEAK_TFLOPS[dtype]
+    ex = 3.0 if dtype == "bf16" else 1.0
+    return {
+        "bound": "mfma", "kernel": kname, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak if peak else None,
+        "traffic": committed_traffic(kname),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
+        "launches": la, "avg_launch_ms": ms / max(la, 1), "flops_per_launch": fl / max(la, 1),
+        "kernel_ms_per_step": ms / max(len(infos), 1),
+        "algorithmic_flops_per_unit": "8 n^2 per filtered column-step (complex multiply-add = 8 flops)",
+        "timed_span": "operand split + product + split-K reduction of each filter product",
+        # a split-BF16 product executes 3 BF16 MFMA products per real product
+        "executed_per_algorithmic": ex,
+        "executed_frac": achieved * ex / peak if peak else None,
+    }
+
+
+def run_sequence(args):
+    """The headline workload.  A 12-step SCF sequence (step 0 the constructed
+    pencil, A_k = A_{k-1} + eps_k H_k).  Step 0 is solved cold once (its time
+    is reported); its eigenvectors seed step 1.  The timed region is
+    `--steps` seeded solves cycling through steps 1..11 of the sequence, each
+    repeat starting again from step 0's vectors, bracketed by device
+    synchronisations; `--warmup` untimed seeded solves along the same cycle
+    come first.  Then the cold-start FP64 comparator solves every step once."""
+    import torch
+
+    from paper_1007_4400_amd import gevp, synth
+
+    wl = synth.LARGE if (args.n, args.nev) == (8192, 820) else synth.scaled(synth.LARGE, args.n, nev=args.nev)
+    K = wl.steps
+    h = gevp.Handle(0)
+    t0 = time.perf_counter()
+    A0, B, lam0, L, g = synth.make_pencil_torch(wl, args.seed, qr_on_host=args.host_qr)
+    del L
+    B = gevp.colmajor(B.contiguous())
+    As = [gevp.colmajor(A0)]
+    for k in range(1, K):
+        Hk = synth.unit_hermitian_torch(wl.n, g)
+        As.append(gevp.colmajor((As[-1] + synth.eps(wl, k) * Hk).contiguous()))
+        del Hk
+    exact0 = torch.sort(lam0).values[: wl.nev]
+    torch.cuda.synchronize()
+    log(f"generated {K} steps n={wl.n} in {time.perf_counter() - t0:.1f}s")
+    if args.calibration_copy:
+        _calibration_copy()
+
+    contour = args.filter == "contour"
+    opts = gevp.make_opts(precision=args.precision, filter=args.filter)
+    opts64 = gevp.make_opts(precision="fp64")
+    kx = h.block_size(wl.n, wl.nev, opts)
+    parity = {}
+
+    def solve(A, X0, o):
+        lam, Xo, res, info = h.solve(A, B, wl.nev, X0=X0, tol=args.tol, kx=kx, opts=o)
+        if info["max_resid"] > args.tol:
+            raise RuntimeError(f"residual {info['max_resid']:.3e} above tol")
+        return lam, Xo, info
+
+    # step 0, cold, in the form under test: its vectors seed every repeat
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    lam, X_step0, info0 = solve(As[0], None, opts)
+    t_cold0_mixed = time.perf_counter() - ts
+    err0 = ((lam[: wl.nev] - exact0).abs() / exact0.abs().clamp(min=1.0))
+    parity["step0_lambda_err_max"] = float(err0.max())
+    parity["step0_lambda_err_mean"] = float(err0.mean())
+    log(f"cold step 0 ({args.precision}): {t_cold0_mixed * 1e3:.1f} ms outer {info0['outer_iters']} "
+        f"lambda err vs constructed {parity['step0_lambda_err_max']:.2e}")
+
+    def cycle_step(j):
+        return 1 + (j % (K - 1))
+
+    X = X_step0
+    for j in range(args.warmup):
+        k = cycle_step(j)
+        if k == 1:
+            X = X_step0
+        lam, X, info = solve(As[k], X, opts)
+        log(f"warmup step {k}: outer {info['outer_iters']} resid {info['max_resid']:.2e}")
+
+    # timed region: seeded solves along the cycle; gevp_solve returns after
+    # its work has completed, so each step's host time is its device time
+    h.set_profiling(3 if contour else 6)  # events: filter products and FP64 GEMMs (contour: stages)
+    per_step, infos, lam_first, seed_of = [], [], {}, {}
+    torch.cuda.synchronize()
+    _mark_push("timed")
+    t_start = time.perf_counter()
+    for j in range(args.steps):
+        k = cycle_step(j)
+        if k == 1:
+            X = X_step0
+        if k not in seed_of:
+            seed_of[k] = X
+        ts = time.perf_counter()
+        lam, X, info = solve(As[k], X, opts)
+        per_step.append((k, time.perf_counter() - ts))
+        infos.append(info)
+        if k not in lam_first:
+            lam_first[k] = lam[: wl.nev].clone()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    _mark_pop()
+    h.set_profiling(0)
+    for (k, t), info in zip(per_step, infos):
+        log(f"step {k}: {t * 1e3:.1f} ms outer {info['outer_iters']} coldeg {info['col_degrees']} "
+            f"resid {info['max_resid']:.2e}")
+    parity["max_resid_rel"] = max(i["max_resid"] for i in infos)
+    last_k = per_step[-1][0]
+
+    # per-step medians over the repeats
+    by_step = {}
+    for k, t in per_step:
+        by_step.setdefault(k, []).append(t)
+    med = {k: statistics.median(v) for k, v in sorted(by_step.items())}
+    repeats = [sum(t for (k, t) in per_step[r * (K - 1):(r + 1) * (K - 1)]) / (K - 1)
+               for r in range(len(per_step) // (K - 1))]
+
+    # cold-start FP64 comparator on the same steps (and step 0), each once,
+    # compared eigenvalue by eigenvalue with the seeded mixed solves
+    cold = {}
+    dlam = {}
+    steps_cold = [0] + sorted(med)[: args.cold_steps if args.cold_steps >= 0 else None]
+    for k in steps_cold:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        lam_c, _, info = solve(As[k], None, opts64)
+        cold[k] = time.perf_counter() - ts
+        if k in lam_first:
+            d = (lam_first[k] - lam_c[: wl.nev]).abs() / lam_c[: wl.nev].abs().clamp(min=1.0)
+            dlam[k] = float(d.max())
+        log(f"cold fp64 step {k}: {cold[k] * 1e3:.1f} ms outer {info['outer_iters']}"
+            + (f" max|dlambda| vs seeded {dlam[k]:.2e}" if k in dlam else ""))
+    both = [k for k in med if k in cold]
+    sum_cold = sum(cold[k] for k in both)
+    sum_seed = sum(med[k] for k in both)
+    parity["seeded_vs_cold_fp64_lambda_err_max"] = max(dlam.values()) if dlam else None
+    parity["seeded_vs_cold_fp64_lambda_err_per_step"] = {str(k): v for k, v in sorted(dlam.items())}
+
+    # sampled independent check of returned pairs at the last timed step by the
+    # oracle's O(n^2) residual on the host, scaled by a host lower bound of ||A||_2
+    try:
+        from oracle import oracle
+
+        An = As[last_k].cpu().numpy()
+        Bn = B.cpu().numpy()
+        lam_h = lam.cpu().numpy()
+        Xh = X.cpu().numpy()
+        nA = oracle.norm2_lower(An, iters=20)
+        parity["host_normA_lower"] = nA
+        for i in (0, wl.nev - 1):
+            r, q = oracle.pair_residual(An, Bn, lam_h[i], Xh[:, i])
+            parity[f"oracle_pair_resid_{i}"] = r / nA
+            parity[f"oracle_xBx_{i}"] = q
+        del An, Bn
+    except Exception as e:  # the check is reported, never silently skipped
+        parity["oracle_pair_check_error"] = repr(e)
+
+    # the forms side by side (untimed): one seeded solve of the middle step
+    forms = {}
+    mid = 6 if 6 in seed_of else sorted(seed_of)[len(seed_of) // 2]
+    if not contour:
+        for form in ("fp64", "fp32", "bf16x3"):
+            o = gevp.make_opts(precision=form)
+            kxf = h.block_size(wl.n, wl.nev, o)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            lf, _, _, inf_f = h.solve(As[mid], B, wl.nev, X0=seed_of[mid][:, :kxf], tol=args.tol, kx=kxf, opts=o)
+            forms[form] = {"s": time.perf_counter() - ts, "outer": inf_f["outer_iters"],
+                           "col_degrees": inf_f["col_degrees"], "max_resid": inf_f["max_resid"]}
+        forms["step"] = mid
+
+    # seed monitor (untimed): principal-angle RMS sine and deviation angles of
+    # the last step's result against its seed, and what the monitor adds
+    monitor = {}
+    try:
+        if contour:
+            raise StopIteration  # the seed monitor side report belongs to the Chebyshev run
+        X0m = seed_of[last_k]
+        om = gevp.make_opts(precision=args.precision, seed_monitor=True)
+        t_on, t_off = [], []
+        for _ in range(2):
+            for o_, acc in ((om, t_on), (opts, t_off)):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                _, _, _, inf_m = h.solve(As[last_k], B, wl.nev, X0=X0m, tol=args.tol, kx=kx, opts=o_)
+                torch.cuda.synchronize()
+                acc.append(time.perf_counter() - ts)
+                if o_ is om:
+                    monitor = {k_: inf_m[k_] for k_ in ("seed_sin_rms", "seed_dev_mean", "seed_dev_max",
+                                                         "seed_reindexed")}
+        monitor["added_ms"] = (min(t_on) - min(t_off)) * 1e3
+        monitor["step"] = last_k
+    except StopIteration:
+        monitor = {}
+    except Exception as e:  # reported, never silently skipped
+        monitor = {"error": repr(e)}
+
+    value = t_total / args.steps
+    cold_mean = sum(cold[k] for k in both) / max(len(both), 1)
+    if contour:
+        return _report_contour(args, wl, K, kx, t_total, [t for _, t in per_step], infos, cold_mean,
+                               parity)
+    rf = _roofline_filter(infos, args.precision)
+    rg = _roofline_gemm(infos)
+    # the dominant kernel of the timed step by summed event time
+    primary, secondary = (rg, rf) if rg["kernel_ms_per_step"] >= rf["kernel_ms_per_step"] else (rf, rg)
+    out = {
+        "metric": "per-SCF-step eigensolve time N=8192 nev=820, mixed vs FP64, resid<=1e-10",
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": value * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"scf_sequence_n{wl.n}_nev{wl.nev}_steps{K}_seeded_{args.precision}",
+                   "timed_steps": f"seeded steps 1..{K - 1} of the {K}-step sequence, cycled "
+                                  f"({args.steps} solves; every repeat restarts from step 0's vectors)",
+                   "n": wl.n, "nev": wl.nev, "block": kx, "tol": args.tol,
+                   "precision": args.precision},
+        "roofline": primary,
+        "roofline_secondary": secondary,
+        "median_s_per_step": sum(med.values()) / len(med),
+        "per_step_median_s": {str(k): v for k, v in med.items()},
+        "repeat_mean_s_per_step": repeats,
+        "cold_step0_s": {"fp64": cold.get(0), args.precision: t_cold0_mixed},
+        "cold_fp64_s_per_step": cold_mean,
+        "cold_fp64_per_step_s": {str(k): v for k, v in sorted(cold.items())},
+        "speedup_vs_cold_fp64": sum_cold / sum_seed if sum_seed > 0 else None,
+        "speedup_vs_cold_fp64_steps": f"sum over steps {both[0]}..{both[-1]} of cold FP64 / median seeded",
+        "speedup_incl_step0": ((sum_cold + cold[0]) / (sum_seed + t_cold0_mixed)
+                               if sum_seed > 0 and 0 in cold else None),
+        "forms_seeded_one_step": forms,
+        "parity": parity,
+        "seed_monitor": monitor,
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(wl.n)
+        except Exception as e:
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=11)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 33 = three repeats of seeded steps 1..11 for the "
+                         "sequence, 11 for the update workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; update: 1)")
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--nev", type=int, default=820)
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
@@ -536,7 +839,8 @@ def main():
                     help="contour: seeded steps use the contour-integral (Sakurai-Sugiura) filter; "
                          "FP64 factorisations with --precision fp64, else FP32 ones in the "
                          "residual-correction form (cold steps keep the Chebyshev filter)")
-    ap.add_argument("--cold-steps", type=int, default=2)
+    ap.add_argument("--cold-steps", type=int, default=-1,
+                    help="cold FP64 comparator on the first N timed steps (-1: all of them)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -554,6 +858,10 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 11 if args.workload == "update" else 33
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "update" else 2
     if args.rocprof_summary:
         print(rocprof_summary(args.rocprof_summary, args.summary_kernel or FILTER_KERNELS[args.precision],
                               pmc_last=args.pmc_last))
@@ -567,181 +875,7 @@ def main():
     if args.workload == "update":
         return run_update(args)
 
-    import torch
-
-    from paper_1007_4400_amd import gevp, synth
-
-    wl = synth.LARGE if args.n == 8192 and args.nev == 820 else synth.scaled(synth.LARGE, args.n, nev=args.nev)
-    nsteps = args.warmup + args.steps
-    h = gevp.Handle(0)
-    dev = "cuda"
-    t0 = time.perf_counter()
-    A0, B, lam0, L, g = synth.make_pencil_torch(wl, args.seed, device=dev, qr_on_host=args.host_qr)
-    del L
-    B = gevp.colmajor(B.contiguous())
-    As = [gevp.colmajor(A0)]
-    for k in range(1, nsteps):
-        Hk = synth.unit_hermitian_torch(wl.n, g, device=dev)
-        As.append(gevp.colmajor((As[-1] + synth.eps(wl, k) * Hk).contiguous()))
-        del Hk
-    exact0 = torch.sort(lam0).values[: wl.nev]
-    torch.cuda.synchronize()
-    log(f"generated {nsteps} steps n={wl.n} in {time.perf_counter() - t0:.1f}s")
-
-    if args.calibration_copy:
-        _calibration_copy()
-
-    contour = args.filter == "contour"
-    opts = gevp.make_opts(precision=args.precision, filter=args.filter)
-    opts64 = gevp.make_opts(precision="fp64")
-    kx = h.block_size(wl.n, wl.nev, opts)
-    X = None
-    parity = {"max_resid_rel": 0.0, "step0_lambda_err": None}
-
-    def solve(A, X0, o):
-        lam, Xo, res, info = h.solve(A, B, wl.nev, X0=X0, tol=args.tol, kx=kx, opts=o)
-        if info["max_resid"] > args.tol:
-            raise RuntimeError(f"residual {info['max_resid']:.3e} above tol")
-        return lam, Xo, info
-
-    for k in range(args.warmup):
-        lam, X, info = solve(As[k], X, opts)
-        if k == 0:
-            parity["step0_lambda_err"] = float(((lam[: wl.nev] - exact0).abs() /
-                                                exact0.abs().clamp(min=1.0)).max())
-        log(f"warmup step {k}: outer {info['outer_iters']} resid {info['max_resid']:.2e}")
-
-    # timed seeded solves, filter kernel timed by events around each launch;
-    # the region is also marked for rocprofv3 --marker-trace
-    h.set_profiling(3 if contour else 2)  # contour: stage times for the filter stage
-    per_step, infos = [], []
-    torch.cuda.synchronize()
-    _mark_push("timed")
-    t_start = time.perf_counter()
-    Xprev_last = None
-    for k in range(args.warmup, nsteps):
-        ts = time.perf_counter()
-        Xprev_last = X
-        lam, X, info = solve(As[k], X, opts)
-        per_step.append(time.perf_counter() - ts)
-        infos.append(info)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    _mark_pop()
-    h.set_profiling(0)
-    for k, (t, info) in enumerate(zip(per_step, infos)):
-        log(f"step {args.warmup + k}: {t * 1e3:.1f} ms outer {info['outer_iters']} "
-            f"coldeg {info['col_degrees']} resid {info['max_resid']:.2e}")
-        parity["max_resid_rel"] = max(parity["max_resid_rel"], info["max_resid"])
-
-    # cold-start FP64 comparator on the last timed steps
-    cold = []
-    for k in range(nsteps - args.cold_steps, nsteps):
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        _, _, info = solve(As[k], None, opts64)
-        cold.append(time.perf_counter() - ts)
-        log(f"cold fp64 step {k}: {cold[-1] * 1e3:.1f} ms outer {info['outer_iters']}")
-    cold_mean = sum(cold) / max(len(cold), 1)
-
-    # sampled independent check of two returned pairs by the oracle's O(n^2)
-    # residual on the host (last step)
-    try:
-        from oracle import oracle
-
-        An = As[-1].cpu().numpy()
-        Bn = B.cpu().numpy()
-        lam_h = lam.cpu().numpy()
-        Xh = X.cpu().numpy()
-        for i in (0, wl.nev - 1):
-            r, q = oracle.pair_residual(An, Bn, lam_h[i], Xh[:, i])
-            parity[f"oracle_pair_resid_{i}"] = r / infos[-1]["normA"]
-            parity[f"oracle_xBx_{i}"] = q
-        del An, Bn
-    except Exception as e:  # the check is reported, never silently skipped
-        parity["oracle_pair_check_error"] = repr(e)
-
-    # seed monitor (untimed): principal-angle RMS sine and deviation angles of
-    # the last step's result against its seed, and what the monitor adds to
-    # a seeded solve (best of two solves each way)
-    monitor = {}
-    try:
-        if contour:
-            raise StopIteration  # the seed monitor side report belongs to the Chebyshev run
-        X0m = Xprev_last
-        om = gevp.make_opts(precision=args.precision, seed_monitor=True)
-        t_on, t_off = [], []
-        for _ in range(2):
-            for o_, acc in ((om, t_on), (opts, t_off)):
-                torch.cuda.synchronize()
-                ts = time.perf_counter()
-                _, _, _, inf_m = h.solve(As[-1], B, wl.nev, X0=X0m, tol=args.tol, kx=kx, opts=o_)
-                torch.cuda.synchronize()
-                acc.append(time.perf_counter() - ts)
-                if o_ is om:
-                    monitor = {k_: inf_m[k_] for k_ in ("seed_sin_rms", "seed_dev_mean", "seed_dev_max",
-                                                         "seed_reindexed")}
-        monitor["added_ms"] = (min(t_on) - min(t_off)) * 1e3
-    except StopIteration:
-        monitor = {}
-    except Exception as e:  # reported, never silently skipped
-        monitor = {"error": repr(e)}
-
-    if contour:
-        return _report_contour(args, wl, nsteps, kx, t_total, per_step, infos, cold_mean, parity)
-    filt_ms = sum(i["filter_kernel_ms"] for i in infos)
-    filt_flops = sum(i["filter_flops"] for i in infos)
-    filt_launches = sum(i["filter_launches"] for i in infos)
-    dtype = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}[args.precision]
-    kname = FILTER_KERNELS[args.precision]
-    achieved = filt_flops / (filt_ms * 1e-3) / 1e12 if filt_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[dtype]
-    value = t_total / args.steps
-    out = {
-        "metric": "per-SCF-step eigensolve time N=8192 nev=820, mixed vs FP64, resid<=1e-10",
-        "value": value,
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": value * 1e3,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32+f64", "bf16": "bf16x3+f64"}[dtype],
-        "data": "synthetic",
-        "config": {"workload": f"scf_sequence_n{wl.n}_nev{wl.nev}_steps{nsteps}_seeded_{args.precision}",
-                   "n": wl.n, "nev": wl.nev, "block": kx, "tol": args.tol,
-                   "precision": args.precision},
-        "roofline": {
-            "bound": "mfma",
-            "kernel": kname,
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak if peak else None,
-            "traffic": committed_traffic(kname),
-            "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated)",
-            "launches": filt_launches,
-            "avg_launch_ms": filt_ms / max(filt_launches, 1),
-            "flops_per_launch": filt_flops / max(filt_launches, 1),
-            "algorithmic_flops_per_unit": "8 n^2 per filtered column-step (complex multiply-add = 8 flops)",
-            # a split-BF16 product executes 3 BF16 MFMA products per real product
-            "executed_per_algorithmic": 3.0 if dtype == "bf16" else 1.0,
-            "executed_frac": (achieved * (3.0 if dtype == "bf16" else 1.0)) / peak if peak else None,
-        },
-        "cold_fp64_s_per_step": cold_mean,
-        "speedup_vs_cold_fp64": cold_mean / value if value > 0 else None,
-        "per_step_s": per_step,
-        "parity": parity,
-        "seed_monitor": monitor,
-    }
-    if not args.no_cpu_baseline:
-        try:
-            out["cpu_baseline"] = cpu_baseline(2048, wl.n)
-        except Exception as e:
-            out["cpu_baseline"] = {"error": repr(e)}
-    print(json.dumps(out), flush=True)
+    return run_sequence(args)
 
 
 if __name__ == "__main__":

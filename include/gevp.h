@@ -22,9 +22,11 @@
  *    column-major order with a leading dimension >= the row count, in DEVICE
  *    memory of the handle's device.  Only the lower triangles of A and B are
  *    read (LAPACK uplo = 'L').  A, B and X0 are never written.
- *  - The caller owns every buffer passed in; the handle owns its workspace,
- *    allocated on first use with hipMalloc and grown as needed, freed by
- *    gevp_destroy.
+ *  - The caller owns every buffer passed in.  Device workspace: by default the
+ *    handle allocates it on first use with hipMalloc, grows it as needed and
+ *    frees it in gevp_destroy; after gevp_set_workspace the handle works only
+ *    in the caller's buffer (e.g. a torch tensor) and allocates no device
+ *    memory at all, returning GEVP_ERR_WORKSPACE when a call needs more.
  *  - Work runs on the stream set with gevp_set_stream (default: the null
  *    stream).  gevp_solve returns after its work has completed, because its
  *    status depends on convergence; gevp_backward and the gevp_k_* kernels
@@ -52,8 +54,10 @@ typedef enum {
   GEVP_ERR_HIP = 4,        /* a HIP runtime call failed */
   GEVP_ERR_NONFINITE = 5,  /* NaN or Inf in A, B or X0 */
   GEVP_ERR_ALLOC = 6,      /* workspace allocation failed */
-  GEVP_ERR_SINGULAR = 7    /* a shifted matrix of the contour filter had a zero or
+  GEVP_ERR_SINGULAR = 7,   /* a shifted matrix of the contour filter had a zero or
                               non-finite pivot */
+  GEVP_ERR_WORKSPACE = 8   /* the buffer given to gevp_set_workspace is too small
+                              for this call (see gevp_workspace_size) */
 } gevp_status;
 
 typedef enum {
@@ -74,7 +78,7 @@ typedef struct {
   int skip_final_residual;  /* 1: skip the original-basis residual check */
   int batch_streams;        /* gevp_solve_batched: concurrent streams; 0 = 8 */
   int seed_monitor;         /* 1: with a seed X0, report how it relates to the result
-                               (gevp_info seed_*; needs the final residual check) */
+                               (gevp_info seed_*) */
   int filter;               /* gevp_filter; default GEVP_FILTER_CHEBYSHEV */
   int contour_points;       /* quadrature nodes of the contour filter; 0 = 8 */
   int reserved[4];
@@ -113,8 +117,14 @@ typedef struct {
      "Eigenvectors evolution": how far eigenvectors move between SCF steps).
      With k = min(nev, k0) and M = X0(:, :k)^H B X(:, :k) (both blocks
      B-orthonormal, so the singular values of M are the cosines of the
-     principal angles between the two spans):
-       seed_sin_rms   = sqrt(max(0, k - ||M||_F^2) / k), the RMS sine of those angles;
+     principal angles between the two spans; formed in the reduced basis as
+     (L^H X0)^H (L^H X)):
+       seed_sin_rms   = the RMS sine of those angles, sqrt(sum_j ||r_j||_B^2 / k)
+                        with r_j the B-orthogonal projection residual of seed
+                        column j onto span X(:, :k) (equal to
+                        sqrt(k - ||M||_F^2) in exact arithmetic, but free of
+                        its cancellation, so it resolves angles down to
+                        rounding level);
        seed_dev_mean, seed_dev_max: per result column j, the deviation angle
                         arccos(max_i |M(i, j)|) / (pi/2) (1 = orthogonal), mean and max;
        seed_reindexed = columns j matched to a seed column other than j;
@@ -136,6 +146,14 @@ typedef struct {
   int contour_applications;
   int64_t contour_columns;
   double seed_dev_std;    /* see the seed monitor fields above */
+  /* FP64 complex GEMM launches (profiling bit 4, every stream of the solve):
+     summed duration (HIP events around each launch, split-K reduction
+     included), algorithmic flops (8 m n k for a dense product, half of it
+     where only one triangle of the output or of op(A) is involved) and the
+     number of launches */
+  double gemm_kernel_ms;
+  double gemm_flops;
+  int64_t gemm_launches;
 } gevp_info;
 
 typedef enum {
@@ -156,10 +174,12 @@ gevp_status gevp_create(gevp_handle* h, int device);
 gevp_status gevp_set_stream(gevp_handle h, void* hip_stream);
 
 /* Profiling bits: 1 = per-stage HIP event times into gevp_info.ms (adds a
- * synchronisation per stage); 2 = HIP events around every filter GEMM launch,
- * summed into gevp_info.filter_kernel_ms (no added synchronisation), and
- * around the scan and apply kernels of gevp_update_thresholded
- * (gevp_update_info.scan_ms, apply_ms). */
+ * synchronisation per stage); 2 = HIP events around every filter product
+ * (its operand conversion, product and split-K reduction kernels), summed
+ * into gevp_info.filter_kernel_ms (no added synchronisation), and around the
+ * scan and apply kernels of gevp_update_thresholded (gevp_update_info.scan_ms,
+ * apply_ms); 4 = HIP events around every FP64 GEMM launch, summed into
+ * gevp_info.gemm_kernel_ms with their flops. */
 gevp_status gevp_set_profiling(gevp_handle h, int flags);
 
 /* Free the workspace and the handle. */
@@ -169,6 +189,33 @@ const char* gevp_status_string(gevp_status s);
 
 /* Block width nev + nex that gevp_solve uses for these options. */
 int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev);
+
+/* Device workspace, in bytes, that gevp_solve needs for a problem of order n
+ * with nev wanted pairs and these options (any seed), including six fixed
+ * split-K buffers of 128 MiB for the streams a solve may use.  Also enough for
+ * gevp_backward with the same n and nev columns.  *bytes is written; the
+ * handle is not touched and may be NULL. */
+gevp_status gevp_workspace_size(gevp_handle h, const gevp_opts* opts, int64_t n, int64_t nev,
+                                size_t* bytes);
+
+/* The same for gevp_solve_batched over `count` problems of orders n[i] with
+ * nev[i] wanted pairs: every concurrent stream gets an equal share, sized for
+ * the largest problem. */
+gevp_status gevp_workspace_size_batched(gevp_handle h, const gevp_opts* opts, int count,
+                                        const int64_t* n, const int64_t* nev, size_t* bytes);
+
+/* Work in caller-owned device memory from now on (the paper states the
+ * problem, section 1, eq. (3); where the memory comes from is the caller's
+ * choice, e.g. a torch tensor).  dev_ptr: device memory of the handle's
+ * device, 256-byte aligned, `bytes` >= 6 x 128 MiB + 256 (the split-K slots
+ * at its top end), owned by the caller and left valid until the handle is
+ * destroyed or the workspace replaced.  The handle then calls no hipMalloc
+ * or hipFree for device memory; a call that needs more than the buffer
+ * returns GEVP_ERR_WORKSPACE before launching anything.  Memory the handle
+ * had allocated itself is freed here.  dev_ptr = NULL returns to
+ * library-managed memory.  Waits for the handle's streams.  Calls that share
+ * a handle must not overlap (one handle per stream, as always). */
+gevp_status gevp_set_workspace(gevp_handle h, void* dev_ptr, size_t bytes);
 
 /*
  * Lowest eigenpairs of A x = lambda B x.
@@ -320,7 +367,7 @@ gevp_status gevp_k_contour_filter(gevp_handle h, int64_t n, const void* C, int64
 
 /* ------------------------------------------------------------------------
  * Thresholded partial update of a Hermitian matrix between two SCF
- * iterations (section 3, paragraph "Matrix generation").  The paper measures
+ * iterations (section 2, paragraph "Matrix generation").  The paper measures
  * the change between adjacent Hamiltonians at one k-point by the largest
  * entry variation delta and proposes updating only the entries whose change,
  * normalised by delta, exceeds a threshold p_t; the other entries keep their

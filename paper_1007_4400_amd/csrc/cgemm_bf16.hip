@@ -456,6 +456,9 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   uint4* bp = (uint4*)wb;
   p.Bp = bp;
   p.part = (zf*)(wb + ws_round((size_t)n * p.KG * 64));
+  // the event pair (profiling bit 2) brackets the whole product: the split of
+  // the iterate into planes, the product and the split-K reduction
+  GEVP_TRY(fev_mark(c));
   // B planes
   {
     const int64_t items = n * (int64_t)p.KG;
@@ -473,7 +476,7 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   const int64_t total = tiles * p.splits;
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
-  // 136 KB of LDS per work-group (gfx950 has 160 KB per CU); set once,
+  // 128 KiB of LDS per work-group (gfx950 has 160 KB per CU); set once,
   // thread-safely (batched solves launch from several host threads)
   static const bool attr_set = [&]() {
     (void)hipFuncSetAttribute((const void*)k_cgemm_bf16x3_filter,
@@ -481,15 +484,14 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
     return true;
   }();
   (void)attr_set;
-  GEVP_TRY(fev_mark(c));
   hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(512), DMA_LDS, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
-  GEVP_TRY(fev_mark(c));
   if (p.splits > 1) {
     const int64_t elems = tiles * BM * BN;
     hipLaunchKernelGGL(k_bf16_splitk_reduce, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,
                        c->stream, p);
     GEVP_HIP_TRY(hipGetLastError());
   }
+  GEVP_TRY(fev_mark(c));
   return GEVP_OK;
 }

@@ -318,6 +318,7 @@ gevp_status panel_ctx(gevp_ctx* c, gevp_ctx** out) {
     }
     w->owns_stream = true;
     c->panel = w;
+    ext_assign(c, w, SLOT_PANEL);
   }
   for (hipEvent_t& e : c->pev)
     if (!e) GEVP_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -396,7 +397,10 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
     const int64_t half = ((n + NB - 1) / NB / 2) * NB;  // first row of the second half
     bool mid_done = false;
     gevp_ctx* pc = c;  // without inner streams the panels run in order on c's stream
-    if (c->inner_streams) GEVP_TRY(panel_ctx(c, &pc));
+    if (c->inner_streams) {
+      GEVP_TRY(panel_ctx(c, &pc));
+      pc->profiling = c->profiling & 4;
+    }
     const bool two = pc != c;
     hipEvent_t evp = c->pev[0], evn = c->pev[1];
     // the panel stream starts after the work already queued on the main stream

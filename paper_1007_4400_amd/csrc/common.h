@@ -30,8 +30,12 @@ typedef double2 zd;  // complex128 stored as (re, im)
   } while (0)
 
 int gevp_log_enabled();
-// event pair around one filter product kernel (profiling bit 2), see solver.hip
+// event pair around one filter product (profiling bit 2), see solver.hip
 gevp_status fev_mark(gevp_ctx* c);
+// event pair around one FP64 GEMM launch (profiling bit 4); gev_end also adds
+// the launch's algorithmic flops to the context's tally
+gevp_status gev_begin(gevp_ctx* c);
+gevp_status gev_end(gevp_ctx* c, double flops);
 int gevp_device_cus(int device);  // compute units of a device (cached)
 
 struct gevp_ctx {
@@ -46,6 +50,11 @@ struct gevp_ctx {
   hipEvent_t* fev = nullptr;
   int fev_cap = 0;
   int fev_used = 0;
+  // event pairs around FP64 GEMM launches (profiling bit 4) and their flops
+  hipEvent_t* gev = nullptr;
+  int gev_cap = 0;
+  int gev_used = 0;
+  double gev_flops = 0.0;
   // split-K partial products of launch_zgemm (grown on demand, freed by destroy)
   void* skw = nullptr;
   size_t skw_bytes = 0;
@@ -62,7 +71,25 @@ struct gevp_ctx {
   // streams of the contour filter's independent quadrature nodes (on demand)
   std::vector<gevp_ctx*> qctx;
   bool owns_stream = false;
+  // Caller-owned device memory (gevp_set_workspace): ws and skw point into it
+  // and are never allocated or freed by the library.  On the handle, ext_base
+  // / ext_bytes describe the whole region; sub-contexts only borrow slices.
+  bool ext = false;
+  char* ext_base = nullptr;
+  size_t ext_bytes = 0;
 };
+
+// Split-K partial products of launch_zgemm: one fixed-size buffer per stream
+// context (2048 partial 64 x 64 complex128 tiles).
+constexpr size_t SKW_BYTES = (size_t)2048 * 64 * 64 * 16;
+// Slots of a caller-owned workspace reserved for split-K buffers, at its top
+// end: the handle's stream, the second stream of a seeded solve, the panel
+// stream of the Cholesky factorisation and three quadrature-node streams.
+constexpr int EXT_SLOTS = 6;
+enum { SLOT_MAIN = 0, SLOT_AUX = 1, SLOT_PANEL = 2, SLOT_QUAD0 = 3 };
+// Lend slot `slot` of parent's caller-owned workspace to the sub-context
+// child (no-op when parent manages its own memory).
+void ext_assign(gevp_ctx* parent, gevp_ctx* child, int slot);
 
 // Workspace carving.  reserve() (re)allocates when `bytes` exceeds the current
 // size; take() hands out 256-byte aligned pieces until reset().
@@ -146,6 +173,13 @@ gevp_status contour_apply32(gevp_ctx* c, int64_t n, int64_t m, const zd* Q, int6
 // Small Hermitian eigensolver (n <= 2048): H (full storage, overwritten),
 // theta ascending, Z (n x n) unitary.  work >= heev_work_bytes(n).
 size_t heev_work_bytes(int64_t n);
+// Eigen-decomposition of the real symmetric tridiagonal T (diagonal d[n],
+// off-diagonal e[n-1]): theta ascending by Sturm-count multisection, the
+// orthonormal eigenvectors by inverse iteration, Zt[i * n + j] = component i
+// of eigenvector j.  work >= tridiag_eig_work_bytes(n).  Asynchronous.
+size_t tridiag_eig_work_bytes(int64_t n);
+gevp_status tridiag_eig(gevp_ctx* c, int64_t n, const double* d, const double* e, double* theta,
+                        double* Zt, void* work);
 gevp_status heev_small(gevp_ctx* c, int64_t n, zd* H, int64_t ldh, double* theta, zd* Z,
                        int64_t ldz, void* work);
 
@@ -168,10 +202,14 @@ gevp_status launch_colnorms(gevp_ctx* c, int64_t rows, int64_t cols, const zd* V
 // 6 doubles).  seed_monitor_stats also completes it on the host and waits:
 // res = sin_rms, dev_mean, dev_max, reindexed, dev_std under the
 // angle-minimising matching, match[j] = matched seed column (may be null).
+// rnorm (device, k, optional): norms of the projection residuals of the seed
+// columns onto the result's span; sin_rms then comes from them instead of
+// from k - ||M||_F^2.
 gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
-                                double* out);
+                                double* out, const double* rnorm = nullptr);
 gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
-                               double* out, double res[5], int* match);
+                               double* out, double res[5], int* match,
+                               const double* rnorm = nullptr);
 gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                                const int* perm, zd* D, int64_t ldd);
 gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx);

@@ -374,6 +374,7 @@ gevp_status quad_ctx(gevp_ctx* c, int i, gevp_ctx** out) {
     w->owns_stream = true;
     w->inner_streams = false;
     c->qctx.push_back(w);
+    ext_assign(c, w, SLOT_QUAD0 + (int)c->qctx.size() - 1);
   }
   *out = c->qctx[i];
   return GEVP_OK;

@@ -582,6 +582,39 @@ constexpr int64_t APPLY_LDS = 131072;  // LDS budget of the reflector sweep (byt
 
 inline int trd_groups(int64_t n) { return (int)(n - 1 < 256 ? (n > 1 ? n - 1 : 1) : 256); }
 
+size_t tridiag_eig_work_bytes(int64_t n) {
+  return 5 * ws_round(sizeof(double) * n * n) + ws_round(sizeof(double) * 8);  // U, Vv, Ww, Lm, Sw; norm
+}
+
+gevp_status tridiag_eig(gevp_ctx* c, int64_t n64, const double* d, const double* e, double* theta,
+                        double* Zt, void* work) {
+  if (n64 <= 0) return GEVP_OK;
+  const int n = (int)n64;
+  char* w = (char*)work;
+  auto take = [&](size_t bytes) {
+    void* p = w;
+    w += ws_round(bytes);
+    return p;
+  };
+  double* U = (double*)take(sizeof(double) * n * n);
+  double* Vv = (double*)take(sizeof(double) * n * n);
+  double* Ww = (double*)take(sizeof(double) * n * n);
+  double* Lm = (double*)take(sizeof(double) * n * n);
+  double* Sw = (double*)take(sizeof(double) * n * n);
+  double* tn = (double*)take(sizeof(double) * 8);
+  hipLaunchKernelGGL(k_tri_norm, dim3(1), dim3(64), 0, c->stream, d, e, n, tn);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 3) / 4), dim3(HT), sizeof(double) * 2 * n, c->stream,
+                     d, e, n, theta);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_tri_invit, dim3((n + 63) / 64), dim3(64), sizeof(double) * 2 * n, c->stream,
+                     d, e, n, theta, U, Vv, Ww, Lm, Sw, Zt, tn);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, tn);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
 size_t heev_work_bytes(int64_t n) {
   const int G = trd_groups(n);
   size_t b = 0;
@@ -590,8 +623,8 @@ size_t heev_work_bytes(int64_t n) {
   b += 2 * ws_round(sizeof(double) * n);      // d, e
   b += ws_round(sizeof(zd) * 2 * n);          // pb
   b += ws_round(sizeof(zd) * 2 * G);          // pp
-  b += 6 * ws_round(sizeof(double) * n * n);  // U, Vv, Ww, Lm, Zt + spare
-  b += ws_round(sizeof(double) * 8);
+  b += ws_round(sizeof(double) * n * n);      // Zt
+  b += tridiag_eig_work_bytes(n);
   return b;
 }
 
@@ -619,13 +652,8 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   a.pb = (zd*)take(sizeof(zd) * 2 * n);
   a.pp = (zd*)take(sizeof(zd) * 2 * G);
   a.G = G;
-  double* U = (double*)take(sizeof(double) * n * n);
-  double* Vv = (double*)take(sizeof(double) * n * n);
-  double* Ww = (double*)take(sizeof(double) * n * n);
-  double* Lm = (double*)take(sizeof(double) * n * n);
   double* Zt = (double*)take(sizeof(double) * n * n);
-  double* Sw = (double*)take(sizeof(double) * n * n);
-  double* tn = (double*)take(sizeof(double) * 8);
+  void* tw = take(tridiag_eig_work_bytes(n));
 
   const size_t shv = sizeof(zd) * (size_t)n;
   const size_t sh3 = 3 * shv;  // v_s, w_{s-1}, v_{s-1}
@@ -651,18 +679,7 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
       GEVP_HIP_TRY(hipGetLastError());
     }
   }
-  hipLaunchKernelGGL(k_tri_norm, dim3(1), dim3(64), 0, c->stream, a.d, a.e, n, tn);
-  GEVP_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_tri_bisect, dim3((n + 3) / 4), dim3(HT), sizeof(double) * 2 * n, c->stream,
-                     a.d, a.e, n, theta);
-  GEVP_HIP_TRY(hipGetLastError());
-  // ||T|| is needed on the host only as a scale for the zero-pivot guard and
-  // the cluster tolerance; read it back (one small synchronous copy).
-  hipLaunchKernelGGL(k_tri_invit, dim3((n + 63) / 64), dim3(64), sizeof(double) * 2 * n, c->stream,
-                     a.d, a.e, n, theta, U, Vv, Ww, Lm, Sw, Zt, tn);
-  GEVP_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_tri_cluster_mgs, dim3(n), dim3(HT), 0, c->stream, theta, n, Zt, tn);
-  GEVP_HIP_TRY(hipGetLastError());
+  GEVP_TRY(tridiag_eig(c, n, a.d, a.e, theta, Zt, tw));
   const unsigned tb = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
   GEVP_HIP_TRY(hipGetLastError());

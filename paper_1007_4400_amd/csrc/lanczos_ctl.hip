@@ -84,86 +84,36 @@ __global__ __launch_bounds__(1024) void k_lanczos_vec(int64_t n, const zd* vprev
   }
 }
 
-// Eigenvalues of the k x k Lanczos tridiagonal with the first component of
-// each eigenvector, by implicit Wilkinson-shift QR tracking only the first
-// row of the accumulated rotations.  Single thread; k <= 64.
-__global__ void k_lanczos_finish(const double* alpha, const double* beta, int k, double frac,
-                                 double* out) {
+// Summary of the k Ritz values theta (ascending) of the Lanczos tridiagonal
+// and the first components Zt[0 * k + j] of its eigenvectors (from
+// tridiag_eig: Sturm-count multisection and inverse iteration).  The squared
+// first components are the weights the start vector gives each Ritz value,
+// a coarse estimate of the spectral density.  Single thread; k <= 64.
+__global__ void k_lanczos_summary(const double* theta, const double* Zt, const double* beta, int k,
+                                  double frac, double* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double d[64], e[64], z[64];
-  for (int i = 0; i < k; ++i) {
-    d[i] = alpha[i];
-    e[i] = (i < k - 1) ? beta[i] : 0.0;
-    z[i] = (i == 0) ? 1.0 : 0.0;
-  }
-  double tn = 0.0;
-  for (int i = 0; i < k; ++i) tn = fmax(tn, fabs(d[i]) + fabs(e[i]) + (i ? fabs(e[i - 1]) : 0.0));
-  int m = k - 1, guard = 0;
-  while (m > 0 && guard < 100 * k) {
-    if (fabs(e[m - 1]) <= DBL_EPSILON * (fabs(d[m - 1]) + fabs(d[m])) || fabs(e[m - 1]) <= DBL_EPSILON * tn) {
-      e[m - 1] = 0.0;
-      --m;
-      continue;
-    }
-    int l = m - 1;
-    while (l > 0 && fabs(e[l - 1]) > DBL_EPSILON * (fabs(d[l - 1]) + fabs(d[l])) &&
-           fabs(e[l - 1]) > DBL_EPSILON * tn)
-      --l;
-    ++guard;
-    const double aa = d[m - 1], bb = e[m - 1], cc = d[m];
-    const double del = 0.5 * (aa - cc);
-    const double den = del + copysign(hypot(del, bb), del);
-    const double mu = (den != 0.0) ? cc - bb * bb / den : cc - fabs(bb);
-    double x = d[l] - mu, y = e[l];
-    for (int q = l; q < m; ++q) {
-      const double r = hypot(x, y);
-      const double cs = (r == 0.0) ? 1.0 : x / r, sn = (r == 0.0) ? 0.0 : y / r;
-      if (q > l) e[q - 1] = r;
-      const double dq = d[q], dq1 = d[q + 1], eq = e[q];
-      d[q] = cs * cs * dq + 2.0 * cs * sn * eq + sn * sn * dq1;
-      d[q + 1] = sn * sn * dq - 2.0 * cs * sn * eq + cs * cs * dq1;
-      e[q] = cs * sn * (dq1 - dq) + (cs * cs - sn * sn) * eq;
-      if (q < m - 1) {
-        x = e[q];
-        y = sn * e[q + 1];
-        e[q + 1] = cs * e[q + 1];
-      }
-      const double z0 = z[q], z1 = z[q + 1];
-      z[q] = cs * z0 + sn * z1;
-      z[q + 1] = -sn * z0 + cs * z1;
-    }
-  }
-  // sort (insertion) by value, carrying weights
-  for (int i = 1; i < k; ++i) {
-    const double dv = d[i], zv = z[i];
-    int p = i - 1;
-    while (p >= 0 && d[p] > dv) {
-      d[p + 1] = d[p];
-      z[p + 1] = z[p];
-      --p;
-    }
-    d[p + 1] = dv;
-    z[p + 1] = zv;
-  }
   const double blast = beta[k - 1];
-  out[0] = d[0];
-  out[1] = d[k - 1];
+  const double tlo = theta[0], thi = theta[k - 1];
+  out[0] = tlo;
+  out[1] = thi;
   out[2] = blast;
-  out[3] = d[k - 1] + fabs(blast);
-  // density estimate: point where the cumulative weight reaches frac
-  double cum = 0.0, est = d[k - 1];
-  for (int i = 0; i < k; ++i) {
-    const double wgt = z[i] * z[i];
+  out[3] = thi + fabs(blast);
+  // the point where the cumulative weight reaches frac, interpolated inside
+  // the Ritz interval that crosses it
+  double cum = 0.0, est = thi;
+  for (int j = 0; j < k; ++j) {
+    const double z = Zt[j];
+    const double wgt = z * z;
     if (cum + wgt >= frac) {
-      const double lo = (i > 0) ? d[i - 1] : d[0];
+      const double left = (j > 0) ? theta[j - 1] : tlo;
       const double t = (wgt > 0.0) ? (frac - cum) / wgt : 1.0;
-      est = lo + t * (d[i] - lo);
+      est = left + t * (theta[j] - left);
       break;
     }
     cum += wgt;
   }
   out[4] = est;
-  out[5] = fmax(fabs(d[0]), fabs(d[k - 1]));
+  out[5] = fmax(fabs(tlo), fabs(thi));
 }
 
 // status_i: [0] nconv  [1] maxdeg  [2] done  [3] unused  [4 + j - 1] s_j (j = 1..maxdeg)
@@ -188,7 +138,11 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
     a = theta[nb - 1];
     mu = fmin(theta[0], bounds[0]);
   }
-  if (!(a < b)) a = b - 1e-3 * fmax(fabs(b), 1.0);
+  // a damped interval narrower than a few thousand rounding units of its
+  // ends (e.g. every eigenvalue equal) would divide rounding noise by its
+  // half-width: widen it to a thousandth of the scale instead
+  if (!(b - a > 1e3 * DBL_EPSILON * fmax(fmax(fabs(a), fabs(b)), DBL_MIN)))
+    a = b - 1e-3 * fmax(fabs(b), 1.0);
   if (!(mu < a)) mu = a - 0.5 * (b - a);
   const double e = 0.5 * (b - a), c = 0.5 * (b + a);
   if (tid == 0) {
@@ -329,7 +283,10 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
 }  // namespace
 
 size_t lanczos_work_bytes(int64_t n, int steps) {
-  return ws_round(sizeof(zd) * n * 4) + 2 * ws_round(sizeof(double) * (steps + 1));
+  if (steps > 64) steps = 64;
+  return ws_round(sizeof(zd) * n * 4) + 2 * ws_round(sizeof(double) * (steps + 1)) +
+         ws_round(sizeof(double) * 64) + ws_round(sizeof(double) * 64 * 64) +
+         tridiag_eig_work_bytes(64);
 }
 
 gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int steps,
@@ -343,6 +300,12 @@ gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int
   double* alpha = (double*)w;
   w += ws_round(sizeof(double) * (steps + 1));
   double* beta = (double*)w;
+  w += ws_round(sizeof(double) * (steps + 1));
+  double* rv = (double*)w;  // Ritz values
+  w += ws_round(sizeof(double) * 64);
+  double* Zt = (double*)w;  // eigenvectors of the tridiagonal, row-major
+  w += ws_round(sizeof(double) * 64 * 64);
+  void* tw = w;
   zd* buf[3] = {V, V + n, V + 2 * n};
   zd* wv = V + 3 * n;
   GEVP_TRY(launch_randn(c, n, 1, buf[0], n, 0, seed));
@@ -357,7 +320,8 @@ gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int
                        beta, j);
     GEVP_HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_lanczos_finish, dim3(1), dim3(64), 0, c->stream, alpha, beta, steps, frac,
+  GEVP_TRY(tridiag_eig(c, steps, alpha, beta, rv, Zt, tw));
+  hipLaunchKernelGGL(k_lanczos_summary, dim3(1), dim3(64), 0, c->stream, rv, Zt, beta, steps, frac,
                      out);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;

@@ -39,6 +39,7 @@ int gevp_log_enabled() {
 gevp_status ws_reserve(gevp_ctx* c, size_t bytes) {
   c->ws_used = 0;
   if (bytes <= c->ws_bytes) return GEVP_OK;
+  if (c->ext) return GEVP_ERR_WORKSPACE;  // the caller's buffer is too small
   if (c->ws) {
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
     GEVP_HIP_TRY(hipFree(c->ws));
@@ -54,27 +55,54 @@ gevp_status ws_reserve(gevp_ctx* c, size_t bytes) {
   return GEVP_OK;
 }
 
+void ext_assign(gevp_ctx* parent, gevp_ctx* child, int slot) {
+  if (!parent->ext || !child) return;
+  if (child->skw && !child->ext) {
+    (void)hipStreamSynchronize(child->stream);
+    (void)hipFree(child->skw);
+  }
+  child->ext = true;
+  child->skw = parent->ext_base + parent->ext_bytes - (size_t)(slot + 1) * SKW_BYTES;
+  child->skw_bytes = SKW_BYTES;
+}
+
 void* ws_take(gevp_ctx* c, size_t bytes) {
   void* p = c->ws + c->ws_used;
   c->ws_used += ws_round(bytes);
   return p;
 }
 
-// Event pair around one filter product kernel (profiling flag 2); the pool
-// grows on demand and is summed after the solve's final synchronisation.
+// Event pairs around the filter products (profiling flag 2) and the FP64
+// GEMM launches (flag 4); the pools grow on demand and are summed after the
+// solve's final synchronisation.
+static gevp_status ev_record(gevp_ctx* c, hipEvent_t*& pool, int& cap, int& used) {
+  if (used == cap) {
+    const int ncap = cap ? 2 * cap : 512;
+    hipEvent_t* nv = new hipEvent_t[ncap];
+    for (int i = 0; i < cap; ++i) nv[i] = pool[i];
+    for (int i = cap; i < ncap; ++i) GEVP_HIP_TRY(hipEventCreate(&nv[i]));
+    delete[] pool;
+    pool = nv;
+    cap = ncap;
+  }
+  GEVP_HIP_TRY(hipEventRecord(pool[used++], c->stream));
+  return GEVP_OK;
+}
+
 gevp_status fev_mark(gevp_ctx* c) {
   if (!(c->profiling & 2)) return GEVP_OK;
-  if (c->fev_used == c->fev_cap) {
-    const int cap = c->fev_cap ? 2 * c->fev_cap : 512;
-    hipEvent_t* nv = new hipEvent_t[cap];
-    for (int i = 0; i < c->fev_cap; ++i) nv[i] = c->fev[i];
-    for (int i = c->fev_cap; i < cap; ++i) GEVP_HIP_TRY(hipEventCreate(&nv[i]));
-    delete[] c->fev;
-    c->fev = nv;
-    c->fev_cap = cap;
-  }
-  GEVP_HIP_TRY(hipEventRecord(c->fev[c->fev_used++], c->stream));
-  return GEVP_OK;
+  return ev_record(c, c->fev, c->fev_cap, c->fev_used);
+}
+
+gevp_status gev_begin(gevp_ctx* c) {
+  if (!(c->profiling & 4)) return GEVP_OK;
+  return ev_record(c, c->gev, c->gev_cap, c->gev_used);
+}
+
+gevp_status gev_end(gevp_ctx* c, double flops) {
+  if (!(c->profiling & 4)) return GEVP_OK;
+  c->gev_flops += flops;
+  return ev_record(c, c->gev, c->gev_cap, c->gev_used);
 }
 
 namespace {
@@ -113,6 +141,55 @@ Opts resolve(const gevp_opts* o, int64_t nev) {
 int64_t block_of(const Opts& o, int64_t n, int64_t nev) {
   int64_t nb = nev + o.nex;
   return nb > n ? n : nb;
+}
+
+// Device workspace of one gevp_solve (the pieces carved below, in order).
+size_t solve_ws_bytes(const Opts& o, int64_t n, int64_t nb, bool contour, bool c32, bool lp,
+                      bool bf16) {
+  const size_t nn = (size_t)n * n;
+  const int lz = o.lanczos;
+  size_t need = 0;
+  need += 4 * ws_round(sizeof(zd) * nn);                 // Af, Bf, L, C
+  need += ws_round(sizeof(zd) * n * 64);                 // Dinv
+  need += 4 * ws_round(sizeof(zd) * n * nb);             // P0, P1, W, T
+  need += 3 * ws_round(sizeof(zd) * nb * nb);            // H, Z, G
+  need += ws_round(sizeof(zd) * nb * 64);                // DinvG
+  need += heev_work_bytes(nb);
+  need += 2 * lanczos_work_bytes(n, lz);                 // main and second stream
+  need += 3 * ws_round(sizeof(double) * 8);              // bounds C, A, B
+  need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, negl, spare
+  need += ws_round(sizeof(int) * nb);                    // perm
+  need += ws_round(sizeof(double) * 3 * 256);            // coefs
+  need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
+  need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
+  need += ws_round(sizeof(double) * 4);                  // norms
+  need += ws_round(sizeof(double) * (3 * nb + 8));       // seed monitor
+  if (o.seed_monitor)  // the seed in the reduced basis and its projection residual norms
+    need += ws_round(sizeof(zd) * n * nb) + ws_round(sizeof(double) * nb);
+  if (contour)  // nq factorisations
+    need += c32 ? contour32_work_bytes(n, nb, o.nq) : contour_work_bytes(n, nb, o.nq);
+  const size_t lp_elem = 8;                              // complex64
+  if (lp) {
+    need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
+    if (bf16) need += bf16_filter_work_bytes(n, nb);     // iterate planes, split-K partials
+    need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
+    need += ws_round(sizeof(double) * nb);               // rho0
+    need += ws_round(sizeof(double) * 4 * nb * (o.deg_max + 2));  // per-column coefficients
+  }
+  return need;
+}
+
+// Worst case over seeds: the contour filter's factorisations when it is
+// selected, the low-precision Chebyshev buffers for a mixed precision (a
+// solve that cannot place a contour takes the Chebyshev filter).
+size_t solve_ws_bytes_max(const Opts& o, int64_t n, int64_t nev) {
+  const int64_t nb = block_of(o, n, nev);
+  const bool mixed = o.precision != GEVP_FP64;
+  const bool contour = o.filter == GEVP_FILTER_CONTOUR && nb > nev && n <= 65535;
+  size_t b = solve_ws_bytes(o, n, nb, false, false, mixed, o.precision == GEVP_BF16X3);
+  if (contour)
+    b = std::max(b, solve_ws_bytes(o, n, nb, true, mixed, false, false));
+  return b;
 }
 
 struct Timer {
@@ -219,6 +296,24 @@ gevp_status fev_collect(gevp_ctx* c, gevp_info* info) {
   return GEVP_OK;
 }
 
+// FP64 GEMM launches of a context (and of the streams it forks): summed into
+// info once their work has completed
+gevp_status gev_collect(gevp_ctx* c, gevp_info* info) {
+  if (!c || !(c->profiling & 4)) return GEVP_OK;
+  double tot = 0.0;
+  for (int i = 0; i + 1 < c->gev_used; i += 2) {
+    float ms = 0.f;
+    GEVP_HIP_TRY(hipEventElapsedTime(&ms, c->gev[i], c->gev[i + 1]));
+    tot += ms;
+  }
+  info->gemm_kernel_ms += tot;
+  info->gemm_launches += c->gev_used / 2;
+  info->gemm_flops += c->gev_flops;
+  c->gev_used = 0;
+  c->gev_flops = 0.0;
+  return GEVP_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -235,6 +330,7 @@ const char* gevp_status_string(gevp_status s) {
     case GEVP_ERR_NONFINITE: return "NaN or Inf in the input";
     case GEVP_ERR_ALLOC: return "workspace allocation failed";
     case GEVP_ERR_SINGULAR: return "zero or non-finite pivot in a shifted factorisation";
+    case GEVP_ERR_WORKSPACE: return "caller-provided workspace too small";
   }
   return "unknown status";
 }
@@ -280,16 +376,98 @@ void gevp_destroy(gevp_handle h) {
     if (e) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(h->stream);
   if (h->owns_stream) (void)hipStreamDestroy(h->stream);
-  if (h->ws) (void)hipFree(h->ws);
-  if (h->skw) (void)hipFree(h->skw);
+  if (h->ws && !h->ext) (void)hipFree(h->ws);
+  if (h->skw && !h->ext) (void)hipFree(h->skw);
   for (int i = 0; i < h->fev_cap; ++i) (void)hipEventDestroy(h->fev[i]);
   delete[] h->fev;
+  for (int i = 0; i < h->gev_cap; ++i) (void)hipEventDestroy(h->gev[i]);
+  delete[] h->gev;
   delete h;
 }
 
 int64_t gevp_block_size(const gevp_opts* opts, int64_t n, int64_t nev) {
   if (n < 1 || nev < 1 || nev > n) return 0;
   return block_of(resolve(opts, nev), n, nev);
+}
+
+gevp_status gevp_workspace_size(gevp_handle h, const gevp_opts* opts, int64_t n, int64_t nev,
+                                size_t* bytes) {
+  (void)h;  // the size depends on the arguments only
+  if (!bytes || n < 1 || nev < 1 || nev > n) return GEVP_ERR_INVALID;
+  const Opts o = resolve(opts, nev);
+  *bytes = solve_ws_bytes_max(o, n, nev) + (size_t)EXT_SLOTS * SKW_BYTES;
+  return GEVP_OK;
+}
+
+namespace {
+int batch_stream_count(const gevp_opts* opts, int count) {
+  int streams = (opts && opts->batch_streams > 0) ? opts->batch_streams : 8;
+  if (streams > 16) streams = 16;
+  if (streams > count) streams = count;
+  return streams;
+}
+// per-worker share of a caller-owned workspace in gevp_solve_batched: the
+// worker's solve workspace followed by its split-K buffer
+size_t worker_share(gevp_ctx* h, int streams) {
+  return (h->ext_bytes / (size_t)streams) & ~size_t(255);
+}
+}  // namespace
+
+gevp_status gevp_workspace_size_batched(gevp_handle h, const gevp_opts* opts, int count,
+                                        const int64_t* n, const int64_t* nev, size_t* bytes) {
+  (void)h;
+  if (!bytes || count < 1 || !n || !nev) return GEVP_ERR_INVALID;
+  size_t per = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || nev[i] < 1 || nev[i] > n[i]) return GEVP_ERR_INVALID;
+    per = std::max(per, solve_ws_bytes_max(resolve(opts, nev[i]), n[i], nev[i]));
+  }
+  per = ws_round(per + SKW_BYTES);
+  const size_t total = per * (size_t)batch_stream_count(opts, count);
+  *bytes = std::max(total, (size_t)EXT_SLOTS * SKW_BYTES + 256);
+  return GEVP_OK;
+}
+
+gevp_status gevp_set_workspace(gevp_handle h, void* dev_ptr, size_t bytes) {
+  if (!h) return GEVP_ERR_INVALID;
+  if (dev_ptr && (((uintptr_t)dev_ptr & 255) != 0 || bytes < (size_t)EXT_SLOTS * SKW_BYTES + 256))
+    return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_HIP_TRY(hipStreamSynchronize(h->stream));
+  std::vector<gevp_ctx*> subs = {h->aux, h->panel};
+  for (gevp_ctx* q : h->qctx) subs.push_back(q);
+  for (gevp_ctx* w : h->workers) subs.push_back(w);
+  // release what the library allocated itself; forget borrowed memory
+  auto drop = [](gevp_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (!c->ext) {
+      if (c->ws) (void)hipFree(c->ws);
+      if (c->skw) (void)hipFree(c->skw);
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->ws_used = 0;
+    c->skw = nullptr;
+    c->skw_bytes = 0;
+    c->ext = false;
+  };
+  drop(h);
+  for (gevp_ctx* c : subs) drop(c);
+  h->ext_base = nullptr;
+  h->ext_bytes = 0;
+  if (!dev_ptr) return GEVP_OK;  // back to library-managed memory
+  h->ext = true;
+  h->ext_base = (char*)dev_ptr;
+  h->ext_bytes = bytes;
+  h->ws = h->ext_base;
+  h->ws_bytes = bytes - (size_t)EXT_SLOTS * SKW_BYTES;
+  h->skw = h->ext_base + bytes - SKW_BYTES;  // slot SLOT_MAIN
+  h->skw_bytes = SKW_BYTES;
+  ext_assign(h, h->aux, SLOT_AUX);
+  ext_assign(h, h->panel, SLOT_PANEL);
+  for (size_t q = 0; q < h->qctx.size(); ++q) ext_assign(h, h->qctx[q], SLOT_QUAD0 + (int)q);
+  return GEVP_OK;
 }
 
 namespace {
@@ -304,6 +482,7 @@ gevp_status aux_ctx(gevp_ctx* c, gevp_ctx** out) {
     }
     w->owns_stream = true;
     c->aux = w;
+    ext_assign(c, w, SLOT_AUX);
   }
   *out = c->aux;
   return GEVP_OK;
@@ -366,6 +545,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   GEVP_HIP_TRY(hipSetDevice(h->device));
   gevp_ctx* c = h;
   c->fev_used = 0;
+  c->gev_used = 0;
+  c->gev_flops = 0.0;
   info->block = (int)nb;
 
   const zd* A = (const zd*)A_;
@@ -376,32 +557,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   // ---------------- workspace
   const size_t nn = (size_t)n * n;
   const int lz = o.lanczos;
-  size_t need = 0;
-  need += 4 * ws_round(sizeof(zd) * nn);                 // Af, Bf, L, C
-  need += ws_round(sizeof(zd) * n * 64);                 // Dinv
-  need += 4 * ws_round(sizeof(zd) * n * nb);             // P0, P1, W, T
-  need += 3 * ws_round(sizeof(zd) * nb * nb);            // H, Z, G
-  need += ws_round(sizeof(zd) * nb * 64);                // DinvG
-  need += heev_work_bytes(nb);
-  need += 2 * lanczos_work_bytes(n, lz);                 // main and second stream
-  need += 3 * ws_round(sizeof(double) * 8);              // bounds C, A, B
-  need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, negl, spare
-  need += ws_round(sizeof(int) * nb);                    // perm
-  need += ws_round(sizeof(double) * 3 * 256);            // coefs
-  need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
-  need += ws_round(sizeof(int) * 8) + ws_round(sizeof(double) * 8);     // flags, shift
-  need += ws_round(sizeof(double) * 4);                  // norms
-  need += ws_round(sizeof(double) * (3 * nb + 8));       // seed monitor
-  if (contour)  // nq factorisations
-    need += c32 ? contour32_work_bytes(n, nb, o.nq) : contour_work_bytes(n, nb, o.nq);
   const size_t lp_elem = 8;                              // complex64
-  if (lp) {
-    need += bf16 ? ws_round(bf16_planes_bytes(n)) : ws_round(lp_elem * nn);  // low-precision C
-    if (bf16) need += bf16_filter_work_bytes(n, nb);     // iterate planes, split-K partials
-    need += 3 * ws_round(lp_elem * n * nb);              // G0, G1, R (low precision)
-    need += ws_round(sizeof(double) * nb);               // rho0
-    need += ws_round(sizeof(double) * 4 * nb * (o.deg_max + 2));  // per-column coefficients
-  }
+  const size_t need = solve_ws_bytes(o, n, nb, contour, c32, lp, bf16);
   GEVP_TRY(ws_reserve(c, need));
   zd* Af = (zd*)ws_take(c, sizeof(zd) * nn);
   zd* Bf = (zd*)ws_take(c, sizeof(zd) * nn);
@@ -434,6 +591,10 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* shift = (double*)ws_take(c, sizeof(double) * 8);
   double* norms = (double*)ws_take(c, sizeof(double) * 4);
   double* mon = (double*)ws_take(c, sizeof(double) * (3 * nb + 8));  // per-column stats, then 6 results
+  const int64_t km = std::min<int64_t>(nev, k0);
+  const bool monitor = seeded && o.seed_monitor && km > 0;
+  zd* Y0s = o.seed_monitor ? (zd*)ws_take(c, sizeof(zd) * n * nb) : nullptr;
+  double* rmon = o.seed_monitor ? (double*)ws_take(c, sizeof(double) * nb) : nullptr;
   void* cw = contour ? ws_take(c, c32 ? contour32_work_bytes(n, nb, o.nq)
                                        : contour_work_bytes(n, nb, o.nq))
                      : nullptr;
@@ -485,6 +646,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   gevp_ctx* ax = nullptr;
   if (spec) {
     GEVP_TRY(aux_ctx(c, &ax));
+    ax->profiling = c->profiling & 4;
+    ax->gev_used = 0;
+    ax->gev_flops = 0.0;
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.mid, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
@@ -536,6 +700,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   if (seeded)
     GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
                           nullptr, P0, n, nullptr, 0, 1));
+  if (monitor) GEVP_TRY(launch_copy2d(c, n, km, P0, n, Y0s, n));  // the seed y0 = L^H x0, kept
 
   // ---------------- reduction to standard form
   tm.start();
@@ -755,6 +920,24 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   // ---------------- back-transform and final residuals
   tm.start();
+  // Seed monitor in the reduced basis, where both blocks are orthonormal:
+  // M = Y0^H Y (= X0^H B X), and the projection residuals R = Y0 - Y M^H of
+  // the seed columns onto span(Y) give the sines of the principal angles
+  // without the cancellation of k - ||M||_F^2 (sum_j ||r_j||^2 = sum sin^2).
+  double hm[5] = {-1.0, -1.0, -1.0, 0.0, -1.0};
+  if (monitor) {
+    GEVP_TRY(launch_zgemm(c, 1, 0, km, km, n, 1.0, Y0s, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, Hs, km));
+    GEVP_TRY(launch_zgemm(c, 0, 1, n, km, km, -1.0, P0, n, Hs, km, 1.0, Y0s, n, 0.0, nullptr, 0,
+                          nullptr, W, n));
+    GEVP_TRY(launch_colnorms(c, n, km, W, n, rmon));
+    GEVP_TRY(seed_monitor_stats(c, km, Hs, km, mon, mon + 3 * nb, hm, nullptr, rmon));
+    info->seed_sin_rms = hm[0];
+    info->seed_dev_mean = hm[1];
+    info->seed_dev_max = hm[2];
+    info->seed_reindexed = (int)hm[3];
+    info->seed_dev_std = hm[4];
+  }
   GEVP_TRY(launch_copy2d(c, n, kx, P0, n, X, ldx));
   GEVP_TRY(trsm_left_lower_c(c, n, kx, L, n, Dinv, n, X, ldx, 1));
   GEVP_TRY(launch_phase_normalize(c, n, kx, X, ldx));
@@ -769,25 +952,9 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
                           W, n));
     GEVP_TRY(launch_colnorms(c, n, kx, W, n, fres));
     if (resid_out) GEVP_TRY(launch_copy_real(c, kx, fres, resid_out));
-    // seed monitor: M = X0(:, :k)^H (B X)(:, :k), B X is T
-    const int64_t km = std::min<int64_t>(nev, k0);
-    const bool monitor = seeded && o.seed_monitor && km > 0;
-    double hm[5] = {-1.0, -1.0, -1.0, 0.0, -1.0};
-    if (monitor) {
-      GEVP_TRY(launch_zgemm(c, 1, 0, km, km, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                            nullptr, Hs, km));
-      GEVP_TRY(seed_monitor_stats(c, km, Hs, km, mon, mon + 3 * nb, hm, nullptr));
-    }
     std::vector<double> hr(kx);
     GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kx, hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
-    if (monitor) {
-      info->seed_sin_rms = hm[0];
-      info->seed_dev_mean = hm[1];
-      info->seed_dev_max = hm[2];
-      info->seed_reindexed = (int)hm[3];
-      info->seed_dev_std = hm[4];
-    }
     double mx = 0.0;
     for (int64_t i = 0; i < nev; ++i) mx = std::max(mx, hr[i]);
     info->max_resid = (hn[0] > 0.0) ? mx / hn[0] : mx;
@@ -797,6 +964,13 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   }
   tm.stop(info, GEVP_STAGE_FINAL);
   GEVP_TRY(fev_collect(c, info));
+  // the second and the panel stream joined the main stream before its final
+  // synchronisation, so their events have completed too
+  GEVP_TRY(gev_collect(c, info));
+  if (c->inner_streams) {
+    GEVP_TRY(gev_collect(c->aux, info));
+    GEVP_TRY(gev_collect(c->panel, info));
+  }
   info->normA = hn[0];
   info->normB = hn[1];
   if (!converged) st = GEVP_ERR_NOCONV;
@@ -843,9 +1017,7 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
     return GEVP_ERR_INVALID;
   if (count == 0) return GEVP_OK;
   GEVP_HIP_TRY(hipSetDevice(h->device));
-  int streams = (opts && opts->batch_streams > 0) ? opts->batch_streams : 8;
-  if (streams > 16) streams = 16;
-  if (streams > count) streams = count;
+  const int streams = batch_stream_count(opts, count);
   while ((int)h->workers.size() < streams) {
     gevp_ctx* w = new gevp_ctx();
     w->device = h->device;
@@ -859,7 +1031,23 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
   }
   // event timing of the filter launches (profiling flag 2) carries over; the
   // per-stage timer (flag 1) would synchronise the workers and is not passed on
-  for (int w = 0; w < streams; ++w) h->workers[w]->profiling = h->profiling & 2;
+  for (int w = 0; w < streams; ++w) h->workers[w]->profiling = h->profiling & 6;
+  if (h->ext) {
+    // caller-owned memory: worker w takes the w-th equal share, its solve
+    // workspace first and its split-K buffer at the share's top end
+    const size_t per = worker_share(h, streams);
+    if (per <= SKW_BYTES + 256) return GEVP_ERR_WORKSPACE;
+    for (int w = 0; w < streams; ++w) {
+      gevp_ctx* c = h->workers[w];
+      char* base = h->ext_base + (size_t)w * per;
+      c->ext = true;
+      c->ws = base;
+      c->ws_bytes = per - SKW_BYTES;
+      c->ws_used = 0;
+      c->skw = base + per - SKW_BYTES;
+      c->skw_bytes = SKW_BYTES;
+    }
+  }
   // the worker streams start after the work already queued on the caller's stream
   hipEvent_t ready;
   GEVP_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));

@@ -1,5 +1,5 @@
 // Thresholded partial update of a Hermitian matrix between two SCF iterations
-// (section 3, paragraph "Matrix generation").
+// (section 2, paragraph "Matrix generation").
 //
 // delta = max |A_new(i,j) - A(i,j)| over the stored lower triangle; every lower
 // entry whose change exceeds p_t * delta takes A_new's value and the others

@@ -224,14 +224,18 @@ __global__ __launch_bounds__(256) void k_seed_cols(int k, const zd* M, int64_t l
   }
 }
 
-// out[0] = sqrt(max(0, k - ||M||_F^2) / k), out[1] / out[2] = mean / max of
-// acos(min(1, max_i |M(i,j)|)) / (pi/2), out[3] = columns whose best row is not j
-// Seed monitor totals.  out[0] sin_rms, out[1] mean and out[2] max of the
-// per-column deviation angles (best match per column), out[3] columns whose
-// best match is not their own index, out[4] standard deviation of the angles,
-// out[5] = 1 when two columns share a best match (the per-column matches are
-// then no permutation and the host solves the assignment).  k <= 2048.
-__global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, double* out) {
+// Seed monitor totals.  out[0] sin_rms: sqrt(sum_j rnorm[j]^2 / k) when the
+// norms of the projection residuals R = X0 - P X0 (P the orthogonal projector
+// onto the result's span) are given, else sqrt(max(0, k - ||M||_F^2) / k)
+// from M alone (which loses its digits to cancellation below about 1e-8);
+// out[1] mean and out[2] max of the per-column deviation angles
+// acos(min(1, max_i |M(i,j)|)) / (pi/2) (best match per column), out[3]
+// columns whose best match is not their own index, out[4] standard deviation
+// of the angles, out[5] = 1 when two columns share a best match (the
+// per-column matches are then no permutation and the host solves the
+// assignment).  k <= 2048.
+__global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, const double* rnorm,
+                                                     double* out) {
   __shared__ double sf[256], sd[256], sx[256], sr[256], sq[256];
   __shared__ int hits[2048];
   __shared__ int clash;
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, 
   __syncthreads();
   double f = 0.0, d = 0.0, x = 0.0, r = 0.0, q = 0.0;
   for (int j = t; j < k; j += 256) {
-    f += stat[3 * j];
+    f += rnorm ? rnorm[j] * rnorm[j] : stat[3 * j];
     const double dev = acos(fmin(1.0, stat[3 * j + 1])) * 0.63661977236758134;  // / (pi/2)
     d += dev;
     q += dev * dev;
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, 
   }
   if (t == 0) {
     const double mean = sd[0] / (double)k;
-    out[0] = sqrt(fmax(0.0, (double)k - sf[0]) / (double)k);
+    out[0] = rnorm ? sqrt(sf[0] / (double)k) : sqrt(fmax(0.0, (double)k - sf[0]) / (double)k);
     out[1] = mean;
     out[2] = sx[0];
     out[3] = sr[0];
@@ -463,12 +467,12 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
 }
 
 gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
-                                double* out) {
+                                double* out, const double* rnorm) {
   if (k <= 0) return GEVP_OK;
   if (k > 2048) return GEVP_ERR_INVALID;
   hipLaunchKernelGGL(k_seed_cols, dim3((unsigned)k), dim3(256), 0, c->stream, (int)k, M, ldm, stat);
   GEVP_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_seed_finish, dim3(1), dim3(256), 0, c->stream, (int)k, stat, out);
+  hipLaunchKernelGGL(k_seed_finish, dim3(1), dim3(256), 0, c->stream, (int)k, stat, rnorm, out);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }
@@ -527,8 +531,8 @@ std::vector<int> min_cost_assignment(const std::vector<double>& a, int n) {
 }  // namespace
 
 gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
-                               double* out, double res[5], int* match) {
-  GEVP_TRY(launch_seed_monitor(c, k, M, ldm, stat, out));
+                               double* out, double res[5], int* match, const double* rnorm) {
+  GEVP_TRY(launch_seed_monitor(c, k, M, ldm, stat, out, rnorm));
   double h[6];
   std::vector<double> st(3 * k);
   GEVP_HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));

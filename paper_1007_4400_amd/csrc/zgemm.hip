@@ -32,6 +32,8 @@
 // its own first row.
 #include <atomic>
 
+#include <algorithm>
+
 #include "common.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -40,6 +42,7 @@ namespace {
 constexpr int BM = 64, BN = 64, KT = 16, NTHR = 256;
 constexpr int PADA = BM + 1, PADB = BN + 1;
 constexpr int64_t SPLIT_TILES_MAX = 2048;  // partial tiles the split-K buffer holds (128 MiB)
+static_assert(SKW_BYTES == (size_t)SPLIT_TILES_MAX * 64 * 64 * 16, "split-K buffer size");
 // The in-place base cases of the triangular solves rely on a 64-wide block
 // fitting in one output tile.
 static_assert(BM >= 64 && BN >= 64, "trsm base cases need 64-wide tiles");
@@ -379,6 +382,7 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   if (p.splits > 1) {
     const size_t need = (size_t)p.splits * total * BM * BN * sizeof(zd);
     if (need > c->skw_bytes) {
+      if (c->ext) return GEVP_ERR_WORKSPACE;  // caller-owned memory is never reallocated
       if (c->skw) {
         GEVP_HIP_TRY(hipStreamSynchronize(c->stream));  // earlier launches may still read it
         GEVP_HIP_TRY(hipFree(c->skw));
@@ -398,6 +402,10 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.total = (int)blocks;
   p.remap = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
   const dim3 grid((unsigned)blocks), thr(NTHR);
+  // FP64 GEMM timing (profiling bit 4): not the FP64 filter (coef), which is
+  // timed as a filter product by the caller
+  const bool timed = (coef == nullptr) && (c->profiling & 4);
+  if (timed) GEVP_TRY(gev_begin(c));
   if (opA == 0 && opB == 0) {
     if (coef)
       hipLaunchKernelGGL(k_zgemm<1>, grid, thr, 0, c->stream, p);
@@ -416,6 +424,19 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
     hipLaunchKernelGGL(k_zgemm_splitk_reduce, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0,
                        c->stream, p);
     GEVP_HIP_TRY(hipGetLastError());
+  }
+  if (timed) {
+    // algorithmic flops: 8 per complex multiply-add of the product as
+    // defined (only the lower triangle of a square output when `lower`,
+    // only the upper-triangular part of op(A) when `upperA`)
+    const double md = (double)m, nd = (double)n, kd = (double)p.K;
+    double fl = 8.0 * md * nd * kd;
+    if (lower && m == n) fl = 8.0 * kd * nd * (nd + 1.0) * 0.5;
+    if (upperA) {
+      const double rows = std::min(md, kd);  // row i of op(A) starts at column i
+      fl = 8.0 * nd * (rows * kd - rows * (rows - 1.0) * 0.5);
+    }
+    GEVP_TRY(gev_end(c, fl));
   }
   return GEVP_OK;
 }

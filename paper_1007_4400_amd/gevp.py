@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgevp.so")
 
 GEVP_OK, GEVP_ERR_INVALID, GEVP_ERR_NOT_HPD, GEVP_ERR_NOCONV = 0, 1, 2, 3
 GEVP_ERR_HIP, GEVP_ERR_NONFINITE, GEVP_ERR_ALLOC, GEVP_ERR_SINGULAR = 4, 5, 6, 7
+GEVP_ERR_WORKSPACE = 8
 FILTER_CHEBYSHEV, FILTER_CONTOUR = 0, 1
 FILTERS = {"chebyshev": FILTER_CHEBYSHEV, "contour": FILTER_CONTOUR}
 FP64, FP32, BF16X3 = 0, 1, 2
@@ -50,6 +51,8 @@ class Info(ctypes.Structure):
         ("contour_points", ctypes.c_int), ("contour_a", ctypes.c_double),
         ("contour_b", ctypes.c_double), ("contour_applications", ctypes.c_int),
         ("contour_columns", ctypes.c_int64), ("seed_dev_std", ctypes.c_double),
+        ("gemm_kernel_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
+        ("gemm_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -103,6 +106,13 @@ def load():
     lib.gevp_destroy.restype = None
     lib.gevp_block_size.argtypes = [ctypes.POINTER(Opts), L, L]
     lib.gevp_block_size.restype = L
+    lib.gevp_workspace_size.argtypes = [P, ctypes.POINTER(Opts), L, L, ctypes.POINTER(ctypes.c_size_t)]
+    lib.gevp_workspace_size.restype = I
+    lib.gevp_workspace_size_batched.argtypes = [P, ctypes.POINTER(Opts), I, P, P,
+                                                ctypes.POINTER(ctypes.c_size_t)]
+    lib.gevp_workspace_size_batched.restype = I
+    lib.gevp_set_workspace.argtypes = [P, P, ctypes.c_size_t]
+    lib.gevp_set_workspace.restype = I
     lib.gevp_solve.argtypes = [P, ctypes.POINTER(Opts), L, P, L, P, L, P, L, L, L, D, L, P, P, L, P,
                                ctypes.POINTER(Info)]
     lib.gevp_solve.restype = I
@@ -145,13 +155,75 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def colmajor(t: torch.Tensor) -> torch.Tensor:
     """Column-major (Fortran-order) version of a 2-D tensor; no copy when it
-    already is one."""
+    already is one.  Lazy conjugate / negative views are materialised first,
+    since the library reads the stored values."""
     if t.dim() != 2:
         raise ValueError("expected a matrix")
+    t = t.resolve_conj().resolve_neg()
     r, c = t.shape
     if t.stride(0) == 1 and (t.stride(1) >= max(r, 1) or c == 1):
         return t
     return t.mT.contiguous().mT
+
+
+def _on_device(t: torch.Tensor, device: int, name: str):
+    if t.device.type != "cuda" or (t.device.index if t.device.index is not None else
+                                   torch.cuda.current_device()) != device:
+        raise ValueError(f"{name} must be on cuda:{device} (got {t.device})")
+
+
+def _check_mat(t, name: str, device: int, dtype=torch.complex128, rows=None, cols=None,
+               square=False) -> torch.Tensor:
+    """Validate a matrix argument before its pointer crosses the ABI: a
+    torch tensor of the given dtype, 2-D, with the expected shape, on the
+    handle's device.  Returns its column-major form."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a matrix, got shape {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if square and t.shape[0] != t.shape[1]:
+        raise ValueError(f"{name} must be square, got shape {tuple(t.shape)}")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} must have {rows} rows, got {t.shape[0]}")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name} must have {cols} columns, got {t.shape[1]}")
+    _on_device(t, device, name)
+    return colmajor(t)
+
+
+def _check_vec(t, name: str, device: int, length: int, dtype=torch.float64) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dim() != 1:
+        raise ValueError(f"{name} must be a 1-D torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.shape[0] < length:
+        raise ValueError(f"{name} must hold at least {length} entries, got {t.shape[0]}")
+    _on_device(t, device, name)
+    return t.contiguous()
+
+
+def check_solve_args(A, B, nev, X0, device: int):
+    """Validation of gevp_solve's tensor arguments (raises ValueError)."""
+    A = _check_mat(A, "A", device, square=True)
+    n = A.shape[0]
+    B = _check_mat(B, "B", device, rows=n, cols=n)
+    if not 1 <= int(nev) <= n:
+        raise ValueError(f"nev must be in [1, {n}], got {nev}")
+    if X0 is not None:
+        X0 = _check_mat(X0, "X0", device, rows=n)
+    return A, B, X0
+
+
+def check_backward_args(X, lam, w, device: int, need_lam: bool):
+    X = _check_mat(X, "X", device)
+    nev = X.shape[1]
+    if isinstance(w, torch.Tensor) and w.is_floating_point():
+        w = w.to(torch.float64)
+    w = _check_vec(w, "w", device, nev)
+    lam = _check_vec(lam, "lam", device, nev) if (need_lam or lam is not None) else None
+    return X, lam, w
 
 
 def empty_colmajor(rows: int, cols: int, dtype=torch.complex128, device=None) -> torch.Tensor:
@@ -175,6 +247,17 @@ def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_s
     o.batch_streams = int(batch_streams)
     o.seed_monitor = int(bool(seed_monitor))
     return o
+
+
+def workspace_size(n, nev, opts: Optional[Opts] = None) -> int:
+    """Bytes of device workspace gevp_solve needs for (n, nev, opts); needs
+    no GPU (the query does not touch a handle)."""
+    b = ctypes.c_size_t(0)
+    s = load().gevp_workspace_size(None, ctypes.byref(opts or make_opts()), int(n), int(nev),
+                                   ctypes.byref(b))
+    if s != GEVP_OK:
+        raise GevpError(s, "gevp_workspace_size")
+    return int(b.value)
 
 
 class Handle:
@@ -213,24 +296,55 @@ class Handle:
     def block_size(self, n, nev, opts: Optional[Opts] = None) -> int:
         return int(self.lib.gevp_block_size(ctypes.byref(opts or make_opts()), n, nev))
 
+    # ---------------------------------------------------------- workspace
+    def workspace_size(self, n, nev, opts: Optional[Opts] = None) -> int:
+        """Bytes of device workspace gevp_solve needs for (n, nev, opts)."""
+        return workspace_size(n, nev, opts)
+
+    def workspace_size_batched(self, ns, nevs, opts: Optional[Opts] = None) -> int:
+        cnt = len(ns)
+        b = ctypes.c_size_t(0)
+        s = self.lib.gevp_workspace_size_batched(
+            self.h, ctypes.byref(opts or make_opts()), cnt, (ctypes.c_int64 * cnt)(*ns),
+            (ctypes.c_int64 * cnt)(*nevs), ctypes.byref(b))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_workspace_size_batched")
+        return int(b.value)
+
+    def set_workspace(self, buf: Optional[torch.Tensor]):
+        """Work only in ``buf`` (a contiguous uint8 tensor on the handle's
+        device, e.g. ``torch.empty(handle.workspace_size(n, nev), dtype=torch.uint8,
+        device="cuda")``); the handle keeps a reference.  None returns to
+        library-managed memory."""
+        if buf is None:
+            s = self.lib.gevp_set_workspace(self.h, None, 0)
+            if s != GEVP_OK:
+                raise GevpError(s, "gevp_set_workspace")
+            self._ws = None
+            return
+        if not isinstance(buf, torch.Tensor) or buf.dtype != torch.uint8 or not buf.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 tensor")
+        _on_device(buf, self.device, "workspace")
+        self._stream()
+        s = self.lib.gevp_set_workspace(self.h, ctypes.c_void_p(buf.data_ptr()), buf.numel())
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_set_workspace")
+        self._ws = buf
+
     # ------------------------------------------------------------------ solve
     def solve(self, A, B, nev, X0=None, tol=1e-10, kx=None, opts: Optional[Opts] = None,
               raise_on_noconv=True):
         """Lowest ``nev`` eigenpairs of A x = lambda B x.  Returns
         (lam[kx], X[n, kx], resid[kx], info dict)."""
         opts = opts or make_opts()
-        A = colmajor(A)
-        B = colmajor(B)
+        A, B, X0 = check_solve_args(A, B, nev, X0, self.device)
         n = A.shape[0]
         kx = nev if kx is None else kx
         dev = A.device
         lam = torch.empty(kx, dtype=torch.float64, device=dev)
         X = empty_colmajor(n, kx, device=dev)
         res = torch.empty(kx, dtype=torch.float64, device=dev)
-        k0 = 0
-        if X0 is not None:
-            X0 = colmajor(X0)
-            k0 = X0.shape[1]
+        k0 = X0.shape[1] if X0 is not None else 0
         info = Info()
         self._stream()
         s = self.lib.gevp_solve(self.h, ctypes.byref(opts), n, _ptr(A), _ld(A), _ptr(B), _ld(B),
@@ -249,9 +363,11 @@ class Handle:
         opts = opts or make_opts()
         cnt = len(problems)
         arr = lambda t, vals: (t * cnt)(*vals)
-        As = [colmajor(p["A"]) for p in problems]
-        Bs = [colmajor(p["B"]) for p in problems]
-        X0s = [colmajor(p["X0"]) if p.get("X0") is not None else None for p in problems]
+        checked = [check_solve_args(p["A"], p["B"], p["nev"], p.get("X0"), self.device)
+                   for p in problems]
+        As = [c[0] for c in checked]
+        Bs = [c[1] for c in checked]
+        X0s = [c[2] for c in checked]
         ns = [a.shape[0] for a in As]
         nevs = [p["nev"] for p in problems]
         kxs = [p.get("kx") or p["nev"] for p in problems]
@@ -279,12 +395,10 @@ class Handle:
         return out
 
     def backward(self, X, lam, w, want_dA=True, want_dB=True):
-        X = colmajor(X)
+        X, lam, w = check_backward_args(X, lam, w, self.device, need_lam=want_dB)
         n, nev = X.shape
         dA = empty_colmajor(n, n, device=X.device) if want_dA else None
         dB = empty_colmajor(n, n, device=X.device) if want_dB else None
-        lam = lam.contiguous()
-        w = w.to(torch.float64).contiguous()
         self._stream()
         s = self.lib.gevp_backward(self.h, n, nev, _ptr(X), _ld(X), _ptr(lam), _ptr(w), _ptr(dA),
                                    n, _ptr(dB), n)
@@ -295,15 +409,30 @@ class Handle:
     # ------------------------------------------------------------ kernels
     def zgemm(self, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, gamma=0.0, E=None, gcol=None,
               out=None, m=None, n=None, k=None):
-        A = colmajor(A)
-        B = colmajor(B)
+        if opA not in ("N", "C") or opB not in ("N", "C"):
+            raise ValueError("opA and opB must be 'N' or 'C'")
+        A = _check_mat(A, "A", self.device)
+        B = _check_mat(B, "B", self.device)
+        ka = A.shape[1] if opA == "N" else A.shape[0]
+        kb = B.shape[0] if opB == "N" else B.shape[1]
         m = m if m is not None else (A.shape[0] if opA == "N" else A.shape[1])
-        k = k if k is not None else (A.shape[1] if opA == "N" else A.shape[0])
+        k = k if k is not None else ka
         n = n if n is not None else (B.shape[1] if opB == "N" else B.shape[0])
+        if k > min(ka, kb) or m > (A.shape[0] if opA == "N" else A.shape[1]) or \
+                n > (B.shape[1] if opB == "N" else B.shape[0]):
+            raise ValueError("m, n, k exceed the operands' shapes")
         if out is None:
             out = empty_colmajor(m, n, device=A.device)
-        C = colmajor(C) if C is not None else None
-        E = colmajor(E) if E is not None else None
+        out = _check_mat(out, "out", self.device)
+        if out.shape[0] < m or out.shape[1] < n:
+            raise ValueError("out is smaller than m x n")
+        C = _check_mat(C, "C", self.device) if C is not None else None
+        E = _check_mat(E, "E", self.device) if E is not None else None
+        for t, nm in ((C, "C"), (E, "E")):
+            if t is not None and (t.shape[0] < m or t.shape[1] < n):
+                raise ValueError(f"{nm} is smaller than m x n")
+        if gcol is not None:
+            gcol = _check_vec(gcol, "gcol", self.device, n)
         self._stream()
         s = self.lib.gevp_k_zgemm(self.h, opA.encode(), opB.encode(), m, n, k, float(alpha),
                                   _ptr(A), _ld(A), _ptr(B), _ld(B), float(beta), _ptr(C),
@@ -316,11 +445,15 @@ class Handle:
     def filter_gemm(self, precision, C, G, P, R, alpha, beta, gamma, delta):
         """One low-precision filter step: D = alpha C G + beta G + gamma P + delta R
         (per-column coefficients); C complex128, G/P/R complex64."""
-        C = colmajor(C)
-        G, P, R = colmajor(G), colmajor(P), colmajor(R)
-        n, m = G.shape
+        C = _check_mat(C, "C", self.device, square=True)
+        n = C.shape[0]
+        G = _check_mat(G, "G", self.device, dtype=torch.complex64, rows=n)
+        m = G.shape[1]
+        P = _check_mat(P, "P", self.device, dtype=torch.complex64, rows=n, cols=m)
+        R = _check_mat(R, "R", self.device, dtype=torch.complex64, rows=n, cols=m)
         D = empty_colmajor(n, m, dtype=torch.complex64, device=G.device)
-        co = [x.to(torch.float64).contiguous() for x in (alpha, beta, gamma, delta)]
+        co = [_check_vec(x.to(torch.float64), nm, self.device, m)
+              for x, nm in zip((alpha, beta, gamma, delta), ("alpha", "beta", "gamma", "delta"))]
         self._stream()
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         s = self.lib.gevp_k_filter_gemm(self.h, pr, n, m, _ptr(C), _ld(C), _ptr(G), _ld(G), _ptr(P),
@@ -331,7 +464,7 @@ class Handle:
 
     def potrf(self, M):
         """In-place lower Cholesky on a column-major copy; returns (L, pivot)."""
-        L = colmajor(M).clone()
+        L = _check_mat(M, "M", self.device, square=True).clone()
         n = L.shape[0]
         piv = ctypes.c_int64(0)
         self._stream()
@@ -341,9 +474,12 @@ class Handle:
         return L, int(piv.value)
 
     def trsm(self, side, trans, L, R):
-        L = colmajor(L)
-        R = colmajor(R).clone()
+        if side not in ("L", "R") or trans not in ("N", "C") or (side, trans) == ("R", "N"):
+            raise ValueError("side/trans must be L/N, L/C or R/C")
+        L = _check_mat(L, "L", self.device, square=True)
         n = L.shape[0]
+        R = _check_mat(R, "R", self.device, rows=n if side == "L" else None,
+                       cols=n if side == "R" else None).clone()
         m = R.shape[1] if side == "L" else R.shape[0]
         self._stream()
         s = self.lib.gevp_k_trsm(self.h, side.encode(), trans.encode(), n, m, _ptr(L), _ld(L),
@@ -353,7 +489,7 @@ class Handle:
         return R
 
     def heev(self, H):
-        H = colmajor(H).clone()
+        H = _check_mat(H, "H", self.device, square=True).clone()
         n = H.shape[0]
         th = torch.empty(n, dtype=torch.float64, device=H.device)
         Z = empty_colmajor(n, n, device=H.device)
@@ -367,7 +503,7 @@ class Handle:
     def seed_monitor(self, M):
         """Seed monitor of a k x k cross-overlap M: returns (sin_rms, dev_mean,
         dev_max, reindexed, dev_std, match)."""
-        M = colmajor(M)
+        M = _check_mat(M, "M", self.device, square=True)
         k = M.shape[0]
         st = (ctypes.c_double * 5)()
         match = (ctypes.c_int * k)()
@@ -382,7 +518,7 @@ class Handle:
     def lu_shifted(self, C, z):
         """Packed LU (no row exchanges) of z I - C; returns (LU, pivot) with
         pivot = 0 or the first failing pivot (1-based)."""
-        C = colmajor(C)
+        C = _check_mat(C, "C", self.device, square=True)
         n = C.shape[0]
         LU = empty_colmajor(n, n, device=C.device)
         piv = ctypes.c_int64(0)
@@ -395,8 +531,8 @@ class Handle:
 
     def contour_filter(self, C, V, a, b, nq):
         """Y = sum_j w_j (z_j I - C)^{-1} V on the circle with diameter [a, b]."""
-        C = colmajor(C)
-        V = colmajor(V)
+        C = _check_mat(C, "C", self.device, square=True)
+        V = _check_mat(V, "V", self.device, rows=C.shape[0])
         n, m = V.shape
         Y = empty_colmajor(n, m, device=V.device)
         self._stream()
@@ -415,10 +551,11 @@ class Handle:
         gevp_update_info fields as a dict (with "status"), or None when
         want_info is False (then the call is asynchronous)."""
         n = _check_inplace(A)
-        A_new = colmajor(A_new)
-        if tuple(A_new.shape) != (n, n) or A_new.dtype != torch.complex128:
-            raise ValueError("A_new must be a complex128 n x n matrix")
+        _on_device(A, self.device, "A")
+        A_new = _check_mat(A_new, "A_new", self.device, rows=n, cols=n)
         ldm = _check_mask(mask, n)
+        if mask is not None:
+            _on_device(mask, self.device, "mask")
         inf = UpdateInfo() if want_info else None
         self._stream()
         s = self.lib.gevp_update_thresholded(self.h, n, _ptr(A), _ld(A), _ptr(A_new), _ld(A_new),
@@ -436,12 +573,12 @@ class Handle:
         """In place on A: lower entries whose bit is set in mask (int32 words
         from empty_mask(n)) are taken from S."""
         n = _check_inplace(A)
-        S = colmajor(S)
-        if tuple(S.shape) != (n, n) or S.dtype != torch.complex128:
-            raise ValueError("S must be a complex128 n x n matrix")
+        _on_device(A, self.device, "A")
+        S = _check_mat(S, "S", self.device, rows=n, cols=n)
         if mask is None:
             raise ValueError("mask is required")
         ldm = _check_mask(mask, n)
+        _on_device(mask, self.device, "mask")
         self._stream()
         s = self.lib.gevp_update_masked(self.h, n, _ptr(A), _ld(A), _ptr(S), _ld(S), _ptr(mask), ldm)
         if s != GEVP_OK:
@@ -464,6 +601,8 @@ def _check_inplace(A) -> int:
         raise ValueError("A must be a complex128 n x n matrix")
     if A.stride(0) != 1 and A.shape[0] > 1:
         raise ValueError("A is updated in place and must be column-major")
+    if A.is_conj() or A.is_neg():
+        raise ValueError("A is updated in place and must not be a lazy conjugate or negative view")
     return int(A.shape[0])
 
 

@@ -18,7 +18,10 @@ A series is refreshed (next step cold) when the subspace moved more than
 ``max_sin_rms``, when the angles stopped shrinking for ``flat_steps``
 consecutive steps (each at least ``flat_ratio`` times the previous one), or
 when a seeded solve cost more than ``max_cost_growth`` times the cheapest
-one of its series.  Host logic only: decisions come from the info
+one of its series.  Angles below ``settled_sin_rms`` count as settled, not
+flat: a sequence whose eigenvectors no longer move measurably has converged
+as far as the eigensolver can tell, and refreshing it would only cost a
+cold solve.  Host logic only: decisions come from the info
 dictionaries ``gevp.Handle.solve`` returns with ``seed_monitor`` enabled.
 """
 from dataclasses import dataclass, field
@@ -32,6 +35,7 @@ class RestartPolicy:
     flat_ratio: float = 0.95
     flat_steps: int = 2
     max_cost_growth: float = 2.0
+    settled_sin_rms: float = 1e-10
     history: List[dict] = field(default_factory=list)
 
     def next_mode(self) -> str:
@@ -46,7 +50,7 @@ class RestartPolicy:
         sin = [h["sin_rms"] for h in series]
         if sin[-1] > self.max_sin_rms:
             return "cold"
-        if len(sin) > self.flat_steps:
+        if len(sin) > self.flat_steps and sin[-1] > self.settled_sin_rms:
             tail = sin[-(self.flat_steps + 1):]
             if all(tail[i + 1] >= self.flat_ratio * tail[i] for i in range(self.flat_steps)):
                 return "cold"

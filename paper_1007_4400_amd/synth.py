@@ -271,7 +271,7 @@ def unit_hermitian_torch(n: int, g, device="cuda", iters: int = 60):
 # matrix-entry evolution (thresholded partial updates)
 #
 # Stand-in for the Hamiltonian differences between adjacent SCF iterations
-# that the paper studies at fixed k-point (section 3, paragraph "Matrix
+# that the paper studies at fixed k-point (section 2, paragraph "Matrix
 # generation", and its figure): wide areas of the difference stay below any
 # threshold, rows and columns of unchanging entries form a cross, and the
 # share of entries above a fixed threshold falls as the run settles.

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     from paper_1007_4400_amd import gevp
 
-    for s in range(8):
+    for s in range(9):
         assert gevp.status_string(s)
     assert "positive definite" in gevp.status_string(gevp.GEVP_ERR_NOT_HPD)
 
@@ -58,3 +58,19 @@ def test_create_without_gpu_fails_cleanly():
 
     with pytest.raises(gevp.GevpError):
         gevp.Handle(0)
+
+
+def test_workspace_size_query_needs_no_gpu():
+    from paper_1007_4400_amd import gevp
+
+    skw = 6 * 128 * 2 ** 20  # six fixed split-K slots
+    b8192 = gevp.workspace_size(8192, 820, gevp.make_opts(precision="bf16x3"))
+    # at least A, B copies, L and C (4 n^2 complex128) and the split-BF16 copy of C
+    assert b8192 >= 4 * 16 * 8192 ** 2 + 8 * 8192 ** 2 + skw
+    assert b8192 < 6 * 16 * 8192 ** 2 + skw
+    assert gevp.workspace_size(256, 16) < gevp.workspace_size(512, 16) < b8192
+    # a low-precision filter needs its copies on top of the FP64 workspace
+    assert gevp.workspace_size(2048, 205, gevp.make_opts(precision="fp32")) > \
+        gevp.workspace_size(2048, 205)
+    with pytest.raises(gevp.GevpError):
+        gevp.workspace_size(10, 11)

@@ -151,14 +151,26 @@ def test_nonfinite_input(h):
 
 
 def test_invalid_arguments(h):
+    import ctypes
+
     from paper_1007_4400_amd import gevp
 
     A = _dev(np.eye(8, dtype=complex))
-    with pytest.raises(gevp.GevpError) as e:
+    # the binding rejects it before the ABI ...
+    with pytest.raises(ValueError):
         h.solve(A, A, 9)
-    assert e.value.status == gevp.GEVP_ERR_INVALID
-    with pytest.raises(gevp.GevpError):
+    # ... and so does the library itself (zhegv-style info = -argument index)
+    lam = torch.empty(9, dtype=torch.float64, device="cuda")
+    X = gevp.empty_colmajor(8, 9, device="cuda")
+    info = gevp.Info()
+    o = gevp.make_opts()
+    vp = ctypes.c_void_p
+    s = h.lib.gevp_solve(h.h, ctypes.byref(o), 8, vp(A.data_ptr()), 8, vp(A.data_ptr()), 8, None, 8, 0,
+                         9, 1e-10, 9, vp(lam.data_ptr()), vp(X.data_ptr()), 8, None, ctypes.byref(info))
+    assert s == gevp.GEVP_ERR_INVALID and info.lapack_info == -11
+    with pytest.raises(gevp.GevpError) as e:
         h.solve(A, A, 2, tol=-1.0)
+    assert e.value.status == gevp.GEVP_ERR_INVALID
 
 
 def test_backward_matches_oracle_gradient(h, oracle_mod):

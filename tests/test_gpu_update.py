@@ -1,4 +1,4 @@
-"""Thresholded partial matrix update on the GPU against the oracle (section 3,
+"""Thresholded partial matrix update on the GPU against the oracle (section 2,
 paragraph "Matrix generation": entries whose change between adjacent SCF
 Hamiltonians exceeds p_t * delta are updated, delta the largest change).
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's thresholded partial update (section 3, paragraph
+"""Pins of the oracle's thresholded partial update (section 2, paragraph
 "Matrix generation": delta = largest entry change between adjacent SCF
 Hamiltonians, entries whose change exceeds p_t * delta are updated).
 

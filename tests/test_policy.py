@@ -58,3 +58,24 @@ def test_seeded_step_needs_monitor():
     p.record("cold", {})
     with pytest.raises(ValueError):
         p.record("seeded", {"col_degrees": 10})
+
+
+def test_settled_angles_are_not_flat():
+    """A settled sequence reports angles at rounding level (or exactly zero):
+    they do not shrink any more, but that is convergence, not stalled
+    progress, so no refresh is forced; a flat series above the floor still is."""
+    p = RestartPolicy(flat_steps=2, flat_ratio=0.95)
+    p.record("cold", {})
+    for s in (1e-4, 0.0, 0.0, 0.0, 0.0):
+        p.record("seeded", _info(s))
+        assert p.next_mode() == "seeded"
+    q = RestartPolicy(flat_steps=2, flat_ratio=0.95, settled_sin_rms=1e-10)
+    q.record("cold", {})
+    for s in (1e-12, 1.1e-12, 1.2e-12):
+        q.record("seeded", _info(s))
+    assert q.next_mode() == "seeded"
+    r = RestartPolicy(flat_steps=2, flat_ratio=0.95)
+    r.record("cold", {})
+    for s in (1e-6, 1e-6, 1e-6):
+        r.record("seeded", _info(s))
+    assert r.next_mode() == "cold"
