@@ -280,6 +280,24 @@ gevp_status gevp_backward(gevp_handle h, int64_t n, int64_t nev, const void* X, 
                           const double* lambda, const double* w,
                           void* dA, int64_t ldda, void* dB, int64_t lddb);
 
+/*
+ * gevp_backward for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, results and asynchronous behaviour, but the n x nev scaled copy
+ * of X lives in a fixed 32 MiB device array of the library (one per device,
+ * held until the process ends; its device address is taken once per device
+ * by gevp_create) and no call here allocates or frees memory, creates events
+ * or splits K.  n * nev * 16 bytes must not exceed 32 MiB (e.g. n = 4096,
+ * nev <= 512): larger problems return GEVP_ERR_WORKSPACE with nothing
+ * launched.  Every call on a device shares that device's array: calls that
+ * overlap on one device (other streams, other handles or threads) race and
+ * must be ordered by the caller.  The array keeps the last call's contents;
+ * nothing in it needs to start at zero.
+ */
+gevp_status gevp_backward_noalloc(gevp_handle h, int64_t n, int64_t nev, const void* X,
+                                  int64_t ldx, const double* lambda, const double* w, void* dA,
+                                  int64_t ldda, void* dB, int64_t lddb);
+
 /* ---- kernel-level entry points (the building blocks, exposed for tests) ---- */
 
 /*

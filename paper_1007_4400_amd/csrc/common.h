@@ -77,6 +77,9 @@ struct gevp_ctx {
   bool ext = false;
   char* ext_base = nullptr;
   size_t ext_bytes = 0;
+  // set for the duration of a call that must not allocate: launch_zgemm then
+  // never splits K (which needs the split-K buffer)
+  bool no_split = false;
 };
 
 // Split-K partial products of launch_zgemm: one fixed-size buffer per stream

@@ -22,10 +22,36 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
 #include "common.h"
+
+// Scratch of gevp_backward_noalloc (the only entry point that allocates
+// nothing): one array per device, held until the process ends.  In host code
+// `scratch` only names the symbol; its device address on each device comes
+// from hipGetSymbolAddress, taken once per device by gevp_create.
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+// device address of `scratch` on the current device `dev` (looked up once)
+gevp_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return GEVP_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GEVP_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return GEVP_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GEVP_OK;
+}
+}  // namespace
 
 int gevp_log_enabled() {
   static int v = -1;
@@ -340,6 +366,17 @@ gevp_status gevp_create(gevp_handle* h, int device) {
   *h = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return GEVP_ERR_HIP;
+  }
+  // set-up of the no-allocation entry point: the device address of this
+  // device's scratch array, with the device current
+  void* sp = nullptr;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) prev = device;
+  const bool ok = hipSetDevice(device) == hipSuccess && scratch_address(device, &sp) == GEVP_OK;
+  (void)hipSetDevice(prev);
+  if (!ok) {
     (void)hipGetLastError();
     return GEVP_ERR_HIP;
   }
@@ -1005,6 +1042,43 @@ gevp_status gevp_backward(gevp_handle h, int64_t n, int64_t nev, const void* X_,
                           nullptr, (zd*)dB_, lddb));
   }
   return GEVP_OK;
+}
+
+gevp_status gevp_backward_noalloc(gevp_handle h, int64_t n, int64_t nev, const void* X_,
+                                  int64_t ldx, const double* lambda, const double* w, void* dA_,
+                                  int64_t ldda, void* dB_, int64_t lddb) {
+  if (!h || n < 1 || nev < 1 || nev > n || !X_ || ldx < n || !w) return GEVP_ERR_INVALID;
+  if (dA_ && ldda < n) return GEVP_ERR_INVALID;
+  if (dB_ && (lddb < n || !lambda)) return GEVP_ERR_INVALID;
+  if ((size_t)n * (size_t)nev * sizeof(zd) > SCRATCH_BYTES) return GEVP_ERR_WORKSPACE;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  void* sp = nullptr;
+  GEVP_TRY(scratch_address(h->device, &sp));  // looked up by gevp_create already
+  gevp_ctx* c = h;
+  const zd* X = (const zd*)X_;
+  zd* Xw = (zd*)sp;  // n x nev scaled columns, in the scratch array
+  // no split-K buffer and no profiling events for the duration of the call
+  const bool ns = c->no_split;
+  const int prof = c->profiling;
+  c->no_split = true;
+  c->profiling = 0;
+  gevp_status st = GEVP_OK;
+  if (dA_) {
+    st = launch_scale_cols(c, n, nev, X, ldx, w, Xw, n);
+    if (st == GEVP_OK)
+      st = launch_zgemm(c, 0, 1, n, n, nev, 1.0, Xw, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                        nullptr, (zd*)dA_, ldda);
+  }
+  if (st == GEVP_OK && dB_) {
+    st = launch_scale_cols(c, n, nev, X, ldx, w, Xw, n);
+    if (st == GEVP_OK) st = launch_scale_cols(c, n, nev, Xw, n, lambda, Xw, n);
+    if (st == GEVP_OK)
+      st = launch_zgemm(c, 0, 1, n, n, nev, -1.0, Xw, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                        nullptr, (zd*)dB_, lddb);
+  }
+  c->no_split = ns;
+  c->profiling = prof;
+  return st;
 }
 
 gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, const int64_t* n,

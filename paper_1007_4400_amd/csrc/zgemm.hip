@@ -374,8 +374,9 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.lower = lower;
   const int nk = (p.K + KT - 1) / KT;
   p.upperA = upperA;
-  int s = upperA ? 1
-                 : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
+  int s = (upperA || c->no_split)
+              ? 1
+              : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
   p.nks = nk > 0 ? (nk + s - 1) / s : 1;
   p.splits = nk > 0 ? (nk + p.nks - 1) / p.nks : 1;
   p.part = nullptr;

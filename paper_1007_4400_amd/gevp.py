@@ -121,6 +121,8 @@ def load():
     lib.gevp_solve_batched.restype = I
     lib.gevp_backward.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
     lib.gevp_backward.restype = I
+    lib.gevp_backward_noalloc.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
+    lib.gevp_backward_noalloc.restype = I
     lib.gevp_k_zgemm.argtypes = [P, C, C, L, L, L, D, P, L, P, L, D, P, L, D, P, L, P, P, L]
     lib.gevp_k_zgemm.restype = I
     lib.gevp_k_filter_gemm.argtypes = [P, I, L, L, P, L, P, L, P, L, P, L, P, L, P, P, P, P]
