@@ -81,7 +81,14 @@ typedef struct {
                                (gevp_info seed_*) */
   int filter;               /* gevp_filter; default GEVP_FILTER_CHEBYSHEV */
   int contour_points;       /* quadrature nodes of the contour filter; 0 = 8 */
-  int reserved[4];
+  int lock_mode;            /* 0 (default): hard locking -- the converged prefix of wanted
+                               pairs leaves the orthonormalisation and Rayleigh-Ritz of later
+                               sweeps; 1: soft locking -- converged columns are only left out
+                               of the filter */
+  int sweep_reduction;      /* low-precision filters: the largest residual reduction one sweep
+                               aims for, as a power of ten (the products' rounding floor); 0 =
+                               default (4 for split-BF16, 6 for FP32) */
+  int reserved[2];
 } gevp_opts;
 
 /* Filter of the subspace iteration.  The contour filter (section 3 names a
@@ -154,6 +161,7 @@ typedef struct {
   double gemm_kernel_ms;
   double gemm_flops;
   int64_t gemm_launches;
+  int locked;             /* columns hard-locked in the last sweep */
 } gevp_info;
 
 typedef enum {

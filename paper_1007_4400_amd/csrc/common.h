@@ -221,6 +221,13 @@ gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const do
 gevp_status launch_scale_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                               const double* w, zd* D, int64_t ldd);
 gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d);
+// locking helpers (nb <= 2048): theta/resid[j] <- theta/resid[perm[j]] for j < nl;
+// stable merge of the ascending runs [0, nl) and [nl, nb) of theta (resid
+// follows), order[p] = the index that lands at position p
+gevp_status launch_permute_prefix(gevp_ctx* c, double* theta, double* resid, const int* perm,
+                                  int64_t nl);
+gevp_status launch_merge_runs(gevp_ctx* c, double* theta, double* resid, int64_t nb, int64_t nl,
+                              int* order);
 gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out);
 
 // Lanczos bounds: runs `steps` steps on the Hermitian M (full storage) and

@@ -139,6 +139,8 @@ struct Opts {
   int skip_final;
   int seed_monitor;
   int filter, nq;
+  int lock_mode;
+  int sweep_reduction;  // log10 of a low-precision sweep's largest aimed reduction (0: default)
 };
 
 Opts resolve(const gevp_opts* o, int64_t nev) {
@@ -161,6 +163,8 @@ Opts resolve(const gevp_opts* o, int64_t nev) {
   r.seed_monitor = o ? o->seed_monitor : 0;
   r.filter = o ? o->filter : 0;
   r.nq = (o && o->contour_points > 0) ? o->contour_points : 8;
+  r.lock_mode = o ? o->lock_mode : 0;
+  r.sweep_reduction = (o && o->sweep_reduction > 0 && o->sweep_reduction < 16) ? o->sweep_reduction : 0;
   return r;
 }
 
@@ -183,7 +187,7 @@ size_t solve_ws_bytes(const Opts& o, int64_t n, int64_t nb, bool contour, bool c
   need += heev_work_bytes(nb);
   need += 2 * lanczos_work_bytes(n, lz);                 // main and second stream
   need += 3 * ws_round(sizeof(double) * 8);              // bounds C, A, B
-  need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, negl, spare
+  need += 4 * ws_round(sizeof(double) * nb);             // theta, resid, final residuals, merge order
   need += ws_round(sizeof(int) * nb);                    // perm
   need += ws_round(sizeof(double) * 3 * 256);            // coefs
   need += ws_round(sizeof(int) * 300) + ws_round(sizeof(double) * 16);  // status
@@ -619,7 +623,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double* theta = (double*)ws_take(c, sizeof(double) * nb);
   double* rres = (double*)ws_take(c, sizeof(double) * nb);
   double* fres = (double*)ws_take(c, sizeof(double) * nb);
-  (void)ws_take(c, sizeof(double) * nb);
+  int* order = (int*)ws_take(c, sizeof(double) * nb);  // merge order of the locked sweep
   int* perm = (int*)ws_take(c, sizeof(int) * nb);
   double* coefs = (double*)ws_take(c, sizeof(double) * 3 * 256);
   int* st_i = (int*)ws_take(c, sizeof(int) * 300);
@@ -772,7 +776,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   int fallbacks = 0;
   // rounding floor of the filter products: FP32 products with FP32
   // accumulation over n terms, or split-BF16 products (about 2^-16 each)
-  const double u_target = bf16 ? 1e-4 : 1e-6;
+  const double u_target =
+      o.sweep_reduction > 0 ? std::pow(10.0, -o.sweep_reduction) : (bf16 ? 1e-4 : 1e-6);
   // the degree model is a first-order estimate: aiming a few times below tol
   // lets the columns it slightly misjudges converge in the same sweep instead
   // of costing another orthonormalisation and Rayleigh-Ritz round
@@ -859,14 +864,49 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   cp.mode = lp ? 2 : 0;
   bool cfact = false;  // contour factorisations done
   double ca = 0.0, cb = 0.0;
+  // Hard locking: every converged wanted Ritz pair leaves the iteration.
+  // The filters pass converged (degree-0) columns through unchanged and the
+  // degree order puts them first, so after a sweep they are P0's first nl
+  // columns; their Ritz values, residuals and W = C P0 columns are permuted
+  // to match.  The next sweep projects them out of the active columns (block
+  // Gram-Schmidt, twice), orthonormalises and projects only the active ones,
+  // and merges the two ascending runs of Ritz values back into one order.
+  int64_t nl = 0;
   for (it = 0; it < o.maxit; ++it) {
+    const int64_t l0 = (o.lock_mode == 0 && it > 0) ? nl : 0;
+    const int64_t na = nb - l0;
+    zd* Pa = P0 + l0 * n;
+    info->locked = (int)l0;
     tm.start();
+    if (l0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        GEVP_TRY(launch_zgemm(c, 1, 0, l0, na, n, 1.0, P0, n, Pa, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                              nullptr, Gs, l0));
+        GEVP_TRY(launch_zgemm(c, 0, 0, n, na, l0, -1.0, P0, n, Gs, l0, 1.0, Pa, n, 0.0, nullptr, 0,
+                              nullptr, Pa, n));
+      }
+    }
     bool skipped = false;
-    GEVP_TRY(cholqr2(c, n, nb, P0, n, qw, &fallbacks, full_seed && it == 0, &skipped));
+    GEVP_TRY(cholqr2(c, n, na, Pa, n, qw, &fallbacks, full_seed && it == 0, &skipped));
     if (spec && it == 0) GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evs.join, 0));
     tm.stop(info, GEVP_STAGE_QR);
     tm.start();
-    if (spec && it == 0 && skipped) {
+    if (l0 > 0) {
+      // Rayleigh-Ritz of the active columns; the locked ones are copied over
+      zd* Wa = W + l0 * n;
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, na, n, 1.0, C, n, Pa, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, Wa, n));
+      GEVP_TRY(launch_zgemm(c, 1, 0, na, na, n, 1.0, Pa, n, Wa, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, Hs, na));
+      GEVP_TRY(launch_symmetrize(c, na, Hs, na));
+      GEVP_TRY(heev_small(c, na, Hs, na, theta + l0, Zs, na, heevw));
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, na, na, 1.0, Pa, n, Zs, na, 0.0, nullptr, 0, 0.0, nullptr,
+                            0, nullptr, P1 + l0 * n, n));
+      GEVP_TRY(launch_zgemm(c, 0, 0, n, na, na, 1.0, Wa, n, Zs, na, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                            nullptr, T + l0 * n, n));
+      GEVP_TRY(launch_copy2d(c, n, l0, P0, n, P1, n));
+      GEVP_TRY(launch_copy2d(c, n, l0, W, n, T, n));
+    } else if (spec && it == 0 && skipped) {
       // Ritz pairs of the seed from the second stream: rotate the basis, then W = C P
       GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, P1, n));
@@ -886,7 +926,15 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     }
     std::swap(P0, P1);
     std::swap(W, T);
-    GEVP_TRY(launch_resid_cols(c, n, nb, W, n, P0, n, theta, rres));
+    GEVP_TRY(launch_resid_cols(c, n, na, W + l0 * n, n, P0 + l0 * n, n, theta + l0, rres + l0));
+    if (l0 > 0) {
+      // one ascending order again: the locked and the active run merged
+      GEVP_TRY(launch_merge_runs(c, theta, rres, nb, l0, order));
+      GEVP_TRY(launch_gather_cols(c, n, nb, P0, n, order, P1, n));
+      GEVP_TRY(launch_gather_cols(c, n, nb, W, n, order, T, n));
+      std::swap(P0, P1);
+      std::swap(W, T);
+    }
     tm.stop(info, GEVP_STAGE_RR);
     info->outer_iters = it + 1;
     GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs, rho0,
@@ -895,9 +943,12 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_HIP_TRY(hipMemcpyAsync(hsd.data(), st_d, sizeof(double) * hsd.size(), hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
     info->nconv = hst[0];
+    // columns the filter leaves alone (degree 0: the converged wanted ones)
+    // are locked for the next sweep
+    nl = (!hst[2] && hst[1] > 0) ? hst[4] : 0;
     if (gevp_log_enabled())
-      fprintf(stderr, "[gevp] it %d nconv %d maxdeg %d a %.4g b %.4g tol %.3g resid %.3g..%.3g\n", it,
-              hst[0], hst[1], hsd[0], hsd[1], hsd[4], hsd[8], hsd[7]);
+      fprintf(stderr, "[gevp] it %d locked %lld nconv %d maxdeg %d a %.4g b %.4g tol %.3g resid %.3g..%.3g\n",
+              it, (long long)l0, hst[0], hst[1], hsd[0], hsd[1], hsd[4], hsd[8], hsd[7]);
     if (hst[2]) {
       converged = true;
       break;
@@ -949,6 +1000,13 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       GEVP_TRY(run_filter_r2(hst[1], hst.data() + 4, hsd[3]));
     } else {
       GEVP_TRY(run_filter(hst[1], hst.data() + 4));
+    }
+    if (nl > 0) {
+      // the columns to lock lead P0 in the filter's degree order: their Ritz
+      // values, residuals and C P0 columns follow them
+      GEVP_TRY(launch_permute_prefix(c, theta, rres, perm, nl));
+      GEVP_TRY(launch_gather_cols(c, n, nl, W, n, perm, T, n));
+      std::swap(W, T);
     }
     tm.stop(info, GEVP_STAGE_FILTER);
   }

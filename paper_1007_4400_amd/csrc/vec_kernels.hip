@@ -281,6 +281,65 @@ __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, 
   }
 }
 
+// Locked columns after a filter sweep: entries j < nl of theta and resid
+// become those of column perm[j] (in place, through LDS; nb <= 2048).
+__global__ __launch_bounds__(256) void k_permute_prefix(double* theta, double* resid, const int* perm,
+                                                        int nl) {
+  __shared__ double st[2048], sr[2048];
+  for (int j = threadIdx.x; j < nl; j += 256) {
+    st[j] = theta[perm[j]];
+    sr[j] = resid[perm[j]];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nl; j += 256) {
+    theta[j] = st[j];
+    resid[j] = sr[j];
+  }
+}
+
+// Stable merge of the two ascending runs theta[0, nl) and theta[nl, nb):
+// position of entry j in the merged order (runs of equal values keep the
+// first run first); theta and resid are rewritten in merged order and
+// order[p] = j is the column that lands at position p.  One work-group,
+// nb <= 2048.
+__global__ __launch_bounds__(256) void k_merge_runs(double* theta, double* resid, int nb, int nl,
+                                                    int* order) {
+  __shared__ double st[2048], sr[2048];
+  for (int j = threadIdx.x; j < nb; j += 256) {
+    st[j] = theta[j];
+    sr[j] = resid[j];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb; j += 256) {
+    const double v = st[j];
+    int lo, hi, base;
+    if (j < nl) {  // entries of the second run strictly below v
+      lo = nl;
+      hi = nb;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      base = j + (lo - nl);
+    } else {  // entries of the first run at or below v
+      lo = 0;
+      hi = nl;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid] <= v) lo = mid + 1; else hi = mid;
+      }
+      base = (j - nl) + lo;
+    }
+    order[base] = j;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < nb; p += 256) {
+    const int j = order[p];
+    theta[p] = st[j];
+    resid[p] = sr[j];
+  }
+}
+
 __global__ void k_gather_cols(int64_t rows, const zd* S, int64_t lds, const int* perm, zd* D,
                               int64_t ldd) {
   const int64_t j = blockIdx.y;
@@ -611,6 +670,25 @@ gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const do
   if (n <= 0) return GEVP_OK;
   hipLaunchKernelGGL(k_add_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n, M,
                      ldm, shift);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_permute_prefix(gevp_ctx* c, double* theta, double* resid, const int* perm,
+                                  int64_t nl) {
+  if (nl <= 0) return GEVP_OK;
+  if (nl > 2048) return GEVP_ERR_INVALID;
+  hipLaunchKernelGGL(k_permute_prefix, dim3(1), dim3(256), 0, c->stream, theta, resid, perm, (int)nl);
+  GEVP_HIP_TRY(hipGetLastError());
+  return GEVP_OK;
+}
+
+gevp_status launch_merge_runs(gevp_ctx* c, double* theta, double* resid, int64_t nb, int64_t nl,
+                              int* order) {
+  if (nb <= 0) return GEVP_OK;
+  if (nb > 2048) return GEVP_ERR_INVALID;
+  hipLaunchKernelGGL(k_merge_runs, dim3(1), dim3(256), 0, c->stream, theta, resid, (int)nb, (int)nl,
+                     order);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
         ("seed", ctypes.c_ulonglong), ("skip_final_residual", ctypes.c_int),
         ("batch_streams", ctypes.c_int), ("seed_monitor", ctypes.c_int),
         ("filter", ctypes.c_int), ("contour_points", ctypes.c_int),
-        ("reserved", ctypes.c_int * 4),
+        ("lock_mode", ctypes.c_int), ("sweep_reduction", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
     ]
 
 
@@ -52,7 +53,7 @@ class Info(ctypes.Structure):
         ("contour_b", ctypes.c_double), ("contour_applications", ctypes.c_int),
         ("contour_columns", ctypes.c_int64), ("seed_dev_std", ctypes.c_double),
         ("gemm_kernel_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
-        ("gemm_launches", ctypes.c_int64),
+        ("gemm_launches", ctypes.c_int64), ("locked", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -238,8 +239,10 @@ def _ld(t: torch.Tensor) -> int:
 
 def make_opts(precision="fp64", nex=0, deg_init=0, deg_max=0, maxit=0, lanczos_steps=0, seed=0,
               skip_final_residual=False, batch_streams=0, seed_monitor=False, filter="chebyshev",
-              contour_points=0) -> Opts:
+              contour_points=0, locking="hard", sweep_reduction=0) -> Opts:
     o = Opts()
+    o.lock_mode = {"hard": 0, "soft": 1}[locking]
+    o.sweep_reduction = int(sweep_reduction)
     o.filter = FILTERS[filter] if isinstance(filter, str) else int(filter)
     o.contour_points = int(contour_points)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)

@@ -63,3 +63,29 @@ def test_mixed_cold(h, oracle_mod):
     lam, X, res, info = h.solve(_dev(p.A), _dev(p.B), wl.nev, tol=TOL,
                                 opts=gevp.make_opts(precision="fp32"))
     _check(oracle_mod, p.A, p.B, lam, X, wl.nev)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_hard_locking_matches_soft_and_oracle(h, oracle_mod, precision):
+    """Converged wanted pairs leave CholQR and Rayleigh-Ritz (hard locking):
+    a seeded sequence and a cold solve give the oracle's pairs at the FP64
+    bar, the same eigenvalues as soft locking, and the lock is really taken."""
+    from paper_1007_4400_amd import gevp
+
+    wl = synth.scaled(synth.MEDIUM, 512, steps=4)
+    hard = gevp.make_opts(precision=precision)
+    soft = gevp.make_opts(precision=precision, locking="soft")
+    kx = h.block_size(wl.n, wl.nev, hard)
+    X = Xs = None
+    locked = 0
+    for k, (A, B) in enumerate(synth.sequence(wl, 4)):
+        lam, X, res, info = h.solve(_dev(A), _dev(B), wl.nev, X0=X, tol=TOL, kx=kx, opts=hard)
+        lam_s, Xs, _, info_s = h.solve(_dev(A), _dev(B), wl.nev, X0=Xs, tol=TOL, kx=kx, opts=soft)
+        print(f"{precision} step {k}: hard outer {info['outer_iters']} locked {info['locked']}, "
+              f"soft outer {info_s['outer_iters']} locked {info_s['locked']}", flush=True)
+        assert info_s["locked"] == 0
+        locked = max(locked, info["locked"])
+        _check(oracle_mod, A, B, lam, X, wl.nev)
+        d = (lam[: wl.nev] - lam_s[: wl.nev]).abs() / lam_s[: wl.nev].abs().clamp(min=1)
+        assert d.max().item() <= TOL
+    assert locked > 0
