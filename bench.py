@@ -630,7 +630,7 @@ def run_sequence(args):
     parity = {}
 
     def solve(A, X0, o):
-        lam, Xo, res, info = h.solve(A, B, wl.nev, X0=X0, tol=args.tol, kx=kx, opts=o)
+        lam, Xo, res, info = h.solve(A, B, wl.nev, X0=X0, tol=args.tol, kx=kx, opts=o, want_resid=False)
         if info["max_resid"] > args.tol:
             raise RuntimeError(f"residual {info['max_resid']:.3e} above tol")
         return lam, Xo, info

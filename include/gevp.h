@@ -247,7 +247,8 @@ gevp_status gevp_set_workspace(gevp_handle h, void* dev_ptr, size_t bytes);
  *   lambda   device float64[kx], ascending
  *   X, ldx   device complex128 n x kx, B-orthonormal eigenvectors; the
  *            largest-modulus entry of each column is real and positive
- *   resid    optional device float64[kx]: ||A x_i - lambda_i B x_i||_2
+ *   resid    optional device float64[kx]: ||A x_i - lambda_i B x_i||_2 (without it
+ *            the final check forms the residuals of the nev wanted pairs only)
  *   info     optional host struct
  * Returns GEVP_OK, or GEVP_ERR_NOCONV with the best pairs written.
  */

@@ -20,16 +20,24 @@
 // loop moves both operands as plain 16-byte chunks and does no conversion.
 //
 // Tiling: 512 threads (8 waves, 2 x 4) own a 128 x 128 complex output tile,
-// each wave 64 x 32 (4 x 2 MFMA blocks); K advances 32 per slice through two
-// LDS stages of 64 KB.  The operands go from global memory into LDS by
-// direct transfers (no staging registers, no LDS stores); a staged row is
-// 256 bytes with its 16-byte chunks XOR-swizzled by the row index so that
-// fragment reads meet no bank conflicts.  Measured at n = 8192 and 948
-// columns: 1.24 ms per launch, against 1.43 ms when the same loop staged
-// through registers and LDS stores (padded rows; loads two slices ahead)
-// and 1.65 ms with 64 x 64 wave tiles (one wave per SIMD).
+// each wave 64 x 32 (4 x 2 MFMA blocks); K advances 32 per slice.  The
+// operands go from global memory into LDS by direct transfers (no staging
+// registers, no LDS stores); a staged row is 256 bytes with its 16-byte
+// chunks XOR-swizzled by the row index so that fragment reads meet no bank
+// conflicts.  The rows of C, streamed from HBM, are staged three slices
+// deep and the iterate's columns two (3 x 32 KB + 2 x 32 KB = the 160 KB of
+// LDS); each stage is its own LDS array and the loop is unrolled by six so
+// that every stage index is a constant: the compiler can then tell a stage
+// being read from the stages whose transfers are in flight, and the only
+// waits on the transfers are the kernel's own (a __syncthreads() would also
+// drain the transfers two slices ahead).  Measured at n = 8192 and 948
+// columns: 1.23 ms per launch against 1.27 ms with two stages of both
+// operands, 1.43 ms when the loop staged through registers and LDS stores,
+// 1.65 ms with 64 x 64 wave tiles (one wave per SIMD), 1.34 ms with
+// 256 x 64 tiles, and no change from raising the wave priority around the
+// MFMAs.
 //
-// One work-group per compute unit runs at a time (128 KB of LDS), so a grid
+// One work-group per compute unit runs at a time (160 KB of LDS), so a grid
 // of T tiles takes ceil(T / CUs) rounds.  When that rounds badly (T = 384 on
 // 256 CUs costs two full rounds for 1.5 rounds of work) the K range is split
 // in s parts: each work-group writes its FP32 partial tile to a workspace
@@ -99,22 +107,39 @@ __device__ __forceinline__ uint4 negbf(uint4 v) {
 // 16-byte chunks are XOR-swizzled (physical chunk = logical chunk ^
 // SWZ(row)) so that fragment reads meet no bank conflicts.  Per
 // K slice the work-group issues 64 wave instructions (4 rows each: 32 for the
-// rows of C, 32 for the iterate's columns), 8 per wave, one slice ahead of the
-// MFMAs through two 64 KB stages.  Rows past the matrix load row 0 instead
-// (valid memory; their outputs are never stored).
+// rows of C, 32 for the iterate's columns), 8 per wave: the rows of C two
+// slices ahead of the MFMAs, the iterate's columns one.  Rows past the matrix
+// load row 0 instead (valid memory; their outputs are never stored).
 constexpr int DROW = 256;  // bytes per staged row
 // chunk swizzle of a staged row: the two 2-bit halves of row % 16 swapped.
 // Measured on this kernel's fragment reads (16 rows x 4 k-groups of 16 B per
 // wave instruction): no bank-conflict cycles, against 4 per read with
 // (row % 16) itself and 12 per read with (row / 2) % 16.
 #define SWZ(row) ((((row) & 3) << 2) | (((row) >> 2) & 3))
-constexpr size_t DMA_LDS = (size_t)2 * (BM + BN) * DROW;
+// stages: three of the rows of C, two of the iterate's columns, 32 KB each
+constexpr size_t A_STAGE = (size_t)BM * DROW, B_STAGE = (size_t)BN * DROW;
+static_assert(3 * A_STAGE + 2 * B_STAGE == 160 * 1024, "the LDS of one compute unit");
+
+template <int V>
+struct ic {
+  static constexpr int value = V;
+};
 
 __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_filter(BfParams p) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  // one array per stage, so that alias analysis separates a stage being read
+  // from the stages whose transfers are still in flight
+  __shared__ __attribute__((aligned(16))) unsigned char sA0[A_STAGE], sA1[A_STAGE], sA2[A_STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char sB0[B_STAGE], sB1[B_STAGE];
   constexpr int WNB = 2, WC = 4;
-  auto As = [&](int b) { return lds + b * ((BM + BN) * DROW); };
-  auto Bs = [&](int b) { return lds + b * ((BM + BN) * DROW) + BM * DROW; };
+  auto As = [&](auto S) -> unsigned char* {
+    if constexpr (decltype(S)::value == 0) return sA0;
+    else if constexpr (decltype(S)::value == 1) return sA1;
+    else return sA2;
+  };
+  auto Bs = [&](auto S) -> unsigned char* {
+    if constexpr (decltype(S)::value == 0) return sB0;
+    else return sB1;
+  };
 
   const int tid = threadIdx.x;
   int L = blockIdx.x;
@@ -159,13 +184,22 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_filter(BfParams p) {
     } else {
       const int gn = (col0 + row < p.N) ? col0 + row : 0;
       gsrc[k] = (const unsigned char*)(p.Bp + (int64_t)gn * p.KG * 4) + gofs;
-      ldst[k] = BM * DROW + blk * 4 * DROW;
+      ldst[k] = blk * 4 * DROW;
     }
   }
-  auto issue = [&](int t, int buf) {
-    unsigned char* stage = lds + buf * ((BM + BN) * DROW);
+  // wave instructions k = 0..3 move rows of C (wi < 32), k = 4..7 iterate columns
+  auto issueA = [&](int t, auto buf) {
+    unsigned char* stage = As(buf);
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 4; ++k)
+      __builtin_amdgcn_global_load_lds((const void*)(gsrc[k] + (int64_t)t * 256),
+                                       (__attribute__((address_space(3))) void*)(stage + ldst[k]),
+                                       16, 0, 0);
+  };
+  auto issueB = [&](int t, auto buf) {
+    unsigned char* stage = Bs(buf);
+#pragma unroll
+    for (int k = 4; k < 8; ++k)
       __builtin_amdgcn_global_load_lds((const void*)(gsrc[k] + (int64_t)t * 256),
                                        (__attribute__((address_space(3))) void*)(stage + ldst[k]),
                                        16, 0, 0);
@@ -178,18 +212,18 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_filter(BfParams p) {
   // transfers overlap the MFMAs (an LDS read after a transfer is issued
   // would wait for it)
   uint4 bf[WNB][4], af[4][4];
-  auto read_frags = [&](int cur) {
+  auto read_frags = [&](auto ca, auto cb) {
 #pragma unroll
     for (int j = 0; j < WNB; ++j) {
       const int col = wc * 16 * WNB + j * 16 + l16;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) bf[j][q] = frag(Bs(cur), col, q);
+      for (int q = 0; q < 4; ++q) bf[j][q] = frag(Bs(cb), col, q);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wr * 64 + i * 16 + l16;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) af[i][q] = frag(As(cur), row, q);
+      for (int q = 0; q < 4; ++q) af[i][q] = frag(As(ca), row, q);
     }
   };
   auto mfmas = [&]() {
@@ -231,18 +265,54 @@ __global__ __launch_bounds__(512, 1) void k_cgemm_bf16x3_filter(BfParams p) {
   const int t0 = kc * p.nks;
   const int t1 = (t0 + p.nks < nk) ? t0 + p.nks : nk;
   const int nloc = t1 - t0;
-  if (nloc > 0) issue(t0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int u = 0; u < nloc; ++u) {
-    const int cur = u & 1;
-    read_frags(cur);
-    if (u + 1 < nloc) issue(t0 + u + 1, cur ^ 1);
+  // issue order: A(0), B(0), A(1), then per slice u: B(u+1), A(u+2); at the
+  // end of slice u everything but this wave's last A transfers (slice u+2,
+  // four instructions) must have landed.  Slice u uses A stage u mod 3 and B
+  // stage u mod 2; the loop is unrolled by 6 so both are constants.
+  if (nloc > 0) {
+    issueA(t0, ic<0>{});
+    issueB(t0, ic<0>{});
+  }
+  if (nloc > 1) {
+    issueA(t0 + 1, ic<1>{});
+    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
+  __builtin_amdgcn_s_barrier();
+  auto body = [&](auto SA, auto SB, int u) {
+    constexpr int sa = decltype(SA)::value, sb = decltype(SB)::value;
+    read_frags(SA, SB);
+    if (u + 1 < nloc) issueB(t0 + u + 1, ic<1 - sb>{});
+    if (u + 2 < nloc) issueA(t0 + u + 2, ic<(sa + 2) % 3>{});
     __builtin_amdgcn_sched_barrier(0);
     mfmas();
     __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's transfers into the other stage
-    __syncthreads();
+    if (u + 2 < nloc)
+      asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // a bare barrier: __syncthreads() would also drain the slice-(u+2) transfers
+    __builtin_amdgcn_s_barrier();
+  };
+  int u = 0;
+  for (; u + 6 <= nloc; u += 6) {
+    body(ic<0>{}, ic<0>{}, u);
+    body(ic<1>{}, ic<1>{}, u + 1);
+    body(ic<2>{}, ic<0>{}, u + 2);
+    body(ic<0>{}, ic<1>{}, u + 3);
+    body(ic<1>{}, ic<0>{}, u + 4);
+    body(ic<2>{}, ic<1>{}, u + 5);
+  }
+  for (; u < nloc; ++u) {
+    switch (u % 6) {
+      case 0: body(ic<0>{}, ic<0>{}, u); break;
+      case 1: body(ic<1>{}, ic<1>{}, u); break;
+      case 2: body(ic<2>{}, ic<0>{}, u); break;
+      case 3: body(ic<0>{}, ic<1>{}, u); break;
+      case 4: body(ic<1>{}, ic<0>{}, u); break;
+      default: body(ic<2>{}, ic<1>{}, u); break;
+    }
   }
   // D layout of v_mfma_f32_16x16x32_bf16: lane l, register r -> row 4 (l/16) + r, col l%16
   if (p.splits > 1) {
@@ -478,13 +548,8 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
   // 128 KiB of LDS per work-group (gfx950 has 160 KB per CU); set once,
   // thread-safely (batched solves launch from several host threads)
-  static const bool attr_set = [&]() {
-    (void)hipFuncSetAttribute((const void*)k_cgemm_bf16x3_filter,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)DMA_LDS);
-    return true;
-  }();
-  (void)attr_set;
-  hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(512), DMA_LDS, c->stream, p);
+  // the stages are static LDS arrays (160 KB): no dynamic LDS
+  hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(512), 0, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
   if (p.splits > 1) {
     const int64_t elems = tiles * BM * BN;

@@ -534,12 +534,12 @@ gevp_status aux_ctx(gevp_ctx* c, gevp_ctx** out) {
 // the caller's X0 and writes workspace the next call reuses.
 struct EventPair {
   hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
+  hipEvent_t reduced = nullptr, bounds = nullptr;  // C formed; its Lanczos bound done
   hipStream_t second = nullptr;  // set once work is queued on the second stream
   ~EventPair() {
     if (second) (void)hipStreamSynchronize(second);
-    if (fork) (void)hipEventDestroy(fork);
-    if (mid) (void)hipEventDestroy(mid);
-    if (join) (void)hipEventDestroy(join);
+    for (hipEvent_t e : {fork, mid, join, reduced, bounds})
+      if (e) (void)hipEventDestroy(e);
   }
 };
 }  // namespace
@@ -693,6 +693,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.fork, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.mid, hipEventDisableTiming));
     GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.join, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.reduced, hipEventDisableTiming));
+    GEVP_HIP_TRY(hipEventCreateWithFlags(&evs.bounds, hipEventDisableTiming));
     // norm estimates (bandwidth-bound) overlap the first, GEMM-bound half of
     // the factorisation
     GEVP_HIP_TRY(hipEventRecord(evs.fork, c->stream));
@@ -759,7 +761,17 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   // ---------------- bounds
   tm.start();
-  GEVP_TRY(lanczos_bounds(c, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw));
+  if (spec) {
+    // the bound of C (bandwidth-bound) goes to the second stream, after its
+    // seed eigensolve, and overlaps the first rotation and C P (GEMM-bound);
+    // the main stream waits for it just before the first controller call
+    GEVP_HIP_TRY(hipEventRecord(evs.reduced, c->stream));
+    GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.reduced, 0));
+    GEVP_TRY(lanczos_bounds(ax, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw2));
+    GEVP_HIP_TRY(hipEventRecord(evs.bounds, ax->stream));
+  } else {
+    GEVP_TRY(lanczos_bounds(c, n, C, n, lz, o.seed ^ 0xC0FFEEull, frac, bC, lanw));
+  }
   if (!spec) {
     GEVP_TRY(lanczos_bounds(c, n, Af, n, lzn, o.seed ^ 0xA11CEull, frac, bA, lanw));
     GEVP_TRY(lanczos_bounds(c, n, Bf, n, lzn, o.seed ^ 0xB0Bull, frac, bB, lanw));
@@ -937,6 +949,7 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     }
     tm.stop(info, GEVP_STAGE_RR);
     info->outer_iters = it + 1;
+    if (spec && it == 0) GEVP_HIP_TRY(hipStreamWaitEvent(c->stream, evs.bounds, 0));
     GEVP_TRY(launch_control(c, cp, theta, rres, bC, norms, tol, st_i, st_d, perm, coefs, rho0,
                             coef2));
     GEVP_HIP_TRY(hipMemcpyAsync(hst.data(), st_i, sizeof(int) * hst.size(), hipMemcpyDeviceToHost, c->stream));
@@ -1040,15 +1053,17 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double hn[2] = {0.0, 0.0};
   GEVP_HIP_TRY(hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, c->stream));
   if (!o.skip_final) {
-    // R = A X - B X diag(lambda): T = B X, then W = A X - diag-scaled T
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, kx, n, 1.0, Bf, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+    // R = A X - B X diag(lambda): T = B X, then W = A X - diag-scaled T, for
+    // the nev wanted columns (all kx when the caller asks for the residuals)
+    const int64_t kr = resid_out ? kx : nev;
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, kr, n, 1.0, Bf, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
                           nullptr, T, n));
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, kx, n, 1.0, Af, n, X, ldx, 0.0, nullptr, 0, -1.0, T, n, theta,
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, kr, n, 1.0, Af, n, X, ldx, 0.0, nullptr, 0, -1.0, T, n, theta,
                           W, n));
-    GEVP_TRY(launch_colnorms(c, n, kx, W, n, fres));
+    GEVP_TRY(launch_colnorms(c, n, kr, W, n, fres));
     if (resid_out) GEVP_TRY(launch_copy_real(c, kx, fres, resid_out));
-    std::vector<double> hr(kx);
-    GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kx, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> hr(kr);
+    GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kr, hipMemcpyDeviceToHost, c->stream));
     GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
     double mx = 0.0;
     for (int64_t i = 0; i < nev; ++i) mx = std::max(mx, hr[i]);

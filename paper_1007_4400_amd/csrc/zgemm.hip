@@ -75,6 +75,23 @@ struct ZgemmParams {
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
 
+// Output tile of linear index `tile`: row-major over all tiles, or, for a
+// lower-triangle launch (p.lower: square output, only tiles on or below the
+// diagonal exist), row-major over the lower triangle of tiles: row tm holds
+// tm + 1 tiles and starts at tm (tm + 1) / 2.
+__device__ __forceinline__ void tile_coords(const ZgemmParams& p, int tile, int& tm, int& tn) {
+  if (p.lower) {
+    int r = (int)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+    while ((int64_t)r * (r + 1) / 2 > tile) --r;  // correct the rounding of the root
+    while ((int64_t)(r + 1) * (r + 2) / 2 <= tile) ++r;
+    tm = r;
+    tn = tile - (int)((int64_t)r * (r + 1) / 2);
+  } else {
+    tm = tile / p.tiles_n;
+    tn = tile - tm * p.tiles_n;
+  }
+}
+
 // One output tile; the operand forms are compile-time constants, so each
 // kernel below carries only its own load and LDS-store pattern.
 template <int OPA, int OPB>
@@ -89,9 +106,9 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
     L = (L & 7) * per + (L >> 3);
   }
   const int kc = L / p.tiles, tile = L - kc * p.tiles;
-  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
+  int tm, tn;
+  tile_coords(p, tile, tm, tn);
   const int row0 = tm * BM, col0 = tn * BN;
-  if (p.lower && col0 > row0 + BM - 1) return;  // tile strictly above the diagonal
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -286,10 +303,10 @@ __global__ __launch_bounds__(256) void k_zgemm_splitk_reduce(ZgemmParams p) {
   const int tile = (int)(e / per);
   const int w = (int)(e - (int64_t)tile * per);
   const int cl = w / BM, rl = w - cl * BM;
-  const int tm = tile / p.tiles_n, tn = tile - tm * p.tiles_n;
+  int tm, tn;
+  tile_coords(p, tile, tm, tn);
   const int row = tm * BM + rl, col = tn * BN + cl;
   if (row >= p.M || col >= p.N) return;
-  if (p.lower && tn * BN > tm * BM + BM - 1) return;
   double ar = 0.0, ai = 0.0;
   for (int kc = 0; kc < p.splits; ++kc) {
     const zd v = p.part[((int64_t)kc * p.tiles + tile) * per + w];
@@ -368,7 +385,12 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.coef = coef;
   p.tiles_n = (int)((n + BN - 1) / BN);
   const int64_t tiles_m = (m + BM - 1) / BM;
-  const int64_t total = tiles_m * p.tiles_n;
+  // a lower-triangle launch enumerates only the tiles on or below the
+  // diagonal (square outputs; BM == BN), so the grid carries no empty
+  // work-groups and the XCD ranges below get equal shares of the work
+  static_assert(BM == BN, "lower-triangle tile enumeration");
+  if (lower && m != n) return GEVP_ERR_INVALID;
+  const int64_t total = lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * p.tiles_n;
   if (total > INT32_MAX) return GEVP_ERR_INVALID;
   p.tiles = (int)total;
   p.lower = lower;
@@ -401,7 +423,13 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   }
   const int64_t blocks = total * p.splits;
   p.total = (int)blocks;
-  p.remap = (blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
+  // XCD-aware order: the hardware deals work-groups to the eight XCDs in
+  // turn; the remap gives each XCD a contiguous range of tiles (rows of
+  // output tiles share their A panel in that XCD's L2).  A product with a
+  // triangular op(A) has tiles of unequal work (row block i runs K from its
+  // first row), so it keeps the dealt order: every XCD then gets every
+  // eighth tile, heavy rows first.
+  p.remap = (!upperA && blocks % 8 == 0 && blocks >= 64) ? 1 : 0;
   const dim3 grid((unsigned)blocks), thr(NTHR);
   // FP64 GEMM timing (profiling bit 4): not the FP64 filter (coef), which is
   // timed as a filter product by the caller

@@ -338,9 +338,11 @@ class Handle:
 
     # ------------------------------------------------------------------ solve
     def solve(self, A, B, nev, X0=None, tol=1e-10, kx=None, opts: Optional[Opts] = None,
-              raise_on_noconv=True):
+              raise_on_noconv=True, want_resid=True):
         """Lowest ``nev`` eigenpairs of A x = lambda B x.  Returns
-        (lam[kx], X[n, kx], resid[kx], info dict)."""
+        (lam[kx], X[n, kx], resid[kx] or None, info dict).  With
+        want_resid=False the per-column residuals are not returned and the
+        final check covers the nev wanted pairs only (info max_resid)."""
         opts = opts or make_opts()
         A, B, X0 = check_solve_args(A, B, nev, X0, self.device)
         n = A.shape[0]
@@ -348,7 +350,7 @@ class Handle:
         dev = A.device
         lam = torch.empty(kx, dtype=torch.float64, device=dev)
         X = empty_colmajor(n, kx, device=dev)
-        res = torch.empty(kx, dtype=torch.float64, device=dev)
+        res = torch.empty(kx, dtype=torch.float64, device=dev) if want_resid else None
         k0 = X0.shape[1] if X0 is not None else 0
         info = Info()
         self._stream()
