@@ -95,6 +95,7 @@ FILTER_KERNELS = {"fp64": "k_zgemm<1>", "fp32": "k_cgemm32_filter", "bf16x3": "k
 KERNEL_SOURCES = {"k_cgemm_bf16x3_filter": "paper_1007_4400_amd/csrc/cgemm_bf16.hip",
                   "k_cgemm32_filter": "paper_1007_4400_amd/csrc/cgemm32.hip",
                   "k_zgemm<1>": "paper_1007_4400_amd/csrc/zgemm.hip",
+                  "k_zgemm_family": "paper_1007_4400_amd/csrc/zgemm.hip",
                   "k_upd_scan": "paper_1007_4400_amd/csrc/update.hip",
                   "k_upd_apply": "paper_1007_4400_amd/csrc/update.hip"}
 
@@ -191,20 +192,29 @@ def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="time
                           "group by kernel_name, counter_name").fetchall()
     except Exception:
         pmc = []
+    names = [a.lstrip("+") for a in kernel_substr.split("|")]
     for kname, cname, val, cnt in pmc:
-        if kernel_substr in kname:
+        if any(nm in kname for nm in names):
             lines.append(f"pmc {cname} avg per dispatch {val:.1f} KiB (x{cnt})  {kname[:80]}")
     if pmc and pmc_last > 0:
-        # the last pmc_last dispatches of the kernel: the launches of the
-        # timed steps (a --pmc run cannot carry the marker range)
+        # the last pmc_last dispatches of the kernel (or family; helper kernels
+        # marked '+' add their bytes but are not counted as dispatches): the
+        # launches of the timed steps (a --pmc run cannot carry the marker range)
         for cname in sorted({r[1] for r in pmc}):
-            vals = [v for (v,) in cur.execute(
-                "select value from counters_collection where kernel_name like ? and counter_name = ? "
-                "order by start", ("%" + kernel_substr + "%", cname)).fetchall()]
-            tail = vals[-pmc_last:]
-            if tail:
-                lines.append(f"pmc {cname} avg per dispatch over the last {len(tail)} (timed) "
-                             f"{sum(tail) / len(tail):.1f} KiB")
+            rows = []
+            for alt in kernel_substr.split("|"):
+                helper = alt.startswith("+")
+                rows += [(st, v, helper) for st, v in cur.execute(
+                    "select start, value from counters_collection where kernel_name like ? and "
+                    "counter_name = ?", ("%" + alt.lstrip("+") + "%", cname)).fetchall()]
+            rows.sort()
+            main_idx = [i for i, r in enumerate(rows) if not r[2]]
+            if len(main_idx) >= 1:
+                first = main_idx[-pmc_last] if len(main_idx) >= pmc_last else main_idx[0]
+                tail = rows[first:]
+                nmain = sum(1 for r in tail if not r[2])
+                lines.append(f"pmc {cname} per dispatch over the last {nmain} (timed) dispatches "
+                             f"(helpers included) {sum(r[1] for r in tail) / max(nmain, 1):.1f} KiB")
     if pmc:
         # the calibration copy (1 GiB read, 1 GiB written) is the largest
         # device copy of the run
@@ -560,8 +570,9 @@ def _roofline_gemm(infos):
     return {
         "bound": "mfma", "kernel": "FP64 complex GEMM family: " + GEMM_FAMILY,
         "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-        "traffic": None,
-        "traffic_note": "no HBM counter summary for this family (MFMA-bound products; K >= 948)",
+        "traffic": committed_traffic("k_zgemm_family"),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated; "
+                        "k_zgemm_splitk_reduce dispatches included)",
         "launches": la, "avg_launch_ms": ms / max(la, 1), "flops_per_launch": fl / max(la, 1),
         "kernel_ms_per_step": ms / max(len(infos), 1),
         "algorithmic_flops_per_unit": "8 flops per complex multiply-add: 8 m n k for a dense product, "
@@ -698,7 +709,8 @@ def run_sequence(args):
     # compared eigenvalue by eigenvalue with the seeded mixed solves
     cold = {}
     dlam = {}
-    steps_cold = [0] + sorted(med)[: args.cold_steps if args.cold_steps >= 0 else None]
+    steps_cold = [] if args.cold_steps == 0 else \
+        [0] + sorted(med)[: args.cold_steps if args.cold_steps > 0 else None]
     for k in steps_cold:
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -712,6 +724,7 @@ def run_sequence(args):
     both = [k for k in med if k in cold]
     sum_cold = sum(cold[k] for k in both)
     sum_seed = sum(med[k] for k in both)
+
     parity["seeded_vs_cold_fp64_lambda_err_max"] = max(dlam.values()) if dlam else None
     parity["seeded_vs_cold_fp64_lambda_err_per_step"] = {str(k): v for k, v in sorted(dlam.items())}
 
@@ -737,7 +750,7 @@ def run_sequence(args):
     # the forms side by side (untimed): one seeded solve of the middle step
     forms = {}
     mid = 6 if 6 in seed_of else sorted(seed_of)[len(seed_of) // 2]
-    if not contour:
+    if not contour and not args.no_side_reports:
         for form in ("fp64", "fp32", "bf16x3"):
             o = gevp.make_opts(precision=form)
             kxf = h.block_size(wl.n, wl.nev, o)
@@ -752,7 +765,7 @@ def run_sequence(args):
     # the last step's result against its seed, and what the monitor adds
     monitor = {}
     try:
-        if contour:
+        if contour or args.no_side_reports:
             raise StopIteration  # the seed monitor side report belongs to the Chebyshev run
         X0m = seed_of[last_k]
         om = gevp.make_opts(precision=args.precision, seed_monitor=True)
@@ -775,7 +788,7 @@ def run_sequence(args):
         monitor = {"error": repr(e)}
 
     value = t_total / args.steps
-    cold_mean = sum(cold[k] for k in both) / max(len(both), 1)
+    cold_mean = sum(cold[k] for k in both) / len(both) if both else None
     if contour:
         return _report_contour(args, wl, K, kx, t_total, [t for _, t in per_step], infos, cold_mean,
                                parity)
@@ -810,7 +823,8 @@ def run_sequence(args):
         "cold_fp64_s_per_step": cold_mean,
         "cold_fp64_per_step_s": {str(k): v for k, v in sorted(cold.items())},
         "speedup_vs_cold_fp64": sum_cold / sum_seed if sum_seed > 0 else None,
-        "speedup_vs_cold_fp64_steps": f"sum over steps {both[0]}..{both[-1]} of cold FP64 / median seeded",
+        "speedup_vs_cold_fp64_steps": (f"sum over steps {both[0]}..{both[-1]} of cold FP64 / median seeded"
+                                       if both else None),
         "speedup_incl_step0": ((sum_cold + cold[0]) / (sum_seed + t_cold0_mixed)
                                if sum_seed > 0 and 0 in cold else None),
         "forms_seeded_one_step": forms,
@@ -842,6 +856,9 @@ def main():
     ap.add_argument("--cold-steps", type=int, default=-1,
                     help="cold FP64 comparator on the first N timed steps (-1: all of them)")
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-side-reports", action="store_true",
+                    help="skip the untimed forms and seed-monitor solves (counter runs: the "
+                         "timed launches are then the last ones of the run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="sequence", choices=["sequence", "batched", "update"],

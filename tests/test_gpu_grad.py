@@ -80,3 +80,69 @@ def test_grad_finite_differences(h):
     fd_a, an_a, fd_b, an_b = map(np.array, (fd_a, an_a, fd_b, an_b))
     assert np.linalg.norm(fd_a - an_a) <= 1e-6 * np.linalg.norm(an_a)
     assert np.linalg.norm(fd_b - an_b) <= 1e-6 * np.linalg.norm(an_b)
+
+
+@pytest.mark.timeout(900)
+def test_grad_finite_differences_cfg5(h):
+    """The differentiation configuration at its own size: n = 4096, nev =
+    410, L = sum_i f_i lambda_i with Fermi-Dirac weights at kT = 0.01 around
+    the 380th eigenvalue, frozen at the base point.  The library's adjoint
+    (gevp_backward) against central finite differences with h = 1e-6 along
+    64 Hermitian directions of unit spectral norm for A and 64 for B, each
+    loss value a full FP64 solve (tol 1e-12, seeded from the base vectors).
+    The noise floor of the differences is measured on 8 directions as the
+    gap between steps h and 2h; the bar is max(1e-6, 3 x floor) on the
+    aggregate error ||FD - an|| / ||an||."""
+    from paper_1007_4400_amd import gevp
+
+    wl = synth.GRAD
+    n, nev = wl.n, wl.nev
+    A0, B0, _, L, g = synth.make_pencil_torch(wl, 5)
+    del L
+    A = gevp.colmajor(A0)
+    B = gevp.colmajor(B0.contiguous())
+    del A0, B0
+    tol = 1e-12
+    kx = h.block_size(n, nev)
+    lam, X, _, info = h.solve(A, B, nev, tol=tol, kx=kx)
+    lam_n = lam[:nev]
+    f = 1.0 / (1.0 + torch.exp((lam_n - lam_n[379]) / 0.01))  # frozen weights
+    dA, dB = h.backward(X[:, :nev], lam_n, f)
+
+    def loss(Ap, Bp):
+        l, _, _, inf = h.solve(Ap, Bp, nev, X0=X, tol=tol, kx=kx, want_resid=False)
+        assert inf["max_resid"] <= tol
+        return float((l[:nev] * f).sum())
+
+    def direction():
+        E = synth.unit_hermitian_torch(n, g)
+        return gevp.colmajor(E.contiguous())
+
+    hstep = 1e-6
+    res = {}
+    for which, G in (("A", dA), ("B", dB)):
+        fd, an, fd2 = [], [], []
+        for j in range(64):
+            E = direction()
+            if which == "A":
+                fp, fm = loss(A + hstep * E, B), loss(A - hstep * E, B)
+            else:
+                fp, fm = loss(A, B + hstep * E), loss(A, B - hstep * E)
+            fd.append((fp - fm) / (2 * hstep))
+            an.append(float(torch.real(torch.sum(torch.conj(G) * E))))
+            if j < 8:  # noise floor: the same difference with step 2h
+                if which == "A":
+                    fp2, fm2 = loss(A + 2 * hstep * E, B), loss(A - 2 * hstep * E, B)
+                else:
+                    fp2, fm2 = loss(A, B + 2 * hstep * E), loss(A, B - 2 * hstep * E)
+                fd2.append((fp2 - fm2) / (4 * hstep))
+            del E
+        fd, an, fd2 = map(np.array, (fd, an, fd2))
+        err = np.linalg.norm(fd - an) / np.linalg.norm(an)
+        floor = np.linalg.norm(fd[:8] - fd2) / np.linalg.norm(an[:8])
+        res[which] = (err, floor)
+        print(f"cfg5 FD d{which}: 64 directions, aggregate rel err {err:.3e}, "
+              f"noise floor (h vs 2h) {floor:.3e}, |an| rms {np.sqrt(np.mean(an ** 2)):.3e}", flush=True)
+    for which, (err, floor) in res.items():
+        assert floor <= 1e-5, (which, floor)
+        assert err <= max(1e-6, 3.0 * floor), (which, err, floor)
