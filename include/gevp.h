@@ -322,6 +322,19 @@ gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n
                          void* D, int64_t ldd);
 
 /*
+ * The structured forms of gevp_k_zgemm that the solver uses internally (no E
+ * term).  lower = 1: square output (m == n), only the 64 x 64 tiles that touch
+ * the lower triangle are computed (entries of tiles entirely above the
+ * diagonal are left as they were; the other entries of the diagonal tiles are
+ * written).  upperA = 1: only the upper triangle of op(A) is used; entries
+ * below its diagonal read as zero whatever the memory holds.  Asynchronous.
+ */
+gevp_status gevp_k_zgemm_tri(gevp_handle h, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                             double beta, const void* Cm, int64_t ldc, void* D, int64_t ldd,
+                             int lower, int upperA);
+
+/*
  * One step of the low-precision residual-correction filter (the Chebyshev
  * recurrence of the mixed-precision forms), per column j < m:
  *   D(:, j) = alpha_j C G(:, j) + beta_j G(:, j) + gamma_j P(:, j) + delta_j R(:, j)

@@ -29,13 +29,16 @@ typedef double2 zd;  // complex128 stored as (re, im)
     if (_s != GEVP_OK) return _s;        \
   } while (0)
 
+// GEVP_LOG=1: failures and per-sweep diagnostics on stderr; GEVP_LOG=2 also
+// prints every timed FP64 GEMM launch (profiling bit 4) with its shape
 int gevp_log_enabled();
 // event pair around one filter product (profiling bit 2), see solver.hip
 gevp_status fev_mark(gevp_ctx* c);
 // event pair around one FP64 GEMM launch (profiling bit 4); gev_end also adds
 // the launch's algorithmic flops to the context's tally
 gevp_status gev_begin(gevp_ctx* c);
-gevp_status gev_end(gevp_ctx* c, double flops);
+// shape = {form (opA * 2 + opB), m, n, k, split-K factor, work-groups}
+gevp_status gev_end(gevp_ctx* c, double flops, const int64_t* shape = nullptr);
 int gevp_device_cus(int device);  // compute units of a device (cached)
 
 struct gevp_ctx {
@@ -55,6 +58,7 @@ struct gevp_ctx {
   int gev_cap = 0;
   int gev_used = 0;
   double gev_flops = 0.0;
+  std::vector<double> gev_shape;  // GEVP_LOG=2: 7 values per timed launch (shape, flops)
   // split-K partial products of launch_zgemm (grown on demand, freed by destroy)
   void* skw = nullptr;
   size_t skw_bytes = 0;
@@ -105,9 +109,9 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 // D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E   (FP64 MFMA, complex128)
 // When `coef` (device double[3]) is non-null it supplies alpha, beta, gamma.
 // lower = 1 computes only the 64 x 64 tiles that touch the lower triangle
-// (Hermitian updates whose upper triangle is never read).  upperA = 1 declares
-// op(A) upper triangular (e.g. L^H): each output row block skips the K range
-// below its first row.  Products with few
+// (Hermitian updates whose upper triangle is never read).  upperA = 1 uses only
+// the upper triangle of op(A) (e.g. L^H): each output row block skips the K
+// range below its first row and entries below op(A)'s diagonal read as zero.  Products with few
 // output tiles and a long K run split-K through c->skw (see zgemm.hip).
 gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
@@ -189,7 +193,6 @@ gevp_status heev_small(gevp_ctx* c, int64_t n, zd* H, int64_t ldh, double* theta
 // elementwise / reduction kernels (vec_kernels.hip)
 gevp_status launch_mirror_lower(gevp_ctx* c, int64_t n, const zd* S, int64_t lds, zd* D,
                                 int64_t ldd, int* flag_nonfinite);
-gevp_status launch_symmetrize(gevp_ctx* c, int64_t n, zd* M, int64_t ldm);
 gevp_status launch_copy2d(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                           zd* D, int64_t ldd);
 gevp_status launch_check_finite(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S,
@@ -228,7 +231,11 @@ gevp_status launch_permute_prefix(gevp_ctx* c, double* theta, double* resid, con
                                   int64_t nl);
 gevp_status launch_merge_runs(gevp_ctx* c, double* theta, double* resid, int64_t nb, int64_t nl,
                               int* order);
-gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out);
+// out[0] = max |M - I| over the lower triangle of M (n >= 1); part: scratch
+// of MAX_OFFIDENT_PARTS doubles
+constexpr int MAX_OFFIDENT_PARTS = 128;
+gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out,
+                                double* part);
 
 // Lanczos bounds: runs `steps` steps on the Hermitian M (full storage) and
 // writes into out[0..5]: theta_min, theta_max, beta_last, upper bound

@@ -57,7 +57,7 @@ int gevp_log_enabled() {
   static int v = -1;
   if (v < 0) {
     const char* s = getenv("GEVP_LOG");
-    v = (s && s[0] == '1') ? 1 : 0;
+    v = (s && (s[0] == '1' || s[0] == '2')) ? s[0] - '0' : 0;
   }
   return v;
 }
@@ -125,9 +125,13 @@ gevp_status gev_begin(gevp_ctx* c) {
   return ev_record(c, c->gev, c->gev_cap, c->gev_used);
 }
 
-gevp_status gev_end(gevp_ctx* c, double flops) {
+gevp_status gev_end(gevp_ctx* c, double flops, const int64_t* shape) {
   if (!(c->profiling & 4)) return GEVP_OK;
   c->gev_flops += flops;
+  if (shape && gevp_log_enabled() >= 2) {
+    for (int i = 0; i < 6; ++i) c->gev_shape.push_back((double)shape[i]);
+    c->gev_shape.push_back(flops);
+  }
   return ev_record(c, c->gev, c->gev_cap, c->gev_used);
 }
 
@@ -268,15 +272,18 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
   if (skipped) *skipped = false;
   for (int pass = 0; pass < 2; ++pass) {
     GEVP_TRY(launch_colnorm_scale(c, n, m, P, ldp));
+    // the Gram matrix's lower triangle only: the factorisation and the check
+    // below read nothing else
     GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, w.G, m));
+                          nullptr, w.G, m, nullptr, 1));
     // An orthonormal seed needs no pass at all, and a first pass that already
     // left the block orthonormal to 5e-13 needs no second one: the Gram
     // matrix is formed either way, and the check replaces the host read of
     // the Cholesky's status.
     if ((pass == 0 && try_skip) || pass == 1) {
       double dev = 1.0;
-      GEVP_TRY(launch_max_offident(c, m, w.G, m, w.shift + 1));
+      // partial maxima in Dg, whose inverse blocks the last solve has consumed
+      GEVP_TRY(launch_max_offident(c, m, w.G, m, w.shift + 1, reinterpret_cast<double*>(w.Dg)));
       GEVP_HIP_TRY(hipMemcpyAsync(&dev, w.shift + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
       if (dev <= 5e-13) {
@@ -297,7 +304,7 @@ gevp_status cholqr2(gevp_ctx* c, int64_t n, int64_t m, zd* P, int64_t ldp, QrWor
       const double u = 1.1102230246251565e-16;
       const double s = 11.0 * ((double)n * m + (double)m * (m + 1)) * u * (double)m;
       GEVP_TRY(launch_zgemm(c, 1, 0, m, m, n, 1.0, P, ldp, P, ldp, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                            nullptr, w.G, m));
+                            nullptr, w.G, m, nullptr, 1));
       GEVP_HIP_TRY(hipMemcpyAsync(w.shift, &s, sizeof(double), hipMemcpyHostToDevice, c->stream));
       GEVP_TRY(launch_add_diag(c, m, w.G, m, w.shift));
       GEVP_HIP_TRY(hipMemcpyAsync(w.flag, &big, sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -335,7 +342,16 @@ gevp_status gev_collect(gevp_ctx* c, gevp_info* info) {
     float ms = 0.f;
     GEVP_HIP_TRY(hipEventElapsedTime(&ms, c->gev[i], c->gev[i + 1]));
     tot += ms;
+    const size_t r = (size_t)(i / 2) * 7;
+    if (r + 7 <= c->gev_shape.size()) {
+      const double* g = c->gev_shape.data() + r;
+      static const char* form[4] = {"NN", "NC", "CN", "CC"};
+      fprintf(stderr, "[gevp] gemm stream %p %s m %lld n %lld k %lld split %lld wg %lld %.4f ms %.1f TFLOP/s\n",
+              (void*)c->stream, form[(int)g[0] & 3], (long long)g[1], (long long)g[2], (long long)g[3],
+              (long long)g[4], (long long)g[5], ms, ms > 0 ? g[6] / (ms * 1e9) : 0.0);
+    }
   }
+  c->gev_shape.clear();
   info->gemm_kernel_ms += tot;
   info->gemm_launches += c->gev_used / 2;
   info->gemm_flops += c->gev_flops;
@@ -720,8 +736,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       GEVP_TRY(launch_zgemm(ax, 0, 0, n, nb, n, 1.0, Af, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, T, n));
       GEVP_TRY(launch_zgemm(ax, 1, 0, nb, nb, n, 1.0, X0, ldx0, T, n, 0.0, nullptr, 0, 0.0, nullptr,
-                            0, nullptr, Hs, nb));
-      GEVP_TRY(launch_symmetrize(ax, nb, Hs, nb));
+                            0, nullptr, Hs, nb, nullptr, 1));
+      GEVP_TRY(launch_mirror_lower(ax, nb, Hs, nb, Hs, nb, nullptr));
       return heev_small(ax, nb, Hs, nb, theta, Zs, nb, heevw);
     };
     const gevp_status sst = second();
@@ -738,18 +754,19 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
     return GEVP_ERR_NOT_HPD;
   }
 
-  // C-space seed y = L^H x, while L's upper triangle is still zero (the
-  // product skips only the zero tiles of L^H)
+  // from here on the upper triangle of L holds L^H, so the products and
+  // solves with L^H multiply blocks as stored (the faster operand form of the
+  // GEMM)
+  GEVP_TRY(launch_mirror_lower(c, n, L, n, L, n, flags + 3));
+  // C-space seed y = L^H x: the upper triangle of L as stored (the product
+  // skips the K range below each row block's diagonal)
   if (seeded)
-    GEVP_TRY(launch_zgemm(c, 1, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, k0, n, 1.0, L, n, X0, ldx0, 0.0, nullptr, 0, 0.0, nullptr, 0,
                           nullptr, P0, n, nullptr, 0, 1));
   if (monitor) GEVP_TRY(launch_copy2d(c, n, km, P0, n, Y0s, n));  // the seed y0 = L^H x0, kept
 
   // ---------------- reduction to standard form
   tm.start();
-  // from here on the upper triangle of L holds L^H, so the solves with L^H
-  // multiply blocks as stored (the faster operand form of the GEMM)
-  GEVP_TRY(launch_mirror_lower(c, n, L, n, L, n, flags + 3));
   GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
   GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
   // C = W L^{-H} is Hermitian: only its lower triangle is formed, then mirrored
@@ -909,8 +926,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       GEVP_TRY(launch_zgemm(c, 0, 0, n, na, n, 1.0, C, n, Pa, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
                             nullptr, Wa, n));
       GEVP_TRY(launch_zgemm(c, 1, 0, na, na, n, 1.0, Pa, n, Wa, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                            nullptr, Hs, na));
-      GEVP_TRY(launch_symmetrize(c, na, Hs, na));
+                            nullptr, Hs, na, nullptr, 1));
+      GEVP_TRY(launch_mirror_lower(c, na, Hs, na, Hs, na, nullptr));
       GEVP_TRY(heev_small(c, na, Hs, na, theta + l0, Zs, na, heevw));
       GEVP_TRY(launch_zgemm(c, 0, 0, n, na, na, 1.0, Pa, n, Zs, na, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, P1 + l0 * n, n));
@@ -928,8 +945,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
       GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, n, 1.0, C, n, P0, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
                             nullptr, W, n));
       GEVP_TRY(launch_zgemm(c, 1, 0, nb, nb, n, 1.0, P0, n, W, n, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                            nullptr, Hs, nb));
-      GEVP_TRY(launch_symmetrize(c, nb, Hs, nb));
+                            nullptr, Hs, nb, nullptr, 1));
+      GEVP_TRY(launch_mirror_lower(c, nb, Hs, nb, Hs, nb, nullptr));
       GEVP_TRY(heev_small(c, nb, Hs, nb, theta, Zs, nb, heevw));
       GEVP_TRY(launch_zgemm(c, 0, 0, n, nb, nb, 1.0, P0, n, Zs, nb, 0.0, nullptr, 0, 0.0, nullptr,
                             0, nullptr, P1, n));
@@ -1250,6 +1267,26 @@ gevp_status gevp_k_zgemm(gevp_handle h, char opA, char opB, int64_t m, int64_t n
   GEVP_HIP_TRY(hipSetDevice(h->device));
   return launch_zgemm(h, oa, ob, m, n, k, alpha, (const zd*)A, lda, (const zd*)B, ldb, beta,
                       (const zd*)Cm, ldc, gamma, (const zd*)E, lde, gcol, (zd*)D, ldd);
+}
+
+gevp_status gevp_k_zgemm_tri(gevp_handle h, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                             double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                             double beta, const void* Cm, int64_t ldc, void* D, int64_t ldd,
+                             int lower, int upperA) {
+  if (!h || m < 0 || n < 0 || k < 0 || !D) return GEVP_ERR_INVALID;
+  if ((lower != 0 && lower != 1) || (upperA != 0 && upperA != 1) || (lower && m != n))
+    return GEVP_ERR_INVALID;
+  const int oa = (opA == 'C' || opA == 'c') ? 1 : 0;
+  const int ob = (opB == 'C' || opB == 'c') ? 1 : 0;
+  if (!(opA == 'N' || opA == 'n' || oa) || !(opB == 'N' || opB == 'n' || ob)) return GEVP_ERR_INVALID;
+  if (k > 0 && (!A || !B)) return GEVP_ERR_INVALID;
+  if (k > 0 && lda < (oa ? k : m)) return GEVP_ERR_INVALID;
+  if (k > 0 && ldb < (ob ? n : k)) return GEVP_ERR_INVALID;
+  if (ldd < m || (Cm && ldc < m)) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  return launch_zgemm(h, oa, ob, m, n, k, alpha, (const zd*)A, lda, (const zd*)B, ldb, beta,
+                      (const zd*)Cm, ldc, 0.0, nullptr, 0, nullptr, (zd*)D, ldd, nullptr, lower,
+                      upperA);
 }
 
 gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t m,

@@ -32,28 +32,36 @@ __device__ __forceinline__ bool finite2(zd v) { return isfinite(v.x) && isfinite
 
 // Full Hermitian copy from the lower triangle, 32 x 32 tiles through LDS so
 // the conjugate-transposed half is written coalesced.  Only tiles on or below
-// the diagonal are launched.
+// the diagonal are launched.  In place (S == D) the strict lower triangle is
+// not written at all, and a diagonal entry only when its imaginary part has
+// to be cleared, so other streams may read the lower triangle meanwhile.
 __global__ __launch_bounds__(256) void k_mirror_lower(const zd* S, int64_t lds, zd* D, int64_t ldd,
                                                       int64_t n, int* flag) {
   __shared__ zd t[32][33];
   const int64_t bi = blockIdx.x, bj = blockIdx.y;
   if (bi < bj) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const bool inplace = (S == D && lds == ldd);
   bool bad = false;
   for (int r = ty; r < 32; r += 8) {
     const int64_t i = bi * 32 + tx, j = bj * 32 + r;  // element (i, j), column j
     zd v = make_double2(0.0, 0.0);
     if (i < n && j < n && i >= j) {
       v = S[i + j * lds];
-      if (i == j) v.y = 0.0;
+      if (i == j) {
+        if (inplace && v.y != 0.0) D[i + j * ldd] = make_double2(v.x, 0.0);
+        v.y = 0.0;
+      }
       bad |= !finite2(v);
     }
     t[r][tx] = v;  // t[col][row]
   }
   __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
-    if (i < n && j < n && i >= j) D[i + j * ldd] = t[r][tx];
+  if (!inplace) {
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+      if (i < n && j < n && i >= j) D[i + j * ldd] = t[r][tx];
+    }
   }
   // conjugate transpose: D(j, i) = conj(S(i, j)) for i > j
   for (int r = ty; r < 32; r += 8) {
@@ -63,32 +71,7 @@ __global__ __launch_bounds__(256) void k_mirror_lower(const zd* S, int64_t lds, 
       D[row + col * ldd] = make_double2(v.x, -v.y);
     }
   }
-  if (bad) atomicOr(flag, 1);
-}
-
-__global__ __launch_bounds__(256) void k_symmetrize(zd* M, int64_t ldm, int64_t n) {
-  __shared__ zd a[32][33], b[32][33];
-  const int64_t bi = blockIdx.x, bj = blockIdx.y;
-  if (bi < bj) return;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bi * 32 + tx, j = bj * 32 + r;  // lower tile element
-    a[r][tx] = (i < n && j < n) ? M[i + j * ldm] : make_double2(0.0, 0.0);
-    const int64_t i2 = bj * 32 + tx, j2 = bi * 32 + r;  // mirrored tile element
-    b[r][tx] = (i2 < n && j2 < n) ? M[i2 + j2 * ldm] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  // lower element (i, j) = (bi*32+tx, bj*32+r) pairs with upper (j, i) = b[tx][r]
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
-    if (i < n && j < n && i >= j) {
-      const zd lo = a[r][tx], up = b[tx][r];
-      zd h = make_double2(0.5 * (lo.x + up.x), 0.5 * (lo.y - up.y));
-      if (i == j) h.y = 0.0;
-      M[i + j * ldm] = h;
-      M[j + i * ldm] = make_double2(h.x, -h.y);
-    }
-  }
+  if (bad && flag) atomicOr(flag, 1);
 }
 
 __global__ void k_copy2d(int64_t rows, int64_t cols, const zd* S, int64_t lds, zd* D, int64_t ldd) {
@@ -432,11 +415,13 @@ __global__ void k_copy_real(int64_t n, const double* s, double* d) {
 // out[0] = max_ij |M(i,j) - delta_ij| (one work-group)
 // max |M - I| over all entries; a non-finite entry gives +inf (fmax alone
 // would drop a NaN), so a block with NaN never passes a tolerance test
-__global__ __launch_bounds__(1024) void k_max_offident(int64_t n, const zd* M, int64_t ldm, double* out) {
-  __shared__ double sh[1024];
+// max |M - I| over the lower triangle of a Hermitian M (the upper triangle is
+// not read): one partial maximum per work-group, columns dealt round-robin
+__global__ __launch_bounds__(256) void k_max_offident(int64_t n, const zd* M, int64_t ldm, double* part) {
+  __shared__ double sh[256];
   double mx = 0.0;
-  for (int64_t j = 0; j < n; ++j)
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x)
+    for (int64_t i = j + threadIdx.x; i < n; i += 256) {
       zd v = M[i + j * ldm];
       if (i == j) v.x -= 1.0;
       const double h = hypot(v.x, v.y);
@@ -444,7 +429,20 @@ __global__ __launch_bounds__(1024) void k_max_offident(int64_t n, const zd* M, i
     }
   sh[threadIdx.x] = mx;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_parts(int cnt, const double* part, double* out) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += 256) mx = fmax(mx, part[i]);  // partials are never NaN
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
@@ -462,14 +460,6 @@ gevp_status launch_mirror_lower(gevp_ctx* c, int64_t n, const zd* S, int64_t lds
   if (n <= 0) return GEVP_OK;
   const unsigned t = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(k_mirror_lower, dim3(t, t), dim3(256), 0, c->stream, S, lds, D, ldd, n, flag);
-  GEVP_HIP_TRY(hipGetLastError());
-  return GEVP_OK;
-}
-
-gevp_status launch_symmetrize(gevp_ctx* c, int64_t n, zd* M, int64_t ldm) {
-  if (n <= 0) return GEVP_OK;
-  const unsigned t = (unsigned)((n + 31) / 32);
-  hipLaunchKernelGGL(k_symmetrize, dim3(t, t), dim3(256), 0, c->stream, M, ldm, n);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }
@@ -701,8 +691,13 @@ gevp_status launch_copy_real(gevp_ctx* c, int64_t n, const double* s, double* d)
   return GEVP_OK;
 }
 
-gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out) {
-  hipLaunchKernelGGL(k_max_offident, dim3(1), dim3(1024), 0, c->stream, n, M, ldm, out);
+gevp_status launch_max_offident(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, double* out,
+                                double* part) {
+  if (n <= 0) return GEVP_ERR_INVALID;
+  const int g = (int)std::min<int64_t>(n, MAX_OFFIDENT_PARTS);
+  hipLaunchKernelGGL(k_max_offident, dim3(g), dim3(256), 0, c->stream, n, M, ldm, part);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(256), 0, c->stream, g, part, out);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

@@ -28,8 +28,11 @@
 // part, plus the reduction); each writes its raw partial tile to the
 // handle's buffer and a second kernel sums the parts in a fixed order and
 // applies the epilogue, so results do not depend on scheduling.  upperA = 1
-// declares op(A) upper triangular (L^H): a row block starts its K walk at
-// its own first row.
+// declares op(A) upper triangular (L^H, or the upper triangle of a matrix
+// whose lower triangle holds something else): a row block starts its K walk
+// at its own first row, and the entries below the diagonal of op(A) read as
+// zero, so only the upper triangle is ever used.  A split whose K range lies
+// entirely below a row block's diagonal contributes a zero partial tile.
 #include <atomic>
 
 #include <algorithm>
@@ -133,10 +136,10 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
   do {                                                                                \
     if (opA == 0) {                                                                   \
       const int gm_ = row0 + (tid & 63), gk_ = k0 + (tid >> 6) + 4 * (i);             \
-      dst = (gm_ < p.M && gk_ < p.K) ? p.A[gm_ + (int64_t)gk_ * p.lda]: make_double2(0.0, 0.0);      \
+      dst = (gm_ < p.M && gk_ < p.K && !(p.upperA && gk_ < gm_)) ? p.A[gm_ + (int64_t)gk_ * p.lda]: make_double2(0.0, 0.0); \
     } else {                                                                          \
       const int gk_ = k0 + (tid & 15), gm_ = row0 + (tid >> 4) + 16 * (i);            \
-      dst = (gm_ < p.M && gk_ < p.K) ? zconj(p.A[gk_ + (int64_t)gm_ * p.lda]) : make_double2(0.0, 0.0); \
+      dst = (gm_ < p.M && gk_ < p.K && !(p.upperA && gk_ < gm_)) ? zconj(p.A[gk_ + (int64_t)gm_ * p.lda]) : make_double2(0.0, 0.0); \
     }                                                                                 \
   } while (0)
 #define LDB_(i, dst)                                                                  \
@@ -396,7 +399,7 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.lower = lower;
   const int nk = (p.K + KT - 1) / KT;
   p.upperA = upperA;
-  int s = (upperA || c->no_split)
+  int s = c->no_split
               ? 1
               : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
   p.nks = nk > 0 ? (nk + s - 1) / s : 1;
@@ -465,7 +468,8 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
       const double rows = std::min(md, kd);  // row i of op(A) starts at column i
       fl = 8.0 * nd * (rows * kd - rows * (rows - 1.0) * 0.5);
     }
-    GEVP_TRY(gev_end(c, fl));
+    const int64_t shape[6] = {opA * 2 + opB, m, n, p.K, p.splits, blocks};
+    GEVP_TRY(gev_end(c, fl, shape));
   }
   return GEVP_OK;
 }

@@ -126,6 +126,8 @@ def load():
     lib.gevp_backward_noalloc.restype = I
     lib.gevp_k_zgemm.argtypes = [P, C, C, L, L, L, D, P, L, P, L, D, P, L, D, P, L, P, P, L]
     lib.gevp_k_zgemm.restype = I
+    lib.gevp_k_zgemm_tri.argtypes = [P, C, C, L, L, L, D, P, L, P, L, D, P, L, P, L, I, I]
+    lib.gevp_k_zgemm_tri.restype = I
     lib.gevp_k_filter_gemm.argtypes = [P, I, L, L, P, L, P, L, P, L, P, L, P, L, P, P, P, P]
     lib.gevp_k_filter_gemm.restype = I
     lib.gevp_k_potrf.argtypes = [P, L, P, L, ctypes.POINTER(L)]
@@ -447,6 +449,30 @@ class Handle:
                                   _ld(E) if E is not None else m, _ptr(gcol), _ptr(out), _ld(out))
         if s != GEVP_OK:
             raise GevpError(s, "gevp_k_zgemm")
+        return out
+
+    def zgemm_tri(self, opA, opB, A, B, out, alpha=1.0, beta=0.0, C=None, lower=False,
+                  upperA=False):
+        """The structured products (gevp_k_zgemm_tri): `out` is written in
+        place (lower: only tiles touching the lower triangle)."""
+        if opA not in ("N", "C") or opB not in ("N", "C"):
+            raise ValueError("opA and opB must be 'N' or 'C'")
+        A = _check_mat(A, "A", self.device)
+        B = _check_mat(B, "B", self.device)
+        out = _check_mat(out, "out", self.device)
+        m = A.shape[0] if opA == "N" else A.shape[1]
+        k = A.shape[1] if opA == "N" else A.shape[0]
+        n = B.shape[1] if opB == "N" else B.shape[0]
+        if (B.shape[0] if opB == "N" else B.shape[1]) != k or tuple(out.shape) != (m, n):
+            raise ValueError("operand shapes do not agree")
+        C = _check_mat(C, "C", self.device, rows=m, cols=n) if C is not None else None
+        self._stream()
+        s = self.lib.gevp_k_zgemm_tri(self.h, opA.encode(), opB.encode(), m, n, k, float(alpha),
+                                      _ptr(A), _ld(A), _ptr(B), _ld(B), float(beta), _ptr(C),
+                                      _ld(C) if C is not None else m, _ptr(out), _ld(out),
+                                      int(bool(lower)), int(bool(upperA)))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_zgemm_tri")
         return out
 
     def filter_gemm(self, precision, C, G, P, R, alpha, beta, gamma, delta):

@@ -65,6 +65,55 @@ def test_zgemm_plain_and_inplace_beta(h):
 
 
 # panel boundaries of the factorisation (384-wide panels of 64-wide blocks)
+@pytest.mark.parametrize("opA,opB", [("C", "N"), ("N", "C"), ("N", "N")])
+@pytest.mark.parametrize("n,k", [(200, 70), (948, 8192), (130, 4000)])
+def test_zgemm_lower_triangle_tiles(h, opA, opB, n, k):
+    """Lower-triangle launches (Gram and projected matrices): the tiles that
+    touch the lower triangle hold the product, the tiles entirely above the
+    diagonal are left as they were.  (948, 8192) runs split-K."""
+    from paper_1007_4400_amd import gevp
+
+    print(f"zgemm lower {opA}{opB} n={n} k={k}", flush=True)
+    rng = np.random.default_rng(n + k)
+    A = _cn(rng, *((n, k) if opA == "N" else (k, n)))
+    B = _cn(rng, *((k, n) if opB == "N" else (n, k)))
+    D0 = _cn(rng, n, n)
+    opa = A if opA == "N" else A.conj().T
+    opb = B if opB == "N" else B.conj().T
+    ref = opa @ opb
+    out = h.zgemm_tri(opA, opB, _dev(A), _dev(B), gevp.colmajor(_dev(D0)), lower=True)
+    torch.cuda.synchronize()
+    got = _np(out)
+    ti, tj = np.meshgrid(np.arange(n) // 64, np.arange(n) // 64, indexing="ij")
+    computed = ti >= tj
+    scale = np.abs(opa) @ np.abs(opb)
+    assert np.max(np.abs(got - ref)[computed] / scale[computed]) <= 1e-14 * np.sqrt(k)
+    assert np.array_equal(got[~computed], D0[~computed])
+
+
+@pytest.mark.parametrize("opA", ["N", "C"])
+@pytest.mark.parametrize("m,n,beta", [(300, 70, 0.0), (1000, 130, -0.5), (8192, 96, 0.0)])
+def test_zgemm_upper_triangular_a(h, opA, m, n, beta):
+    """upperA launches use only the upper triangle of op(A): whatever lies
+    below its diagonal (here random values) reads as zero.  (8192, 96) runs
+    split-K, with splits that lie entirely below a row block's diagonal."""
+    print(f"zgemm upperA {opA} m={m} n={n}", flush=True)
+    rng = np.random.default_rng(m + 7 * n)
+    A = _cn(rng, m, m)
+    B = _cn(rng, m, n)
+    C = _cn(rng, m, n)
+    opa = A if opA == "N" else A.conj().T
+    ref = np.triu(opa) @ B + beta * C
+    from paper_1007_4400_amd import gevp
+
+    out = gevp.empty_colmajor(m, n, device=torch.device("cuda"))
+    out = h.zgemm_tri(opA, "N", _dev(A), _dev(B), out, beta=beta,
+                      C=_dev(C) if beta != 0.0 else None, upperA=True)
+    torch.cuda.synchronize()
+    scale = np.abs(np.triu(opa)) @ np.abs(B) + abs(beta) * np.abs(C)
+    assert np.max(np.abs(_np(out) - ref) / scale) <= 1e-14 * np.sqrt(m)
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 333, 383, 384, 385, 769, 1000])
 def test_potrf(h, n):
     print(f"potrf n={n}", flush=True)
