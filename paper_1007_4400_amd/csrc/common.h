@@ -59,6 +59,15 @@ struct gevp_ctx {
   int gev_used = 0;
   double gev_flops = 0.0;
   std::vector<double> gev_shape;  // GEVP_LOG=2: 7 values per timed launch (shape, flops)
+  // replayable launch sequences (the tridiagonalisation's one launch per
+  // reflector, heev.hip): executable graphs keyed by their kernel arguments,
+  // captured on a private stream, released by destroy
+  struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
   // split-K partial products of launch_zgemm (grown on demand, freed by destroy)
   void* skw = nullptr;
   size_t skw_bytes = 0;

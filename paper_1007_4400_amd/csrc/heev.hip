@@ -628,6 +628,65 @@ size_t heev_work_bytes(int64_t n) {
   return b;
 }
 
+// One launch per reflector: the kernel boundary is the grid-wide barrier (a
+// cooperative single launch with explicit barriers measured slower, because
+// each barrier must write back and invalidate the XCD caches).  Issued one by
+// one, the launches cost the host about 4.4 us each at n = 948, more than the
+// later, shorter steps take on the GPU; so the sequence is captured once per
+// argument set into a graph and replayed (the first call also pays the
+// capture).  Any failure of the graph calls falls back to direct launches.
+namespace {
+constexpr size_t MAX_GRAPHS = 8;
+
+gevp_status hetrd_direct(gevp_ctx* c, hipStream_t st, const TrdArgs& a, int G, size_t sh3) {
+  for (int s = 0; s <= a.n - 1; ++s) {
+    hipLaunchKernelGGL(k_hetrd_step, dim3(G), dim3(HT), sh3, st, a, s);
+    GEVP_HIP_TRY(hipGetLastError());
+  }
+  return GEVP_OK;
+}
+
+gevp_status hetrd_launches(gevp_ctx* c, const TrdArgs& a, int G, size_t sh3) {
+  const std::vector<int64_t> key = {a.n, G, (int64_t)(uintptr_t)a.H, a.ldh, (int64_t)(uintptr_t)a.V,
+                                    a.ldv, (int64_t)(uintptr_t)a.tau, (int64_t)(uintptr_t)a.d,
+                                    (int64_t)(uintptr_t)a.e, (int64_t)(uintptr_t)a.pb,
+                                    (int64_t)(uintptr_t)a.pp, (int64_t)sh3};
+  for (gevp_ctx::GraphEntry& g : c->graphs)
+    if (g.key == key) {
+      if (hipGraphLaunch(g.exec, c->stream) == hipSuccess) return GEVP_OK;
+      (void)hipGetLastError();
+      return hetrd_direct(c, c->stream, a, G, sh3);
+    }
+  if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->cap_stream = nullptr;
+    (void)hipGetLastError();
+    return hetrd_direct(c, c->stream, a, G, sh3);
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const gevp_status st = hetrd_direct(c, c->cap_stream, a, G, sh3);
+    ok = (hipStreamEndCapture(c->cap_stream, &graph) == hipSuccess) && st == GEVP_OK && graph;
+  }
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    (void)hipGetLastError();
+    if (gevp_log_enabled()) fprintf(stderr, "[gevp] tridiagonalisation graph unavailable: direct launches\n");
+    return hetrd_direct(c, c->stream, a, G, sh3);
+  }
+  if (c->graphs.size() >= MAX_GRAPHS) {  // the oldest may still run on the stream
+    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({key, exec});
+  GEVP_HIP_TRY(hipGraphLaunch(exec, c->stream));
+  return GEVP_OK;
+}
+}  // namespace
+
 gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* theta, zd* Z,
                        int64_t ldz, void* work) {
   if (n64 <= 0) return GEVP_OK;
@@ -671,13 +730,7 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
     GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd), c->stream));
   } else {
     GEVP_HIP_TRY(hipMemsetAsync(a.tau, 0, sizeof(zd) * n, c->stream));
-    // one launch per reflector: the kernel boundary is the grid-wide barrier
-    // (a cooperative single launch with explicit barriers measured slower,
-    // because each barrier must write back and invalidate the XCD caches)
-    for (int s = 0; s <= n - 1; ++s) {
-      hipLaunchKernelGGL(k_hetrd_step, dim3(G), dim3(HT), sh3, c->stream, a, s);
-      GEVP_HIP_TRY(hipGetLastError());
-    }
+    GEVP_TRY(hetrd_launches(c, a, G, sh3));
   }
   GEVP_TRY(tridiag_eig(c, n, a.d, a.e, theta, Zt, tw));
   const unsigned tb = (unsigned)((n + 31) / 32);

@@ -168,6 +168,33 @@ def test_heev_vs_oracle(h, n, oracle_mod):
     assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10
 
 
+def test_heev_replayed_sequence(h):
+    """The tridiagonalisation's launches are captured once per argument set
+    and replayed: consecutive eigensolves of different matrices of one order
+    (same workspace, so the same captured sequence) each match numpy's
+    eigenvalues and give their own eigenvectors; a fresh handle (captures
+    anew) gives bitwise the same results as the replays."""
+    from paper_1007_4400_amd import gevp
+
+    n = 300
+    rng = np.random.default_rng(11)
+    outs = []
+    for r in range(3):
+        G = _cn(rng, n, n)
+        H = 0.5 * (G + G.conj().T) + r * np.eye(n)
+        th, Z = h.heev(_dev(H))
+        th, Z = _np(th), _np(Z)
+        lam = np.linalg.eigvalsh(H)
+        nrm = max(1.0, np.max(np.abs(lam)))
+        assert np.max(np.abs(th - lam)) <= 1e-13 * nrm * np.sqrt(n)
+        assert np.max(np.abs(H @ Z - Z * th[None, :])) <= 1e-12 * nrm * np.sqrt(n)
+        outs.append((H, th, Z))
+    h2 = gevp.Handle(0)
+    th2, Z2 = h2.heev(_dev(outs[-1][0]))
+    assert np.array_equal(_np(th2), outs[-1][1]) and np.array_equal(_np(Z2), outs[-1][2])
+    h2.close()
+
+
 @pytest.mark.parametrize("n", [40, 300])
 def test_heev_degenerate(h, oracle_mod, n):
     # repeated eigenvalues: an invariant subspace, not unique vectors
