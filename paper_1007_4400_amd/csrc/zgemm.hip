@@ -45,6 +45,7 @@ namespace {
 constexpr int BM = 64, BN = 64, KT = 16, NTHR = 256;
 constexpr int PADA = BM + 1, PADB = BN + 1;
 constexpr int64_t SPLIT_TILES_MAX = 2048;  // partial tiles the split-K buffer holds (128 MiB)
+constexpr int SKINNY_K_MAX = 1024;         // longest K for the skinny-tile kernels
 static_assert(SKW_BYTES == (size_t)SPLIT_TILES_MAX * 64 * 64 * 16, "split-K buffer size");
 // The in-place base cases of the triangular solves rely on a 64-wide block
 // fitting in one output tile.
@@ -297,6 +298,120 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm_nc(ZgemmParams p) { zgemm_til
 __global__ __launch_bounds__(NTHR, 2) void k_zgemm_cn(ZgemmParams p) { zgemm_tile<1, 0>(p); }
 __global__ __launch_bounds__(NTHR, 2) void k_zgemm_cc(ZgemmParams p) { zgemm_tile<1, 1>(p); }
 
+// Skinny tiles for products with at most 64 rows (TALL: 64 x 16 output
+// tiles) or at most 64 columns (16 x 64 tiles) and a short K: the base cases
+// and 64-wide updates of the triangular solves and the panel products of the
+// Cholesky factorisation.  With 64 x 64 tiles such a product has one tile per
+// 64 columns (or rows), so 15 work-groups for a 64 x 948 result, and each of
+// their waves runs a chain of 16 MFMAs per 4 K; here each of the four waves
+// owns one 16 x 16 block (4 MFMAs per 4 K), so the work-groups are four times
+// as many and their chains four times shorter.  A tile still spans every row
+// (TALL) or every column (wide) of the result, so a base case that writes its
+// right operand in place (TALL) or its left operand in place (wide) reads its
+// whole K range before it writes, as with the 64 x 64 tiles.
+template <int OPA, int OPB, int TALL>
+__global__ __launch_bounds__(NTHR) void k_zgemm_sk(ZgemmParams p) {
+  constexpr int SM = TALL ? 64 : 16, SN = TALL ? 16 : 64;
+  __shared__ zd As[2][KT][SM + 1];
+  __shared__ zd Bs[2][KT][SN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_n = (p.N + SN - 1) / SN;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
+  const int row0 = tm * SM, col0 = tn * SN;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int bm = TALL ? wave : 0, bn = TALL ? 0 : wave;  // this wave's 16 x 16 block
+  d4 accR = d4{0, 0, 0, 0}, accI = d4{0, 0, 0, 0};
+  constexpr int LA = SM * KT / NTHR, LB = SN * KT / NTHR;  // loads per thread and slice
+  zd ra[LA], rb[LB];
+  // thread -> (m, k) of op(A) and (k, n) of op(B), the stored layout's fast
+  // index on consecutive threads
+  auto a_mk = [&](int i, int& m, int& k) {
+    if (OPA == 0) { m = tid % SM; k = tid / SM + (NTHR / SM) * i; }
+    else { k = tid & 15; m = (tid >> 4) + 16 * i; }
+  };
+  auto b_kn = [&](int i, int& k, int& n) {
+    if (OPB == 0) { k = tid & 15; n = (tid >> 4) + 16 * i; }
+    else { n = tid % SN; k = tid / SN + (NTHR / SN) * i; }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      int m, k;
+      a_mk(i, m, k);
+      const int gm = row0 + m, gk = k0 + k;
+      ra[i] = (gm < p.M && gk < p.K)
+                  ? (OPA == 0 ? p.A[gm + (int64_t)gk * p.lda] : zconj(p.A[gk + (int64_t)gm * p.lda]))
+                  : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      int k, n;
+      b_kn(i, k, n);
+      const int gn = col0 + n, gk = k0 + k;
+      rb[i] = (gn < p.N && gk < p.K)
+                  ? (OPB == 0 ? p.B[gk + (int64_t)gn * p.ldb] : zconj(p.B[gn + (int64_t)gk * p.ldb]))
+                  : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      int m, k;
+      a_mk(i, m, k);
+      As[b][k][m] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      int k, n;
+      b_kn(i, k, n);
+      Bs[b][k][n] = rb[i];
+    }
+  };
+  const int nk = (p.K + KT - 1) / KT;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int cur = t & 1;
+    if (t + 1 < nk) load((t + 1) * KT);
+#pragma unroll
+    for (int ks = 0; ks < KT / 4; ++ks) {
+      const int kk = ks * 4 + lg;
+      const zd a = As[cur][kk][bm * 16 + l16], b = Bs[cur][kk][bn * 16 + l16];
+      accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, accI, 0, 0, 0);
+      accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accR, 0, 0, 0);
+      accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, accI, 0, 0, 0);
+    }
+    if (t + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+  const int col = col0 + bn * 16 + l16;
+  if (col >= p.N) return;
+  const bool useC = (p.Cm != nullptr) && (p.beta != 0.0);
+  const bool useE = (p.E != nullptr) && (p.gamma != 0.0);
+  const double g = useE ? p.gamma * (p.gcol ? p.gcol[col] : 1.0) : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row0 + bm * 16 + lg + 4 * r;
+    if (row >= p.M) continue;
+    double vr = p.alpha * accR[r], vi = p.alpha * accI[r];
+    if (useC) {
+      const zd cv = p.Cm[row + (int64_t)col * p.ldc];
+      vr += p.beta * cv.x;
+      vi += p.beta * cv.y;
+    }
+    if (useE) {
+      const zd ev = p.E[row + (int64_t)col * p.lde];
+      vr += g * ev.x;
+      vi += g * ev.y;
+    }
+    p.D[row + (int64_t)col * p.ldd] = make_double2(vr, vi);
+  }
+}
+
 // Split-K: sum of the partial tiles in split order, then the epilogue; one
 // thread per output element, consecutive threads on consecutive rows.
 __global__ __launch_bounds__(256) void k_zgemm_splitk_reduce(ZgemmParams p) {
@@ -397,9 +512,18 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   if (total > INT32_MAX) return GEVP_ERR_INVALID;
   p.tiles = (int)total;
   p.lower = lower;
+  // skinny tiles: at most 64 rows (TALL) or columns (wide), fewer 64 x 64
+  // tiles than compute units, a short K.  A result written over its right
+  // operand needs tiles that span all rows (TALL), over its left operand
+  // tiles that span all columns (wide).
+  int skinny = 0;
+  if (!lower && !upperA && !coef && p.K <= SKINNY_K_MAX && total < (int64_t)gevp_device_cus(c->device)) {
+    if (m <= BM && (const zd*)D != A) skinny = 1;
+    else if (n <= BN && (const zd*)D != B) skinny = 2;
+  }
   const int nk = (p.K + KT - 1) / KT;
   p.upperA = upperA;
-  int s = c->no_split
+  int s = (c->no_split || skinny)
               ? 1
               : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
   p.nks = nk > 0 ? (nk + s - 1) / s : 1;
@@ -437,6 +561,29 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   // FP64 GEMM timing (profiling bit 4): not the FP64 filter (coef), which is
   // timed as a filter product by the caller
   const bool timed = (coef == nullptr) && (c->profiling & 4);
+  if (skinny) {
+    const int64_t sm = skinny == 1 ? 64 : 16, sn = skinny == 1 ? 16 : 64;
+    const int64_t sk_tiles = ((m + sm - 1) / sm) * ((n + sn - 1) / sn);
+    if (timed) GEVP_TRY(gev_begin(c));
+    const dim3 sg((unsigned)sk_tiles), st(NTHR);
+    if (skinny == 1) {
+      if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_zgemm_sk<0, 0, 1>), sg, st, 0, c->stream, p);
+      else if (opA == 0) hipLaunchKernelGGL((k_zgemm_sk<0, 1, 1>), sg, st, 0, c->stream, p);
+      else if (opB == 0) hipLaunchKernelGGL((k_zgemm_sk<1, 0, 1>), sg, st, 0, c->stream, p);
+      else hipLaunchKernelGGL((k_zgemm_sk<1, 1, 1>), sg, st, 0, c->stream, p);
+    } else {
+      if (opA == 0 && opB == 0) hipLaunchKernelGGL((k_zgemm_sk<0, 0, 0>), sg, st, 0, c->stream, p);
+      else if (opA == 0) hipLaunchKernelGGL((k_zgemm_sk<0, 1, 0>), sg, st, 0, c->stream, p);
+      else if (opB == 0) hipLaunchKernelGGL((k_zgemm_sk<1, 0, 0>), sg, st, 0, c->stream, p);
+      else hipLaunchKernelGGL((k_zgemm_sk<1, 1, 0>), sg, st, 0, c->stream, p);
+    }
+    GEVP_HIP_TRY(hipGetLastError());
+    if (timed) {
+      const int64_t shape[6] = {opA * 2 + opB, m, n, p.K, 1, sk_tiles};
+      GEVP_TRY(gev_end(c, 8.0 * (double)m * (double)n * (double)p.K, shape));
+    }
+    return GEVP_OK;
+  }
   if (timed) GEVP_TRY(gev_begin(c));
   if (opA == 0 && opB == 0) {
     if (coef)

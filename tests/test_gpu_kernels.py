@@ -65,6 +65,52 @@ def test_zgemm_plain_and_inplace_beta(h):
 
 
 # panel boundaries of the factorisation (384-wide panels of 64-wide blocks)
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("C", "N"), ("N", "C"), ("C", "C")])
+@pytest.mark.parametrize("m,n,k", [(64, 948, 64), (50, 300, 200), (948, 64, 64), (300, 40, 500),
+                                   (64, 70, 1024), (17, 5, 3)])
+def test_zgemm_skinny_tiles(h, opA, opB, m, n, k):
+    """Products with at most 64 rows or columns and a short K run on 64 x 16
+    or 16 x 64 tiles (one wave each); ragged edges and the K limit included."""
+    print(f"zgemm skinny {opA}{opB} m={m} n={n} k={k}", flush=True)
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = _cn(rng, *((m, k) if opA == "N" else (k, m)))
+    B = _cn(rng, *((k, n) if opB == "N" else (n, k)))
+    C = _cn(rng, m, n)
+    E = _cn(rng, m, n)
+    g = rng.standard_normal(n)
+    opa = A if opA == "N" else A.conj().T
+    opb = B if opB == "N" else B.conj().T
+    ref = -0.5 * opa @ opb + 2.0 * C - 0.25 * E * g[None, :]
+    out = h.zgemm(opA, opB, _dev(A), _dev(B), alpha=-0.5, beta=2.0, C=_dev(C), gamma=-0.25,
+                  E=_dev(E), gcol=_dev(g))
+    torch.cuda.synchronize()
+    scale = 0.5 * np.abs(opa) @ np.abs(opb) + 2.0 * np.abs(C) + 0.25 * np.abs(E * g[None, :])
+    assert np.max(np.abs(_np(out) - ref) / scale) <= 1e-14 * np.sqrt(k) * 10
+
+
+@pytest.mark.parametrize("side", ["L", "R"])
+def test_zgemm_in_place_base_cases(h, side):
+    """The base cases of the triangular solves overwrite one operand: the
+    left one as X = X T (rows of 16, every column in one tile) and the right
+    one as X = T X (columns of 16, every row in one tile)."""
+    from paper_1007_4400_amd import gevp
+
+    rng = np.random.default_rng(3)
+    T = np.tril(_cn(rng, 64, 64))
+    if side == "L":  # X (64 x 948) <- T X
+        X = _cn(rng, 64, 948)
+        Xd = gevp.colmajor(_dev(X))
+        h.zgemm("N", "N", _dev(T), Xd, out=Xd)
+        ref = T @ X
+    else:  # X (948 x 64) <- X T^H
+        X = _cn(rng, 948, 64)
+        Xd = gevp.colmajor(_dev(X))
+        h.zgemm("N", "C", Xd, _dev(T), out=Xd)
+        ref = X @ T.conj().T
+    torch.cuda.synchronize()
+    assert np.max(np.abs(_np(Xd) - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
 @pytest.mark.parametrize("opA,opB", [("C", "N"), ("N", "C"), ("N", "N")])
 @pytest.mark.parametrize("n,k", [(200, 70), (948, 8192), (130, 4000)])
 def test_zgemm_lower_triangle_tiles(h, opA, opB, n, k):
