@@ -262,6 +262,11 @@ struct CtlParams {
   int mode;         // 0: from Ritz data, 1: cold start, 2: Ritz data, residual-correction filter
   double u_target;  // mode 2: smallest per-sweep residual reduction worth aiming for
   double margin;    // degrees aim at tol / margin (convergence is still tested at tol)
+  // mode 2: when every wanted column can reach tol / margin with a reduction
+  // of at most 1 / u_reach, the sweep aims there at once, with degrees up to
+  // deg_reach (a sweep more than the rounding floor u_target usually allows)
+  double u_reach;
+  int deg_reach;
 };
 gevp_status launch_control(gevp_ctx* c, const CtlParams& p, const double* theta,
                            const double* resid, const double* bounds, const double* norms,

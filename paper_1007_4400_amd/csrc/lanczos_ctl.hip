@@ -151,7 +151,22 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
       while (nc < nev && resid[nc] <= tol_abs) ++nc;
     sh_nconv = nc;
   }
+  // largest reduction a wanted column needs (mode 2): within 1 / u_reach, one
+  // sweep aims for the tolerance directly instead of stopping at u_target
+  __shared__ double red_sh[256];
+  double rmax = 0.0;
+  if (p.mode == 2)
+    for (int i = tid; i < nev && i < nb; i += 256)
+      if (resid[i] > tol_abs) rmax = fmax(rmax, resid[i] * p.margin / tol_abs);
+  red_sh[tid] = rmax;
   __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red_sh[tid] = fmax(red_sh[tid], red_sh[tid + s]);
+    __syncthreads();
+  }
+  const bool reach = p.mode == 2 && p.u_reach > 0.0 && red_sh[0] * p.u_reach <= 1.0;
+  const double u_cap = reach ? p.u_reach : p.u_target;
+  const int dmax = reach ? max(p.deg_max, p.deg_reach) : p.deg_max;
   const bool done = (p.mode != 1) && sh_nconv >= nev;
   // per-column degrees
   for (int i = tid; i < nb; i += 256) {
@@ -164,17 +179,17 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
       } else {
         const double t = (theta[i] - c) / e;
         if (t >= -1.0) {
-          m = p.deg_max;
+          m = dmax;
         } else {
           const double rho = fabs(t) + sqrt(t * t - 1.0);
           // reduction wanted this sweep; a low-precision filter (mode 2) cannot
           // beat its rounding floor, so it aims no further than u_target
           double red = resid[i] * p.margin / tol_abs;
-          if (p.mode == 2 && red * p.u_target > 1.0) red = 1.0 / p.u_target;
+          if (p.mode == 2 && red * u_cap > 1.0) red = 1.0 / u_cap;
           const double need = log(red) / log(rho);
           m = (int)ceil(need) + 1;
           if (m < 2) m = 2;
-          if (m > p.deg_max) m = p.deg_max;
+          if (m > dmax) m = dmax;
         }
       }
     } else {
@@ -189,7 +204,7 @@ __global__ __launch_bounds__(256) void k_control(CtlParams p, const double* thet
     for (int i = 0; i < nb && i < nev; ++i) mx = max(mx, deg[i]);
     if (p.mode == 1) mx = deg[0];
     if (mx == 0 && !done) mx = 2;
-    if (mx > p.deg_max + (p.deg_max & 1)) mx = p.deg_max + (p.deg_max & 1);
+    if (mx > dmax + (dmax & 1)) mx = dmax + (dmax & 1);
     sh_maxdeg = done ? 0 : mx;
   }
   __syncthreads();
