@@ -546,9 +546,8 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   const int64_t total = tiles * p.splits;
   p.total = (int)total;
   p.remap = (total % 8 == 0 && total >= 64) ? 1 : 0;
-  // 128 KiB of LDS per work-group (gfx950 has 160 KB per CU); set once,
-  // thread-safely (batched solves launch from several host threads)
-  // the stages are static LDS arrays (160 KB): no dynamic LDS
+  // the stages are static LDS arrays (the 160 KB of a compute unit): no
+  // dynamic LDS
   hipLaunchKernelGGL(k_cgemm_bf16x3_filter, dim3((unsigned)total), dim3(512), 0, c->stream, p);
   GEVP_HIP_TRY(hipGetLastError());
   if (p.splits > 1) {
