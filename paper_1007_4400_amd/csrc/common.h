@@ -122,11 +122,15 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 // the upper triangle of op(A) (e.g. L^H): each output row block skips the K
 // range below its first row and entries below op(A)'s diagonal read as zero.  Products with few
 // output tiles and a long K run split-K through c->skw (see zgemm.hip).
+// A2 (op(A) = 'N' only): op(A) is [A; A2] stacked, rows 0..m1-1 from A and
+// rows m1..m-1 from A2 (same lda): two products that share op(B) in one
+// launch, so their tiles fill the rounds together.
 gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, int64_t k,
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef = nullptr, int lower = 0, int upperA = 0);
+                         const double* coef = nullptr, int lower = 0, int upperA = 0,
+                         int64_t m1 = 0, const zd* A2 = nullptr);
 
 // Blocked Cholesky of the lower triangle; Dinv (n x 64 column-major, ld =
 // ldi) receives the inverses of the 64 x 64 diagonal blocks; *info_dev

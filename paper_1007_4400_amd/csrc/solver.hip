@@ -634,8 +634,10 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   zd* Dinv = (zd*)ws_take(c, sizeof(zd) * n * 64);
   zd* P0 = (zd*)ws_take(c, sizeof(zd) * n * nb);
   zd* P1 = (zd*)ws_take(c, sizeof(zd) * n * nb);
-  zd* W = (zd*)ws_take(c, sizeof(zd) * n * nb);
-  zd* T = (zd*)ws_take(c, sizeof(zd) * n * nb);
+  // W and T adjacent: the final residual stacks [A X; B X] over both
+  zd* const WT = (zd*)ws_take(c, sizeof(zd) * 2 * n * nb);
+  zd* W = WT;
+  zd* T = WT + n * nb;
   zd* Hs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
   zd* Zs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
   zd* Gs = (zd*)ws_take(c, sizeof(zd) * nb * nb);
@@ -1086,14 +1088,14 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   double hn[2] = {0.0, 0.0};
   GEVP_HIP_TRY(hipMemcpyAsync(hn, norms, sizeof(hn), hipMemcpyDeviceToHost, c->stream));
   if (!o.skip_final) {
-    // R = A X - B X diag(lambda): T = B X, then W = A X - diag-scaled T, for
-    // the nev wanted columns (all kx when the caller asks for the residuals)
+    // R = A X - B X diag(lambda) for the nev wanted columns (all kx when the
+    // caller asks for the residuals): [A X; B X] as one 2n-row product (its
+    // tiles fill the compute units' rounds better than two n-row products),
+    // then the column norms of the top half minus the scaled bottom half
     const int64_t kr = resid_out ? kx : nev;
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, kr, n, 1.0, Bf, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
-                          nullptr, T, n));
-    GEVP_TRY(launch_zgemm(c, 0, 0, n, kr, n, 1.0, Af, n, X, ldx, 0.0, nullptr, 0, -1.0, T, n, theta,
-                          W, n));
-    GEVP_TRY(launch_colnorms(c, n, kr, W, n, fres));
+    GEVP_TRY(launch_zgemm(c, 0, 0, 2 * n, kr, n, 1.0, Af, n, X, ldx, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, WT, 2 * n, nullptr, 0, 0, n, Bf));
+    GEVP_TRY(launch_resid_cols(c, n, kr, WT, 2 * n, WT + n, 2 * n, theta, fres));
     if (resid_out) GEVP_TRY(launch_copy_real(c, kx, fres, resid_out));
     std::vector<double> hr(kr);
     GEVP_HIP_TRY(hipMemcpyAsync(hr.data(), fres, sizeof(double) * kr, hipMemcpyDeviceToHost, c->stream));

@@ -75,6 +75,8 @@ struct ZgemmParams {
   int upperA;       // op(A) upper triangular: slices below the tile's first row are zero
   int splits, nks;  // K split in `splits` parts of nks slices
   zd* part;         // splits > 1: raw partial tiles [split][tile][col][row]
+  const zd* A2;     // op(A) = 'N' only: rows >= M1 of op(A) are rows - M1 of A2 (same lda)
+  int M1;
 };
 
 __device__ __forceinline__ zd zconj(zd a) { return make_double2(a.x, -a.y); }
@@ -137,7 +139,10 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
   do {                                                                                \
     if (opA == 0) {                                                                   \
       const int gm_ = row0 + (tid & 63), gk_ = k0 + (tid >> 6) + 4 * (i);             \
-      dst = (gm_ < p.M && gk_ < p.K && !(p.upperA && gk_ < gm_)) ? p.A[gm_ + (int64_t)gk_ * p.lda]: make_double2(0.0, 0.0); \
+      const bool lo_ = gm_ >= p.M1;                                                   \
+      const zd* ab_ = lo_ ? p.A2 : p.A;                                               \
+      const int gr_ = lo_ ? gm_ - p.M1 : gm_;                                         \
+      dst = (gm_ < p.M && gk_ < p.K && !(p.upperA && gk_ < gm_)) ? ab_[gr_ + (int64_t)gk_ * p.lda]: make_double2(0.0, 0.0); \
     } else {                                                                          \
       const int gk_ = k0 + (tid & 15), gm_ = row0 + (tid >> 4) + 16 * (i);            \
       dst = (gm_ < p.M && gk_ < p.K && !(p.upperA && gk_ < gm_)) ? zconj(p.A[gk_ + (int64_t)gm_ * p.lda]) : make_double2(0.0, 0.0); \
@@ -477,8 +482,10 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
                          double alpha, const zd* A, int64_t lda, const zd* B, int64_t ldb,
                          double beta, const zd* Cm, int64_t ldc, double gamma, const zd* E,
                          int64_t lde, const double* gcol, zd* D, int64_t ldd,
-                         const double* coef, int lower, int upperA) {
+                         const double* coef, int lower, int upperA, int64_t m1, const zd* A2) {
   if (m <= 0 || n <= 0) return GEVP_OK;
+  // a stacked left operand [A; A2]: plain 'N' form only
+  if (A2 && (opA != 0 || lower || upperA || coef || m1 <= 0 || m1 >= m)) return GEVP_ERR_INVALID;
   if (m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return GEVP_ERR_INVALID;
   ZgemmParams p;
   p.M = (int)m;
@@ -501,6 +508,8 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.beta = beta;
   p.gamma = gamma;
   p.coef = coef;
+  p.A2 = A2;
+  p.M1 = A2 ? (int)m1 : (int)m;
   p.tiles_n = (int)((n + BN - 1) / BN);
   const int64_t tiles_m = (m + BM - 1) / BM;
   // a lower-triangle launch enumerates only the tiles on or below the
@@ -517,7 +526,8 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   // operand needs tiles that span all rows (TALL), over its left operand
   // tiles that span all columns (wide).
   int skinny = 0;
-  if (!lower && !upperA && !coef && p.K <= SKINNY_K_MAX && total < (int64_t)gevp_device_cus(c->device)) {
+  if (!lower && !upperA && !coef && !A2 && p.K <= SKINNY_K_MAX &&
+      total < (int64_t)gevp_device_cus(c->device)) {
     if (m <= BM && (const zd*)D != A) skinny = 1;
     else if (n <= BN && (const zd*)D != B) skinny = 2;
   }
