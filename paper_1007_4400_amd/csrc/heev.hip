@@ -580,7 +580,11 @@ __global__ void k_tri_norm(const double* d, const double* e, int n, double* out)
 // while n - 1 <= 4 G, at most one work-group per compute unit
 constexpr int64_t APPLY_LDS = 131072;  // LDS budget of the reflector sweep (bytes)
 
-inline int trd_groups(int64_t n) { return (int)(n - 1 < 256 ? (n > 1 ? n - 1 : 1) : 256); }
+// work-groups of the tridiagonalisation: one column per wave as far as the
+// order allows, and at most HT, since the next step's block reduction reads
+// one work-group partial per thread (measured at n = 948: 12.4 ms per
+// eigensolve with 256 groups, 13.2 with 192, 17.6 with 64)
+inline int trd_groups(int64_t n) { return (int)(n - 1 < HT ? (n > 1 ? n - 1 : 1) : HT); }
 
 size_t tridiag_eig_work_bytes(int64_t n) {
   return 5 * ws_round(sizeof(double) * n * n) + ws_round(sizeof(double) * 8);  // U, Vv, Ww, Lm, Sw; norm
