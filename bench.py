@@ -249,6 +249,7 @@ def run_batched(args):
     log(f"generated 32 problems in {time.perf_counter() - t0:.1f}s")
     opts = gevp.make_opts(precision=args.precision, batch_streams=args.streams)
     X = [None] * len(wls)
+    tuning = None
     per_step, single_step, worst = [], [], 0.0
     filt_ms = filt_flops = 0.0
     filt_launches = 0
@@ -260,6 +261,11 @@ def run_batched(args):
                 del Hk
         probs = [{"A": st["A"], "B": st["B"], "nev": st["wl"].nev, "X0": X[i],
                   "kx": h.block_size(st["wl"].n, st["wl"].nev, opts)} for i, st in enumerate(state)]
+        if k == 1 and not args.no_autotune:
+            # untimed: pick the launch configuration (streams, split-K mode) on
+            # this step's problems; the timed steps use it
+            tuning = h.autotune_batched(probs, tol=args.tol, opts=opts)
+            log(f"autotuned: {tuning}")
         torch.cuda.synchronize()
         h.set_profiling(2 if k > 0 else 0)  # events around every filter launch of the timed steps
         ts = time.perf_counter()
@@ -296,7 +302,9 @@ def run_batched(args):
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"batched_32kpt_n1500-3000_steps8_{args.precision}",
-                   "streams": args.streams, "sizes": [wl.n for wl, _ in wls]},
+                   "streams": tuning["streams"] if tuning else args.streams,
+                   "split_mode": tuning["split_mode"] if tuning else 0,
+                   "autotuned": tuning is not None, "sizes": [wl.n for wl, _ in wls]},
         "sequential_one_stream_s_per_step": single_step[0] if single_step else None,
         "max_resid_rel": worst,
         "roofline": {
@@ -866,6 +874,8 @@ def main():
                          "k-point problems, n in [1500, 3000], 8 SCF steps; update: thresholded "
                          "partial matrix update, n=8192, p_t=0.1, 12 steps")
     ap.add_argument("--streams", type=int, default=8, help="concurrent streams (batched)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: keep --streams and split-K by the cost model instead of autotuning")
     ap.add_argument("--rocprof-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
     ap.add_argument("--summary-kernel", default=None, help="kernel name for --rocprof-summary")
     ap.add_argument("--host-qr", action="store_true",

@@ -279,6 +279,52 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count,
                                double* const* resid, gevp_info* infos);
 
 /*
+ * Launch configuration of gevp_solve_batched (section 1: one pencil per Bloch
+ * vector k; the problems of a batch share the GPU).
+ *   streams     concurrent streams; > 0 overrides opts->batch_streams (at most
+ *               16 and at most count; ignored while a caller-owned workspace is
+ *               set, whose shares gevp_workspace_size_batched sized for the
+ *               options' rule)
+ *   split_mode  split-K of the FP64 and split-BF16 products: 0 = cost model
+ *               over all compute units, 1 = over one stream's share of them,
+ *               2 = no split-K
+ *   seconds     the measured time of one batched call (autotuner output)
+ */
+typedef struct {
+  int streams;
+  int split_mode;
+  double seconds;
+  int reserved[4];
+} gevp_tuning;
+
+/*
+ * Autotuner of gevp_solve_batched: the same arguments, solved once untimed
+ * (workspace set-up) and then once per candidate configuration — streams in
+ * {4, 8, 12, 16} (those <= count, plus count itself when below 16) times the
+ * three split modes — timed on the host around each complete call.  The
+ * fastest configuration is kept in the handle for later gevp_solve_batched
+ * calls and written to *best (may be NULL); the outputs hold the last call's
+ * results.  Costs about a dozen batched solves; allocates workspace like
+ * gevp_solve_batched.  Returns the status of the last call, or that of the
+ * first failing one.
+ */
+gevp_status gevp_autotune_batched(gevp_handle h, const gevp_opts* opts, int count,
+                                  const int64_t* n, const void* const* A, const int64_t* lda,
+                                  const void* const* B, const int64_t* ldb,
+                                  const void* const* X0, const int64_t* ldx0, const int64_t* k0,
+                                  const int64_t* nev, double tol, const int64_t* kx,
+                                  double* const* lambda, void* const* X, const int64_t* ldx,
+                                  double* const* resid, gevp_tuning* best);
+
+/* Set (t != NULL; streams 0..16, split_mode 0..2, else GEVP_ERR_INVALID) or
+ * clear (t == NULL) the handle's batched launch configuration, e.g. one read
+ * back from a tuning cache. */
+gevp_status gevp_set_tuning(gevp_handle h, const gevp_tuning* t);
+
+/* The handle's batched launch configuration (zeros when none is set). */
+gevp_status gevp_get_tuning(gevp_handle h, gevp_tuning* t);
+
+/*
  * Adjoint of L = sum_i w_i lambda_i (first-order perturbation of a
  * B-orthonormal pair: d lambda_i = x_i^H (dA - lambda_i dB) x_i):
  *   dA = X diag(w) X^H,    dB = -X diag(w .* lambda) X^H     (full n x n)

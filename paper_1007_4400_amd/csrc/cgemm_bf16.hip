@@ -539,7 +539,7 @@ gevp_status launch_cgemm_bf16x3_filter(gevp_ctx* c, int64_t m, int64_t n, int64_
   p.tiles_n = (int)((n + BN - 1) / BN);
   const int64_t tiles = ((m + BM - 1) / BM) * p.tiles_n;
   const int nk = (p.KG + 3) / 4;
-  const int s = choose_splits(tiles, nk, gevp_device_cus(c->device));
+  const int s = c->no_split ? 1 : choose_splits(tiles, nk, std::max(1, gevp_device_cus(c->device) / std::max(1, c->cu_div)));
   p.nks = (nk + s - 1) / s;
   p.splits = (nk + p.nks - 1) / p.nks;
   p.tiles = (int)tiles;

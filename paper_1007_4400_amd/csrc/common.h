@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <vector>
@@ -93,6 +94,14 @@ struct gevp_ctx {
   // set for the duration of a call that must not allocate: launch_zgemm then
   // never splits K (which needs the split-K buffer)
   bool no_split = false;
+  // split-K cost models count the compute units divided by this (a batched
+  // worker shares the GPU with the other streams)
+  int cu_div = 1;
+  // launch configuration of gevp_solve_batched chosen by gevp_autotune_batched
+  // or gevp_set_tuning (0 streams: the options' rule)
+  int tune_streams = 0;
+  int tune_split = 0;
+  double tune_seconds = 0.0;
 };
 
 // Split-K partial products of launch_zgemm: one fixed-size buffer per stream

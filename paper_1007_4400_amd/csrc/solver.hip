@@ -19,6 +19,7 @@
 // The only device-to-host traffic is a few status words per sweep.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1199,7 +1200,8 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
     return GEVP_ERR_INVALID;
   if (count == 0) return GEVP_OK;
   GEVP_HIP_TRY(hipSetDevice(h->device));
-  const int streams = batch_stream_count(opts, count);
+  int streams = batch_stream_count(opts, count);
+  if (h->tune_streams > 0 && !h->ext) streams = std::min(std::min(h->tune_streams, 16), count);
   while ((int)h->workers.size() < streams) {
     gevp_ctx* w = new gevp_ctx();
     w->device = h->device;
@@ -1213,7 +1215,12 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
   }
   // event timing of the filter launches (profiling flag 2) carries over; the
   // per-stage timer (flag 1) would synchronise the workers and is not passed on
-  for (int w = 0; w < streams; ++w) h->workers[w]->profiling = h->profiling & 6;
+  for (int w = 0; w < streams; ++w) {
+    gevp_ctx* c = h->workers[w];
+    c->profiling = h->profiling & 6;
+    c->no_split = h->tune_split == 2;
+    c->cu_div = h->tune_split == 1 ? streams : 1;
+  }
   if (h->ext) {
     // caller-owned memory: worker w takes the w-th equal share, its solve
     // workspace first and its split-K buffer at the share's top end
@@ -1266,6 +1273,89 @@ gevp_status gevp_solve_batched(gevp_handle h, const gevp_opts* opts, int count, 
     if (worst == GEVP_OK || worst == GEVP_ERR_NOCONV) worst = s;
   }
   return worst;
+}
+
+gevp_status gevp_set_tuning(gevp_handle h, const gevp_tuning* t) {
+  if (!h) return GEVP_ERR_INVALID;
+  if (!t) {
+    h->tune_streams = 0;
+    h->tune_split = 0;
+    h->tune_seconds = 0.0;
+    return GEVP_OK;
+  }
+  if (t->streams < 0 || t->streams > 16 || t->split_mode < 0 || t->split_mode > 2)
+    return GEVP_ERR_INVALID;
+  h->tune_streams = t->streams;
+  h->tune_split = t->split_mode;
+  h->tune_seconds = t->seconds;
+  return GEVP_OK;
+}
+
+gevp_status gevp_get_tuning(gevp_handle h, gevp_tuning* t) {
+  if (!h || !t) return GEVP_ERR_INVALID;
+  *t = gevp_tuning{};
+  t->streams = h->tune_streams;
+  t->split_mode = h->tune_split;
+  t->seconds = h->tune_seconds;
+  return GEVP_OK;
+}
+
+gevp_status gevp_autotune_batched(gevp_handle h, const gevp_opts* opts, int count,
+                                  const int64_t* n, const void* const* A, const int64_t* lda,
+                                  const void* const* B, const int64_t* ldb,
+                                  const void* const* X0, const int64_t* ldx0, const int64_t* k0,
+                                  const int64_t* nev, double tol, const int64_t* kx,
+                                  double* const* lambda, void* const* X, const int64_t* ldx,
+                                  double* const* resid, gevp_tuning* best) {
+  if (!h || count < 1) return GEVP_ERR_INVALID;
+  std::vector<int> cand;
+  for (int s : {4, 8, 12, 16})
+    if (s <= count) cand.push_back(s);
+  if (count < 16 && std::find(cand.begin(), cand.end(), count) == cand.end()) cand.push_back(count);
+  const int save_s = h->tune_streams, save_m = h->tune_split;
+  const double save_t = h->tune_seconds;
+  auto call = [&]() {
+    return gevp_solve_batched(h, opts, count, n, A, lda, B, ldb, X0, ldx0, k0, nev, tol, kx, lambda,
+                              X, ldx, resid, nullptr);
+  };
+  auto restore = [&]() {
+    h->tune_streams = save_s;
+    h->tune_split = save_m;
+    h->tune_seconds = save_t;
+  };
+  // untimed: every worker stream and workspace the candidates need
+  h->tune_streams = cand.back();
+  h->tune_split = 0;
+  gevp_status st = call();
+  if (st != GEVP_OK && st != GEVP_ERR_NOCONV) {
+    restore();
+    return st;
+  }
+  int bs = 0, bm = 0;
+  double bt = 0.0;
+  for (int s : cand)
+    for (int m = 0; m < 3; ++m) {
+      h->tune_streams = s;
+      h->tune_split = m;
+      GEVP_HIP_TRY(hipDeviceSynchronize());
+      const auto t0 = std::chrono::steady_clock::now();
+      st = call();
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (st != GEVP_OK && st != GEVP_ERR_NOCONV) {
+        restore();
+        return st;
+      }
+      if (bs == 0 || dt < bt) {
+        bs = s;
+        bm = m;
+        bt = dt;
+      }
+    }
+  h->tune_streams = bs;
+  h->tune_split = bm;
+  h->tune_seconds = bt;
+  if (best) GEVP_TRY(gevp_get_tuning(h, best));
+  return st;
 }
 
 // ---- kernel-level entry points

@@ -535,7 +535,9 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
   p.upperA = upperA;
   int s = (c->no_split || skinny)
               ? 1
-              : zgemm_splits(total, nk, 2 * (int64_t)gevp_device_cus(c->device), SPLIT_TILES_MAX);
+              : zgemm_splits(total, nk,
+                             std::max<int64_t>(1, 2 * (int64_t)gevp_device_cus(c->device) / std::max(1, c->cu_div)),
+                             SPLIT_TILES_MAX);
   p.nks = nk > 0 ? (nk + s - 1) / s : 1;
   p.splits = nk > 0 ? (nk + p.nks - 1) / p.nks : 1;
   p.part = nullptr;

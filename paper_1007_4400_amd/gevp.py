@@ -62,6 +62,15 @@ class Info(ctypes.Structure):
         return d
 
 
+class Tuning(ctypes.Structure):
+    """gevp_tuning: launch configuration of gevp_solve_batched."""
+    _fields_ = [("streams", ctypes.c_int), ("split_mode", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("reserved", ctypes.c_int * 4)]
+
+    def as_dict(self):
+        return {"streams": self.streams, "split_mode": self.split_mode, "seconds": self.seconds}
+
+
 class UpdateInfo(ctypes.Structure):
     _fields_ = [
         ("delta", ctypes.c_double), ("entries", ctypes.c_int64), ("updated", ctypes.c_int64),
@@ -120,6 +129,13 @@ def load():
     lib.gevp_solve_batched.argtypes = [P, ctypes.POINTER(Opts), I, P, P, P, P, P, P, P, P, P, D, P,
                                        P, P, P, P, P]
     lib.gevp_solve_batched.restype = I
+    lib.gevp_autotune_batched.argtypes = [P, ctypes.POINTER(Opts), I, P, P, P, P, P, P, P, P, P, D,
+                                          P, P, P, P, P, ctypes.POINTER(Tuning)]
+    lib.gevp_autotune_batched.restype = I
+    lib.gevp_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gevp_set_tuning.restype = I
+    lib.gevp_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gevp_get_tuning.restype = I
     lib.gevp_backward.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
     lib.gevp_backward.restype = I
     lib.gevp_backward_noalloc.argtypes = [P, L, L, P, L, P, P, P, L, P, L]
@@ -365,11 +381,8 @@ class Handle:
         d["status"] = s
         return lam, X, res, d
 
-    def solve_batched(self, problems, tol=1e-10, opts: Optional[Opts] = None, raise_on_noconv=True):
-        """Independent pencils solved concurrently.  ``problems`` is a list of
-        dicts with keys A, B, nev and optional X0, kx.  Returns a list of
-        (lam, X, resid, info dict)."""
-        opts = opts or make_opts()
+    def _batched_args(self, problems):
+        """Checked tensors, outputs and the ctypes arrays of a batched call."""
         cnt = len(problems)
         arr = lambda t, vals: (t * cnt)(*vals)
         checked = [check_solve_args(p["A"], p["B"], p["nev"], p.get("X0"), self.device)
@@ -383,18 +396,30 @@ class Handle:
         lams = [torch.empty(k, dtype=torch.float64, device=a.device) for k, a in zip(kxs, As)]
         Xs = [empty_colmajor(n, k, device=a.device) for n, k, a in zip(ns, kxs, As)]
         rs = [torch.empty(k, dtype=torch.float64, device=a.device) for k, a in zip(kxs, As)]
+        L64, VP = ctypes.c_int64, ctypes.c_void_p
+        args = (cnt, arr(L64, ns), arr(VP, [a.data_ptr() for a in As]),
+                arr(L64, [_ld(a) for a in As]), arr(VP, [b.data_ptr() for b in Bs]),
+                arr(L64, [_ld(b) for b in Bs]),
+                arr(VP, [x.data_ptr() if x is not None else None for x in X0s]),
+                arr(L64, [_ld(x) if x is not None else n for x, n in zip(X0s, ns)]),
+                arr(L64, [x.shape[1] if x is not None else 0 for x in X0s]), arr(L64, nevs))
+        outs = (arr(L64, kxs), arr(VP, [t.data_ptr() for t in lams]),
+                arr(VP, [x.data_ptr() for x in Xs]), arr(L64, [_ld(x) for x in Xs]),
+                arr(VP, [t.data_ptr() for t in rs]))
+        keep = (As, Bs, X0s)  # the tensors the pointers refer to
+        return args, outs, (lams, Xs, rs), keep
+
+    def solve_batched(self, problems, tol=1e-10, opts: Optional[Opts] = None, raise_on_noconv=True):
+        """Independent pencils solved concurrently.  ``problems`` is a list of
+        dicts with keys A, B, nev and optional X0, kx.  Returns a list of
+        (lam, X, resid, info dict)."""
+        opts = opts or make_opts()
+        args, outs, (lams, Xs, rs), keep = self._batched_args(problems)
+        cnt = len(problems)
         infos = (Info * cnt)()
-        L64, VP, DP = ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
         self._stream()
-        s = self.lib.gevp_solve_batched(
-            self.h, ctypes.byref(opts), cnt, arr(L64, ns), arr(VP, [a.data_ptr() for a in As]),
-            arr(L64, [_ld(a) for a in As]), arr(VP, [b.data_ptr() for b in Bs]),
-            arr(L64, [_ld(b) for b in Bs]),
-            arr(VP, [x.data_ptr() if x is not None else None for x in X0s]),
-            arr(L64, [_ld(x) if x is not None else n for x, n in zip(X0s, ns)]),
-            arr(L64, [x.shape[1] if x is not None else 0 for x in X0s]), arr(L64, nevs), float(tol),
-            arr(L64, kxs), arr(VP, [t.data_ptr() for t in lams]), arr(VP, [x.data_ptr() for x in Xs]),
-            arr(L64, [_ld(x) for x in Xs]), arr(VP, [t.data_ptr() for t in rs]), infos)
+        s = self.lib.gevp_solve_batched(self.h, ctypes.byref(opts), *args, float(tol), *outs, infos)
+        del keep
         if s != GEVP_OK and not (s == GEVP_ERR_NOCONV and not raise_on_noconv):
             raise GevpError(s, "gevp_solve_batched")
         out = []
@@ -402,6 +427,61 @@ class Handle:
             d = infos[i].as_dict()
             out.append((lams[i], Xs[i], rs[i], d))
         return out
+
+    def autotune_batched(self, problems, tol=1e-10, opts: Optional[Opts] = None, cache=None):
+        """Pick the batched launch configuration (streams, split-K mode) by
+        timing gevp_solve_batched on these problems (gevp_autotune_batched)
+        and keep it in the handle.  With ``cache`` (a JSON file path), a
+        configuration stored for the same device, precision, problem sizes and
+        tolerance is applied without timing, and a new one is stored.
+        Returns the configuration as a dict."""
+        import hashlib
+        import json
+        import os
+
+        opts = opts or make_opts()
+        sizes = sorted((int(p["A"].shape[0]), int(p["nev"])) for p in problems)
+        key = "|".join([torch.cuda.get_device_name(self.device), str(int(opts.precision)),
+                        f"{float(tol):.3e}", hashlib.sha1(json.dumps(sizes).encode()).hexdigest()])
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_tuning(table[key])
+                return dict(table[key], cached=True)
+        args, outs, _, keep = self._batched_args(problems)
+        best = Tuning()
+        self._stream()
+        s = self.lib.gevp_autotune_batched(self.h, ctypes.byref(opts), *args, float(tol), *outs,
+                                           ctypes.byref(best))
+        del keep
+        if s not in (GEVP_OK, GEVP_ERR_NOCONV):
+            raise GevpError(s, "gevp_autotune_batched")
+        t = best.as_dict()
+        if cache:
+            table[key] = t
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return dict(t, cached=False)
+
+    def set_tuning(self, t):
+        """Apply a batched launch configuration (dict with streams, split_mode
+        and optionally seconds), or clear it with None."""
+        if t is None:
+            s = self.lib.gevp_set_tuning(self.h, None)
+        else:
+            tt = Tuning(int(t["streams"]), int(t["split_mode"]), float(t.get("seconds", 0.0)))
+            s = self.lib.gevp_set_tuning(self.h, ctypes.byref(tt))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        s = self.lib.gevp_get_tuning(self.h, ctypes.byref(t))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_get_tuning")
+        return t.as_dict()
 
     def backward(self, X, lam, w, want_dA=True, want_dB=True):
         X, lam, w = check_backward_args(X, lam, w, self.device, need_lam=want_dB)

@@ -86,3 +86,41 @@ def test_batched_seeded_with_contour_filter(h, oracle_mod):
             assert r.max() <= TOL * np.linalg.norm(A, 2) and orth <= 1e-9
             assert (info["contour_applications"] >= 1) == (k > 0)
             X[i] = Xi
+
+
+def test_autotune_batched_picks_and_caches(h, oracle_mod, tmp_path):
+    """The autotuner times the batched call per stream count and split-K mode,
+    keeps the fastest in the handle, and a JSON cache gives the same choice to
+    a new handle without timing; tuned solves pass the oracle bar, and the
+    configuration can be cleared and is validated."""
+    from paper_1007_4400_amd import gevp
+
+    wls = synth.batched_workloads(count=6, nmin=200, nmax=420, seed=5, steps=1)
+    pencils = [synth.make_pencil(wl, s)[0] for wl, s in wls]
+    probs = [{"A": _dev(p.A), "B": _dev(p.B), "nev": wl.nev} for p, (wl, _) in zip(pencils, wls)]
+    opts = gevp.make_opts(precision="bf16x3")
+    cache = str(tmp_path / "tuning.json")
+    t = h.autotune_batched(probs, tol=TOL, opts=opts, cache=cache)
+    print("tuning", t, flush=True)
+    assert not t["cached"] and t["streams"] in (4, 6) and t["split_mode"] in (0, 1, 2)
+    assert t["seconds"] > 0
+    got = h.get_tuning()
+    assert (got["streams"], got["split_mode"]) == (t["streams"], t["split_mode"])
+    for (lam, X, _, info), p, (wl, _) in zip(h.solve_batched(probs, tol=TOL, opts=opts), pencils, wls):
+        ln = lam.cpu().numpy()[: wl.nev]
+        lo, _ = oracle_mod.solve(p.A, p.B, wl.nev)
+        assert np.max(np.abs(ln - lo) / np.maximum(np.abs(lo), 1.0)) <= TOL
+        r, orth = oracle_mod.residuals(p.A, p.B, ln, X.cpu().numpy()[:, : wl.nev])
+        assert r.max() <= TOL * np.linalg.norm(p.A, 2) and orth <= 1e-9
+    h2 = gevp.Handle(0)
+    t2 = h2.autotune_batched(probs, tol=TOL, opts=opts, cache=cache)
+    assert t2["cached"] and (t2["streams"], t2["split_mode"], t2["seconds"]) == \
+        (t["streams"], t["split_mode"], t["seconds"])
+    assert h2.get_tuning()["streams"] == t["streams"]
+    h2.close()
+    h.set_tuning(None)
+    assert h.get_tuning() == {"streams": 0, "split_mode": 0, "seconds": 0.0}
+    for bad in ({"streams": 17, "split_mode": 0}, {"streams": 4, "split_mode": 3},
+                {"streams": -1, "split_mode": 0}):
+        with pytest.raises(gevp.GevpError):
+            h.set_tuning(bad)
