@@ -85,7 +85,14 @@ __device__ void reg_inverse_to(zd (*S)[NB], zd (*xrow)[NB], int n, zd* Dinv, int
 // 1-based global index) and replaced by 1 so the kernel always finishes.
 constexpr int PB = 16;       // panel width
 constexpr int SLD = NB + 1;  // LDS column stride in complex entries (odd: rows spread over banks)
-constexpr size_t POTRF_LDS = 2 * sizeof(zd) * NB * SLD;
+// L and inv(L) share one array: L in the lower triangle (column-major,
+// S[c * SLD + r], r >= c), the strict lower triangle of inv(L) transposed into
+// the upper one (X(i, j), i > j, at S[i * SLD + j]), inv(L)'s diagonal in a
+// separate vector.  66.5 KB of LDS instead of 133 KB, so the factor fits on a
+// compute unit next to one work-group of the trailing-update GEMM (which holds
+// 66.5 KB) instead of waiting for a unit with both of its GEMM work-groups
+// gone.
+constexpr size_t POTRF_LDS = sizeof(zd) * (NB * SLD + NB);
 
 __device__ __forceinline__ zd zmulc(zd a, zd b) {  // a * conj(b)
   return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
@@ -94,8 +101,10 @@ __device__ __forceinline__ zd zmulc(zd a, zd b) {  // a * conj(b)
 __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, zd* Dinv,
                                                      int64_t ldi, int* info, int goff) {
   extern __shared__ double potrf_lds[];
-  zd* S = reinterpret_cast<zd*>(potrf_lds);  // L, S[c * SLD + r]
-  zd* X = S + NB * SLD;                      // inv(L), same layout
+  zd* S = reinterpret_cast<zd*>(potrf_lds);  // L, S[c * SLD + r], r >= c
+  zd* Xd = S + NB * SLD;                     // diagonal of inv(L)
+  // entry (i, j), i >= j, of inv(L)
+  auto X = [&](int i, int j) -> zd& { return (i == j) ? Xd[i] : S[i * SLD + j]; };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     // all sixteen loads in flight before the first LDS store
@@ -109,8 +118,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
 #pragma unroll
     for (int q = 0; q < NB * NB / 256; ++q) {
       const int e = tid + 256 * q, r = e & (NB - 1), c = e >> 6;
-      S[c * SLD + r] = v[q];
-      X[c * SLD + r] = make_double2(0.0, 0.0);
+      S[c * SLD + r] = v[q];  // zeros above the diagonal: inv(L)'s entries go there later
     }
   }
   __syncthreads();
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
             x[m] = make_double2(x[m].x * il, x[m].y * il);
-            X[(p0 + cg + 4 * m) * SLD + p0 + k] = x[m];
+            if (cg + 4 * m <= k) X(p0 + k, p0 + cg + 4 * m) = x[m];  // row k, lower part
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -168,7 +176,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
           const zd lrk = colk[r];
 #pragma unroll
           for (int m = 0; m < 4; ++m) {
-            const zd xk = X[(p0 + cg + 4 * m) * SLD + p0 + k];
+            const zd xk = (cg + 4 * m <= k) ? X(p0 + k, p0 + cg + 4 * m) : make_double2(0.0, 0.0);
             const zd t = make_double2(lrk.x * xk.x - lrk.y * xk.y, lrk.x * xk.y + lrk.y * xk.x);
             x[m] = make_double2(x[m].x - t.x, x[m].y - t.y);
           }
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
         if (e < R * PB) {
           const int row = p0 + PB + e % R, c = e / R;
           for (int k = 0; k <= c; ++k) {
-            const zd t = zmulc(S[(p0 + k) * SLD + row], X[(p0 + k) * SLD + p0 + c]);
+            const zd t = zmulc(S[(p0 + k) * SLD + row], X(p0 + c, p0 + k));
             v[q].x += t.x;
             v[q].y += t.y;
           }
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
         const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
         const int row = I * PB + r, col = J * PB + c;
         for (int k = J * PB + c; k < I * PB; ++k) {  // X(k, col) = 0 for k < col
-          const zd l = S[k * SLD + row], xk = X[col * SLD + k];
+          const zd l = S[k * SLD + row], xk = X(k, col);
           v[q].x += l.x * xk.x - l.y * xk.y;
           v[q].y += l.x * xk.y + l.y * xk.x;
         }
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
       const int e = tid + 256 * q;
       if (e < I * PB * PB) {
         const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
-        X[(J * PB + c) * SLD + I * PB + r] = v[q];
+        X(I * PB + r, J * PB + c) = v[q];
       }
     }
     __syncthreads();
@@ -253,7 +261,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
         const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
         const int row = I * PB + r, col = J * PB + c;
         for (int k = 0; k <= r; ++k) {
-          const zd xi = X[(I * PB + k) * SLD + row], t = X[col * SLD + I * PB + k];
+          const zd xi = X(row, I * PB + k), t = X(I * PB + k, col);
           v[q].x -= xi.x * t.x - xi.y * t.y;
           v[q].y -= xi.x * t.y + xi.y * t.x;
         }
@@ -265,7 +273,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
       const int e = tid + 256 * q;
       if (e < I * PB * PB) {
         const int J = e >> 8, r = e & 15, c = (e >> 4) & 15;
-        X[(J * PB + c) * SLD + I * PB + r] = v[q];
+        X(I * PB + r, J * PB + c) = v[q];
       }
     }
     __syncthreads();
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(256) void k_potrf_block(zd* M, int64_t ldm, int n, 
     const int r = e & (NB - 1), c = e >> 6;
     if (r < n && c < n) {
       M[r + (int64_t)c * ldm] = (r >= c) ? S[c * SLD + r] : make_double2(0.0, 0.0);
-      Dinv[r + (int64_t)c * ldi] = (r >= c) ? X[c * SLD + r] : make_double2(0.0, 0.0);
+      Dinv[r + (int64_t)c * ldi] = (r >= c) ? X(r, c) : make_double2(0.0, 0.0);
     }
   }
 }
