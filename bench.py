@@ -566,7 +566,7 @@ def _report_contour(args, wl, nsteps, kx, t_total, per_step, infos, cold_mean, p
     print(json.dumps(out), flush=True)
 
 
-GEMM_FAMILY = "k_zgemm<0>, k_zgemm_nc, k_zgemm_cn, k_zgemm_cc (+ k_zgemm_splitk_reduce)"
+GEMM_FAMILY = "k_zgemm<0>, k_zgemm_nc, k_zgemm_cn, k_zgemm_cc, k_zgemm_sk (+ k_zgemm_splitk_reduce)"
 
 
 def _roofline_gemm(infos):
