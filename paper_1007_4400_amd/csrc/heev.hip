@@ -14,7 +14,9 @@
 //     pivoting), one thread per eigenvalue, recurrences in registers; members
 //     of numerically degenerate clusters are then made orthonormal by
 //     modified Gram-Schmidt.
-//  4. Z = U Z_T by applying the reflectors in reverse order.
+//  4. Z = U Z_T by applying the reflectors in reverse order, in compact-WY
+//     blocks of 16 (one kernel forms every block's triangular factor, one
+//     applies the blocks to column slabs of Z held in LDS).
 #include <cfloat>
 
 #include "common.h"
@@ -499,72 +501,168 @@ __global__ __launch_bounds__(256) void k_zt_to_complex(const double* Zt, int n, 
   }
 }
 
-// Z <- G_0 G_1 ... G_{n-2} Z, reflectors applied last to first.  Each
-// work-group owns `cols` columns of Z (one per wave) held in LDS for the whole
-// sweep, so Z never leaves the CU.  Reflectors go through two LDS slots: the
-// next one is loaded into registers while the current one is applied, then
-// stored into the other slot, so each step has one barrier and no exposed
-// global load.
-constexpr int RQ = 8;  // rows per thread of a staged reflector: n <= RQ * 256
-__global__ __launch_bounds__(256) void k_apply_reflectors(int n, int cols, zd* Z, int64_t ldz,
-                                                          const zd* V, int64_t ldv, const zd* tau) {
-  extern __shared__ zd sm2[];
-  zd* sv0 = sm2;          // n
-  zd* sv1 = sm2 + n;      // n
-  zd* sz = sm2 + 2 * n;   // cols x n
+// Z <- G_0 G_1 ... G_{n-2} Z in compact-WY blocks of WYB reflectors: block k
+// (reflectors s0 = WYB k ..) is G_{s0} ... G_{s0+b-1} = I - V T V^H with T
+// upper triangular (forward accumulation: T_ii = tau_i, T(0:i-1, i) =
+// -tau_i T(0:i-1, 0:i-1) V(:, 0:i-1)^H v_i), and the blocks are applied last
+// to first, Z <- Z - V (T (V^H Z)).  k_wy_factors forms every block's T (one
+// work-group per block); k_apply_wy keeps `cols` columns of Z in LDS per
+// work-group and, per block, (1) stages the block's reflectors 64 rows at a
+// time in LDS, where each wave accumulates V^H z for its columns, one row per
+// lane, (2) forms u = T w, (3) subtracts V u row by row.  Two dependent
+// passes per 16 reflectors instead of one barrier-separated step per
+// reflector.
+constexpr int WYB = 16;  // reflectors per block
+
+__global__ __launch_bounds__(256) void k_wy_factors(int n, const zd* V, int64_t ldv, const zd* tau,
+                                                    zd* Tg) {
+  __shared__ zd G[WYB][WYB];  // G[i][j] = v_i^H v_j, i < j
+  __shared__ zd T[WYB][WYB];  // T[r][c]
+  const int k = blockIdx.x, s0 = k * WYB;
+  const int nref = n - 1, b = (nref - s0 < WYB) ? nref - s0 : WYB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = blockIdx.x * cols;
-  for (int q = 0; q < cols; ++q) {
-    const int col = c0 + q;
-    for (int i = tid; i < n; i += 256)
-      sz[q * n + i] = (col < n) ? Z[i + (int64_t)col * ldz] : make_double2(0.0, 0.0);
+  // Gram entries over the later reflector's support (rows >= s0 + j + 1)
+  for (int pidx = wave; pidx < WYB * WYB; pidx += 4) {
+    const int i = pidx / WYB, j = pidx % WYB;
+    if (!(i < j && j < b)) continue;
+    const zd* vi = V + (int64_t)(s0 + i) * ldv;
+    const zd* vj = V + (int64_t)(s0 + j) * ldv;
+    double sr = 0.0, si = 0.0;
+    for (int r = s0 + j + 1 + lane; r < n; r += 64) {
+      const zd a = vi[r], c = vj[r];  // conj(a) c
+      sr += a.x * c.x + a.y * c.y;
+      si += a.x * c.y - a.y * c.x;
+    }
+    sr = wsum(sr);
+    si = wsum(si);
+    if (lane == 0) G[i][j] = make_double2(sr, si);
   }
-  for (int i = n - 1 + tid; i < n; i += 256) sv0[i] = V[i + (int64_t)(n - 2) * ldv];
+  if (tid < WYB * WYB) T[tid % WYB][tid / WYB] = make_double2(0.0, 0.0);
   __syncthreads();
-  const bool active = wave < cols && (c0 + wave) < n;
-  zd* z = sz + wave * n;
-  zd t = tau[n - 2];
-  for (int s = n - 2; s >= 0; --s) {
-    zd* cur = ((n - 2 - s) & 1) ? sv1 : sv0;
-    zd* nxt = ((n - 2 - s) & 1) ? sv0 : sv1;
-    // the next reflector (s - 1) covers rows s .. n-1
-    zd r[RQ];
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) {
-      const int i = s + tid + 256 * q;
-      r[q] = (s >= 1 && i < n) ? V[i + (int64_t)(s - 1) * ldv] : make_double2(0.0, 0.0);
-    }
-    const zd tn = (s >= 1) ? tau[s - 1] : make_double2(0.0, 0.0);
-    if (active && !(t.x == 0.0 && t.y == 0.0)) {
-      double sr = 0.0, si = 0.0;
-      for (int i = s + 1 + lane; i < n; i += 64) {
-        const zd v = cur[i], x = z[i];  // conj(v) x
-        sr += v.x * x.x + v.y * x.y;
-        si += v.x * x.y - v.y * x.x;
-      }
-      sr = wsum(sr);
-      si = wsum(si);
-      const zd f = cmul(t, make_double2(sr, si));
-      for (int i = s + 1 + lane; i < n; i += 64) {
-        const zd fv = cmul(f, cur[i]);
-        z[i].x -= fv.x;
-        z[i].y -= fv.y;
+  for (int i = 0; i < b; ++i) {
+    const zd ti = tau[s0 + i];
+    zd acc = make_double2(0.0, 0.0);
+    if (tid < i) {  // row tid of T(0:i-1, 0:i-1) G(0:i-1, i), T upper triangular
+      for (int m = tid; m < i; ++m) {
+        const zd t = cmul(T[tid][m], G[m][i]);
+        acc.x += t.x;
+        acc.y += t.y;
       }
     }
-    // the other slot was last read in the previous step, before its barrier
-#pragma unroll
-    for (int q = 0; q < RQ; ++q) {
-      const int i = s + tid + 256 * q;
-      if (s >= 1 && i < n) nxt[i] = r[q];
+    __syncthreads();
+    if (tid < i) {
+      const zd v = cmul(ti, acc);
+      T[tid][i] = make_double2(-v.x, -v.y);
     }
-    t = tn;
+    if (tid == i) T[i][i] = ti;
     __syncthreads();
   }
-  for (int q = 0; q < cols; ++q) {
-    const int col = c0 + q;
-    if (col >= n) break;
-    for (int i = tid; i < n; i += 256) Z[i + (int64_t)col * ldz] = sz[q * n + i];
+  if (tid < WYB * WYB) Tg[(int64_t)k * WYB * WYB + tid] = T[tid % WYB][tid / WYB];  // column-major
+}
+
+constexpr int WYR = 64;       // rows of a staged reflector chunk
+constexpr int WYS = WYB + 1;  // LDS row stride of a chunk (odd: lanes on distinct banks)
+__global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_t ldz, const zd* V,
+                                                  int64_t ldv, const zd* Tg) {
+  extern __shared__ zd sm3[];
+  zd* sz = sm3;                       // cols x n
+  zd* vb = sm3 + (size_t)cols * n;    // 2 x WYR x WYS, [row][j]
+  zd* wv = vb + 2 * WYR * WYS;        // cols x WYB: w = V^H z
+  zd* uv = wv + cols * WYB;           // cols x WYB
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = blockIdx.x * cols;
+  const int nc = (n - c0 < cols) ? n - c0 : cols;
+  for (int q = 0; q < cols; ++q)
+    for (int i = tid; i < n; i += 256)
+      sz[(size_t)q * n + i] = (q < nc) ? Z[i + (int64_t)(c0 + q) * ldz] : make_double2(0.0, 0.0);
+  const int nref = n - 1, nblk = (nref + WYB - 1) / WYB;
+  __syncthreads();
+  for (int k = nblk - 1; k >= 0; --k) {
+    const int s0 = k * WYB, b = (nref - s0 < WYB) ? nref - s0 : WYB;
+    const int r0 = s0 + 1;  // first row any reflector of the block touches
+    // (1) w = V^H z: chunks of WYR rows staged in LDS (double buffered); wave
+    // w accumulates the columns w, w + 4, ... one row per lane
+    zd acc[2][WYB];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < WYB; ++j) acc[q][j] = make_double2(0.0, 0.0);
+    const int nch = (n - r0 + WYR - 1) / WYR;
+    auto stage = [&](int ch, zd* buf) {
+      for (int e = tid; e < WYR * WYB; e += 256) {
+        const int rr = e % WYR, j = e / WYR, r = r0 + ch * WYR + rr;
+        buf[rr * WYS + j] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
+      }
+    };
+    if (nch > 0) stage(0, vb);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      zd* cur = vb + (ch & 1) * WYR * WYS;
+      if (ch + 1 < nch) stage(ch + 1, vb + ((ch + 1) & 1) * WYR * WYS);
+      const int r = r0 + ch * WYR + lane;
+      if (r < n) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int c = wave + 4 * q;
+          if (c < cols) {
+            const zd z = sz[(size_t)c * n + r];
+#pragma unroll
+            for (int j = 0; j < WYB; ++j) {  // conj(v) z
+              const zd v = cur[lane * WYS + j];
+              acc[q][j].x += v.x * z.x + v.y * z.y;
+              acc[q][j].y += v.x * z.y - v.y * z.x;
+            }
+          }
+        }
+      }
+      __syncthreads();  // the other buffer is complete, this one is free
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = wave + 4 * q;
+#pragma unroll
+      for (int j = 0; j < WYB; ++j) {
+        const double xr = wsum(acc[q][j].x), xi = wsum(acc[q][j].y);
+        if (lane == 0 && c < cols) wv[c * WYB + j] = make_double2(xr, xi);
+      }
+    }
+    __syncthreads();
+    // (2) u = T w (T upper triangular, column-major)
+    const zd* T = Tg + (int64_t)k * WYB * WYB;
+    if (tid < cols * WYB) {
+      const int c = tid / WYB, i = tid % WYB;
+      zd u = make_double2(0.0, 0.0);
+      for (int m = i; m < b; ++m) {
+        const zd t = cmul(T[i + m * WYB], wv[c * WYB + m]);
+        u.x += t.x;
+        u.y += t.y;
+      }
+      uv[c * WYB + i] = u;
+    }
+    __syncthreads();
+    // (3) z <- z - V u, one thread per row
+    for (int r = r0 + tid; r < n; r += 256) {
+      zd v[WYB];
+#pragma unroll
+      for (int j = 0; j < WYB; ++j)
+        v[j] = (j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
+      for (int c = 0; c < cols; ++c) {
+        zd d = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < WYB; ++j) {
+          const zd t = cmul(v[j], uv[c * WYB + j]);
+          d.x += t.x;
+          d.y += t.y;
+        }
+        zd& z = sz[(size_t)c * n + r];
+        z.x -= d.x;
+        z.y -= d.y;
+      }
+    }
+    __syncthreads();
   }
+  for (int q = 0; q < nc; ++q)
+    for (int i = tid; i < n; i += 256) Z[i + (int64_t)(c0 + q) * ldz] = sz[(size_t)q * n + i];
 }
 
 __global__ void k_tri_norm(const double* d, const double* e, int n, double* out) {
@@ -578,7 +676,7 @@ __global__ void k_tri_norm(const double* d, const double* e, int n, double* out)
 
 // work-groups of a tridiagonalisation step: one wave per trailing column
 // while n - 1 <= 4 G, at most one work-group per compute unit
-constexpr int64_t APPLY_LDS = 131072;  // LDS budget of the reflector sweep (bytes)
+constexpr int64_t WY_LDS = 163840;     // LDS budget of the compact-WY application (bytes)
 
 // work-groups of the tridiagonalisation: one column per wave as far as the
 // order allows, and at most HT, since the next step's block reduction reads
@@ -629,6 +727,7 @@ size_t heev_work_bytes(int64_t n) {
   b += ws_round(sizeof(zd) * 2 * G);          // pp
   b += ws_round(sizeof(double) * n * n);      // Zt
   b += tridiag_eig_work_bytes(n);
+  b += ws_round(sizeof(zd) * WYB * WYB * ((n + WYB - 1) / WYB));  // WY factors
   return b;
 }
 
@@ -717,14 +816,15 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   a.G = G;
   double* Zt = (double*)take(sizeof(double) * n * n);
   void* tw = take(tridiag_eig_work_bytes(n));
+  zd* wyT = (zd*)take(sizeof(zd) * WYB * WYB * ((n + WYB - 1) / WYB));
 
   const size_t shv = sizeof(zd) * (size_t)n;
   const size_t sh3 = 3 * shv;  // v_s, w_{s-1}, v_{s-1}
   static const bool attr = [&]() {
     (void)hipFuncSetAttribute((const void*)k_hetrd_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(3 * sizeof(zd) * 2048));
-    (void)hipFuncSetAttribute((const void*)k_apply_reflectors,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)APPLY_LDS);
+    (void)hipFuncSetAttribute((const void*)k_apply_wy, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)WY_LDS);
     return true;
   }();
   (void)attr;
@@ -741,13 +841,18 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
   GEVP_HIP_TRY(hipGetLastError());
   if (n > 1) {
-    // columns per work-group so that two reflector slots plus the columns fit
-    // APPLY_LDS bytes
-    int cols = (int)((APPLY_LDS - 2 * (int64_t)shv) / (int64_t)shv);
-    if (cols > 4) cols = 4;
+    // columns per work-group: as many as fit WY_LDS next to the two reflector
+    // chunks and the w / u vectors, at most 8 (two per wave)
+    const int64_t fixed = (int64_t)sizeof(zd) * (2 * WYR * WYS);
+    int cols = (int)((WY_LDS - fixed) / ((int64_t)shv + 2 * (int64_t)sizeof(zd) * WYB));
+    if (cols > 8) cols = 8;
     if (cols < 1) return GEVP_ERR_INVALID;  // n > 2048 is not supported here
-    hipLaunchKernelGGL(k_apply_reflectors, dim3((n + cols - 1) / cols), dim3(256),
-                       shv * (2 + cols), c->stream, n, cols, Z, ldz, a.V, a.ldv, a.tau);
+    const size_t lds = (size_t)fixed + (size_t)cols * (shv + 2 * sizeof(zd) * WYB);
+    const int nblk = (n - 1 + WYB - 1) / WYB;
+    hipLaunchKernelGGL(k_wy_factors, dim3(nblk), dim3(256), 0, c->stream, n, a.V, a.ldv, a.tau, wyT);
+    GEVP_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_apply_wy, dim3((n + cols - 1) / cols), dim3(256), lds, c->stream, n, cols,
+                       Z, ldz, a.V, a.ldv, wyT);
     GEVP_HIP_TRY(hipGetLastError());
   }
   return GEVP_OK;
