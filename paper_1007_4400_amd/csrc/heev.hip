@@ -588,17 +588,33 @@ __global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_
 #pragma unroll
       for (int j = 0; j < WYB; ++j) acc[q][j] = make_double2(0.0, 0.0);
     const int nch = (n - r0 + WYR - 1) / WYR;
-    auto stage = [&](int ch, zd* buf) {
-      for (int e = tid; e < WYR * WYB; e += 256) {
-        const int rr = e % WYR, j = e / WYR, r = r0 + ch * WYR + rr;
-        buf[rr * WYS + j] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
+    // a chunk's entries go global -> registers before the current chunk's
+    // products and registers -> LDS after them, so the loads are in flight
+    // while the current chunk is used
+    constexpr int PQ = WYR * WYB / 256;
+    zd pre[PQ];
+    auto load_chunk = [&](int ch) {
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int e = tid + 256 * q, rr = e % WYR, j = e / WYR, r = r0 + ch * WYR + rr;
+        pre[q] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
       }
     };
-    if (nch > 0) stage(0, vb);
+    auto store_chunk = [&](zd* buf) {
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) {
+        const int e = tid + 256 * q;
+        buf[(e % WYR) * WYS + e / WYR] = pre[q];
+      }
+    };
+    if (nch > 0) {
+      load_chunk(0);
+      store_chunk(vb);
+    }
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
       zd* cur = vb + (ch & 1) * WYR * WYS;
-      if (ch + 1 < nch) stage(ch + 1, vb + ((ch + 1) & 1) * WYR * WYS);
+      if (ch + 1 < nch) load_chunk(ch + 1);
       const int r = r0 + ch * WYR + lane;
       if (r < n) {
 #pragma unroll
@@ -615,6 +631,7 @@ __global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_
           }
         }
       }
+      if (ch + 1 < nch) store_chunk(vb + ((ch + 1) & 1) * WYR * WYS);
       __syncthreads();  // the other buffer is complete, this one is free
     }
 #pragma unroll
@@ -640,12 +657,17 @@ __global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_
       uv[c * WYB + i] = u;
     }
     __syncthreads();
-    // (3) z <- z - V u, one thread per row
-    for (int r = r0 + tid; r < n; r += 256) {
-      zd v[WYB];
+    // (3) z <- z - V u, one thread per row, the next row's reflector entries
+    // loaded while the current row is updated
+    zd v[WYB], vn[WYB];
+    auto load_row = [&](int r, zd* dst) {
 #pragma unroll
       for (int j = 0; j < WYB; ++j)
-        v[j] = (j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
+        dst[j] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
+    };
+    load_row(r0 + tid, v);
+    for (int r = r0 + tid; r < n; r += 256) {
+      load_row(r + 256, vn);
       for (int c = 0; c < cols; ++c) {
         zd d = make_double2(0.0, 0.0);
 #pragma unroll
@@ -658,6 +680,8 @@ __global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_
         z.x -= d.x;
         z.y -= d.y;
       }
+#pragma unroll
+      for (int j = 0; j < WYB; ++j) v[j] = vn[j];
     }
     __syncthreads();
   }
