@@ -138,7 +138,7 @@ typedef struct {
        seed_dev_std  = standard deviation of the deviation angles.
      The matching minimises the summed deviation angles over permutations: each
      column's largest overlap when those are distinct (then optimal), else a
-     linear assignment on arccos|M| solved on the host in O(k^3).
+     linear assignment on arccos|M| solved on the device in O(k^3).
      -1 (and 0) when not computed. */
   double seed_sin_rms;
   double seed_dev_mean, seed_dev_max;
@@ -408,17 +408,18 @@ gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t
 gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t m,
                         const void* L, int64_t ldl, void* R, int64_t ldr);
 
-/* Eigen-decomposition of a small Hermitian matrix (n <= 2048) on the GPU:
- * H = Z diag(theta) Z^H, theta ascending.  H (lower read) is overwritten.
- * Synchronous. */
 /* Seed monitor of a k x k cross-overlap M = X0^H B X of two B-orthonormal
- * blocks (device complex128, 1 <= k <= 2048): stats (host double[5]) receives
+ * blocks (device complex128, 1 <= k <= 8192): stats (host double[5]) receives
  * sin_rms, dev_mean, dev_max, reindexed and dev_std as in gevp_info, match
- * (optional host int[k]) the seed column matched to each column.
- * Synchronous. */
+ * (optional host int[k]) the seed column matched to each column.  When two
+ * columns share a best match, the matching is the minimum-total-angle
+ * assignment, solved on the device.  Synchronous. */
 gevp_status gevp_k_seed_monitor(gevp_handle h, int64_t k, const void* M, int64_t ldm, double* stats,
                                 int* match);
 
+/* Eigen-decomposition of a small Hermitian matrix (n <= 2048) on the GPU:
+ * H = Z diag(theta) Z^H, theta ascending.  H (lower read) is overwritten.
+ * Synchronous. */
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh,
                         double* theta, void* Z, int64_t ldz);
 

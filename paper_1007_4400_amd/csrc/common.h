@@ -226,10 +226,12 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
                               const zd* V, int64_t ldv, const double* theta, double* out);
 gevp_status launch_colnorms(gevp_ctx* c, int64_t rows, int64_t cols, const zd* V, int64_t ldv,
                             double* out);
-// seed monitor of a k x k cross-overlap M, k <= 2048 (stat: 3k doubles; out:
-// 6 doubles).  seed_monitor_stats also completes it on the host and waits:
-// res = sin_rms, dev_mean, dev_max, reindexed, dev_std under the
-// angle-minimising matching, match[j] = matched seed column (may be null).
+// seed monitor of a k x k cross-overlap M (stat: 3k doubles; out: 6
+// doubles).  seed_monitor_stats also solves the angle-minimising matching on
+// the device when best matches collide, then copies the results and waits:
+// res = sin_rms, dev_mean, dev_max, reindexed, dev_std under that matching,
+// match[j] = matched seed column (may be null).  Beyond k = 4096 the
+// matching's work arrays need a device scratch of 48 (k + 1) bytes.
 // rnorm (device, k, optional): norms of the projection residuals of the seed
 // columns onto the result's span; sin_rms then comes from them instead of
 // from k - ||M||_F^2.
@@ -237,7 +239,8 @@ gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm
                                 double* out, const double* rnorm = nullptr);
 gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
                                double* out, double res[5], int* match,
-                               const double* rnorm = nullptr);
+                               const double* rnorm = nullptr, void* scratch = nullptr,
+                               size_t scratch_bytes = 0);
 gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                                const int* perm, zd* D, int64_t ldd);
 gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx);

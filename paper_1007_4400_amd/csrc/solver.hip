@@ -1463,11 +1463,13 @@ gevp_status gevp_k_trsm(gevp_handle h, char side, char trans, int64_t n, int64_t
 
 gevp_status gevp_k_seed_monitor(gevp_handle h, int64_t k, const void* M, int64_t ldm, double* stats,
                                 int* match) {
-  if (!h || k < 1 || k > 2048 || !M || ldm < k || !stats) return GEVP_ERR_INVALID;
+  if (!h || k < 1 || k > 8192 || !M || ldm < k || !stats) return GEVP_ERR_INVALID;
   GEVP_HIP_TRY(hipSetDevice(h->device));
-  GEVP_TRY(ws_reserve(h, ws_round(sizeof(double) * (3 * k + 8)) + 256));
+  const size_t sb = sizeof(double) * 6 * (k + 1);  // matching work arrays beyond the LDS limit
+  GEVP_TRY(ws_reserve(h, ws_round(sizeof(double) * (3 * k + 8)) + ws_round(sb) + 512));
   double* w = (double*)ws_take(h, sizeof(double) * (3 * k + 8));
-  return seed_monitor_stats(h, k, (const zd*)M, ldm, w, w + 3 * k, stats, match);
+  void* s = ws_take(h, sb);
+  return seed_monitor_stats(h, k, (const zd*)M, ldm, w, w + 3 * k, stats, match, nullptr, s, sb);
 }
 
 gevp_status gevp_k_heev(gevp_handle h, int64_t n, void* H, int64_t ldh, double* theta, void* Z,

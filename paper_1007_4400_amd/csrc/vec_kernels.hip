@@ -207,6 +207,8 @@ __global__ __launch_bounds__(256) void k_seed_cols(int k, const zd* M, int64_t l
   }
 }
 
+constexpr int SEED_K_MAX = 8192;  // columns of the seed monitor
+
 // Seed monitor totals.  out[0] sin_rms: sqrt(sum_j rnorm[j]^2 / k) when the
 // norms of the projection residuals R = X0 - P X0 (P the orthogonal projector
 // onto the result's span) are given, else sqrt(max(0, k - ||M||_F^2) / k)
@@ -215,12 +217,12 @@ __global__ __launch_bounds__(256) void k_seed_cols(int k, const zd* M, int64_t l
 // acos(min(1, max_i |M(i,j)|)) / (pi/2) (best match per column), out[3]
 // columns whose best match is not their own index, out[4] standard deviation
 // of the angles, out[5] = 1 when two columns share a best match (the
-// per-column matches are then no permutation and the host solves the
-// assignment).  k <= 2048.
+// per-column matches are then no permutation and k_seed_assign solves the
+// assignment).  k <= SEED_K_MAX.
 __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, const double* rnorm,
                                                      double* out) {
   __shared__ double sf[256], sd[256], sx[256], sr[256], sq[256];
-  __shared__ int hits[2048];
+  __shared__ int hits[SEED_K_MAX];
   __shared__ int clash;
   const int t = threadIdx.x;
   for (int i = t; i < k; i += 256) hits[i] = 0;
@@ -261,6 +263,178 @@ __global__ __launch_bounds__(256) void k_seed_finish(int k, const double* stat, 
     out[3] = sr[0];
     out[4] = sqrt(fmax(0.0, sq[0] / (double)k - mean * mean));
     out[5] = clash ? 1.0 : 0.0;
+  }
+}
+
+// When two result columns share a best-matching seed column (out[5] set by
+// k_seed_finish), the re-indexing is the angle-minimising assignment: a
+// minimum-cost perfect matching on the deviation angles acos|M(i, j)| (row:
+// result column j, column: seed column i), solved by shortest augmenting
+// paths with row and column potentials (Kuhn-Munkres, O(k^3)) in one
+// work-group: rows are added one at a time, and every step of a path scans
+// the columns in parallel and takes the smallest reduced cost (ties to the
+// lowest column).  The matching replaces the best matches in stat[3 j + 2],
+// and the deviation statistics out[1..4] are recomputed from it.  Without a
+// clash the kernel returns at once.  The six work arrays (k + 1 entries each)
+// sit in LDS up to ASG_LDS_K columns and in a device buffer beyond.
+constexpr int ASG_T = 1024;
+constexpr int ASG_LDS_K = 4096;
+constexpr size_t asg_bytes(int64_t k) { return (size_t)(k + 1) * (3 * sizeof(double) + 3 * sizeof(int)); }
+template <bool GLB>
+__global__ __launch_bounds__(ASG_T) void k_seed_assign(int k, const zd* M, int64_t ldm, double* stat,
+                                                       double* out, double* gbuf) {
+  if (out[5] == 0.0) return;  // uniform: every best match is distinct
+  extern __shared__ double asg_lds[];
+  double* asg = GLB ? gbuf : asg_lds;
+  double* u = asg;                       // k + 1 row potentials (1-based rows)
+  double* v = u + (k + 1);               // k + 1 column potentials
+  double* minv = v + (k + 1);            // k + 1
+  int* row_of = (int*)(minv + (k + 1));  // k + 1; column 0 is the sentinel
+  int* way = row_of + (k + 1);           // k + 1
+  int* used = way + (k + 1);             // k + 1
+  __shared__ double rv[ASG_T / 64];
+  __shared__ int rc[ASG_T / 64];
+  __shared__ int c0s;
+  __shared__ double deltas;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr int NONE = 0x7fffffff;
+  // (value, column) order of the path step: a real column before none, then
+  // the smaller value, then the smaller column
+  auto better = [](double a, int ca, double b, int cb) {
+    return ca != NONE && (cb == NONE || a < b || (a == b && ca < cb));
+  };
+  auto cost = [&](int r, int c) {  // 1-based row r (result column), column c (seed column)
+    const zd m = M[(int64_t)(r - 1) * ldm + (c - 1)];
+    return acos(fmin(1.0, sqrt(m.x * m.x + m.y * m.y)));
+  };
+  for (int c = t; c <= k; c += ASG_T) {
+    u[c] = 0.0;
+    v[c] = 0.0;
+    row_of[c] = 0;
+    way[c] = 0;
+  }
+  __syncthreads();
+  for (int r = 1; r <= k; ++r) {
+    for (int c = t; c <= k; c += ASG_T) {
+      minv[c] = 1e300;
+      used[c] = 0;
+    }
+    if (t == 0) {
+      row_of[0] = r;
+      c0s = 0;
+    }
+    __syncthreads();
+    for (;;) {
+      const int c0 = c0s;
+      if (t == 0) used[c0] = 1;
+      __syncthreads();
+      const int r0 = row_of[c0];
+      // reduced costs of row r0, and the smallest over the unused columns
+      double best = 1e300;
+      int bc = NONE;
+      for (int c = 1 + t; c <= k; c += ASG_T) {
+        if (used[c]) continue;
+        const double cur = cost(r0, c) - u[r0] - v[c];
+        if (cur < minv[c]) {
+          minv[c] = cur;
+          way[c] = c0;
+        }
+        // c increases along this thread's columns; any unused column is a
+        // valid pick, so a non-finite cost cannot leave the path without one
+        if (bc == NONE || minv[c] < best) {
+          best = minv[c];
+          bc = c;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oc = __shfl_xor(bc, o, 64);
+        if (better(ob, oc, best, bc)) {
+          best = ob;
+          bc = oc;
+        }
+      }
+      if (lane == 0) {
+        rv[wave] = best;
+        rc[wave] = bc;
+      }
+      __syncthreads();
+      if (t == 0) {
+        double b = rv[0];
+        int cc = rc[0];
+        for (int w = 1; w < ASG_T / 64; ++w)
+          if (better(rv[w], rc[w], b, cc)) {
+            b = rv[w];
+            cc = rc[w];
+          }
+        deltas = b;
+        c0s = cc;
+      }
+      __syncthreads();
+      const double delta = deltas;
+      for (int c = t; c <= k; c += ASG_T) {
+        if (used[c]) {
+          u[row_of[c]] += delta;
+          v[c] -= delta;
+        } else {
+          minv[c] -= delta;
+        }
+      }
+      __syncthreads();
+      const bool free_col = row_of[c0s] == 0;  // uniform: c0s and row_of[] are shared
+      __syncthreads();                         // read by all before the path is flipped
+      if (free_col) break;
+    }
+    if (t == 0) {  // flip the augmenting path
+      int c0 = c0s;
+      do {
+        const int c1 = way[c0];
+        row_of[c0] = row_of[c1];
+        c0 = c1;
+      } while (c0 != 0);
+    }
+    __syncthreads();
+  }
+  // the matching (seed column of result column j) and its statistics
+  __shared__ double sd[ASG_T / 64], sq[ASG_T / 64], sx[ASG_T / 64], sr[ASG_T / 64];
+  double d = 0.0, q = 0.0, x = 0.0, re = 0.0;
+  for (int c = 1 + t; c <= k; c += ASG_T) {
+    const int j = row_of[c] - 1, i = c - 1;  // result column j takes seed column i
+    stat[3 * j + 2] = (double)i;
+    const double dv = cost(j + 1, c) * 0.63661977236758134;  // / (pi/2)
+    d += dv;
+    q += dv * dv;
+    x = fmax(x, dv);
+    re += (i != j) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o, 64);
+    q += __shfl_xor(q, o, 64);
+    x = fmax(x, __shfl_xor(x, o, 64));
+    re += __shfl_xor(re, o, 64);
+  }
+  if (lane == 0) {
+    sd[wave] = d;
+    sq[wave] = q;
+    sx[wave] = x;
+    sr[wave] = re;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double D = 0.0, Q = 0.0, X = 0.0, R = 0.0;
+    for (int w = 0; w < ASG_T / 64; ++w) {
+      D += sd[w];
+      Q += sq[w];
+      X = fmax(X, sx[w]);
+      R += sr[w];
+    }
+    const double mean = D / (double)k;
+    out[1] = mean;
+    out[2] = X;
+    out[3] = R;
+    out[4] = sqrt(fmax(0.0, Q / (double)k - mean * mean));
   }
 }
 
@@ -518,7 +692,7 @@ gevp_status launch_resid_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd*
 gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
                                 double* out, const double* rnorm) {
   if (k <= 0) return GEVP_OK;
-  if (k > 2048) return GEVP_ERR_INVALID;
+  if (k > SEED_K_MAX) return GEVP_ERR_INVALID;
   hipLaunchKernelGGL(k_seed_cols, dim3((unsigned)k), dim3(256), 0, c->stream, (int)k, M, ldm, stat);
   GEVP_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_seed_finish, dim3(1), dim3(256), 0, c->stream, (int)k, stat, rnorm, out);
@@ -526,100 +700,33 @@ gevp_status launch_seed_monitor(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm
   return GEVP_OK;
 }
 
-namespace {
-// Minimum-cost assignment of an n x n cost matrix (row r, column c at
-// a[r * n + c]) by shortest augmenting paths with row and column potentials
-// (Kuhn-Munkres, O(n^3)); returns col_of_row.
-std::vector<int> min_cost_assignment(const std::vector<double>& a, int n) {
-  const double inf = 1e300;
-  std::vector<double> u(n + 1, 0.0), v(n + 1, 0.0), minv(n + 1);
-  std::vector<int> row_of(n + 1, 0), way(n + 1, 0);  // 1-based; column 0 is a sentinel
-  std::vector<char> used(n + 1);
-  for (int r = 1; r <= n; ++r) {
-    row_of[0] = r;
-    int c0 = 0;
-    std::fill(minv.begin(), minv.end(), inf);
-    std::fill(used.begin(), used.end(), 0);
-    do {
-      used[c0] = 1;
-      const int r0 = row_of[c0];
-      double delta = inf;
-      int c1 = 0;
-      for (int c = 1; c <= n; ++c) {
-        if (used[c]) continue;
-        const double cur = a[(size_t)(r0 - 1) * n + (c - 1)] - u[r0] - v[c];
-        if (cur < minv[c]) {
-          minv[c] = cur;
-          way[c] = c0;
-        }
-        if (minv[c] < delta) {
-          delta = minv[c];
-          c1 = c;
-        }
-      }
-      for (int c = 0; c <= n; ++c) {
-        if (used[c]) {
-          u[row_of[c]] += delta;
-          v[c] -= delta;
-        } else {
-          minv[c] -= delta;
-        }
-      }
-      c0 = c1;
-    } while (row_of[c0] != 0);
-    do {  // flip the augmenting path
-      const int c1 = way[c0];
-      row_of[c0] = row_of[c1];
-      c0 = c1;
-    } while (c0 != 0);
-  }
-  std::vector<int> col_of(n, 0);
-  for (int c = 1; c <= n; ++c) col_of[row_of[c] - 1] = c - 1;
-  return col_of;
-}
-}  // namespace
-
 gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm, double* stat,
-                               double* out, double res[5], int* match, const double* rnorm) {
+                               double* out, double res[5], int* match, const double* rnorm,
+                               void* scratch, size_t scratch_bytes) {
   GEVP_TRY(launch_seed_monitor(c, k, M, ldm, stat, out, rnorm));
+  if (k <= ASG_LDS_K) {
+    static const bool attr = [] {
+      (void)hipFuncSetAttribute((const void*)k_seed_assign<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)asg_bytes(ASG_LDS_K));
+      return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(k_seed_assign<false>, dim3(1), dim3(ASG_T), asg_bytes(k), c->stream, (int)k, M,
+                       ldm, stat, out, nullptr);
+  } else {
+    if (!scratch || scratch_bytes < asg_bytes(k)) return GEVP_ERR_INVALID;
+    hipLaunchKernelGGL(k_seed_assign<true>, dim3(1), dim3(ASG_T), 0, c->stream, (int)k, M, ldm, stat,
+                       out, (double*)scratch);
+  }
+  GEVP_HIP_TRY(hipGetLastError());
   double h[6];
   std::vector<double> st(3 * k);
   GEVP_HIP_TRY(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   GEVP_HIP_TRY(hipMemcpyAsync(st.data(), stat, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, c->stream));
   GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
   for (int i = 0; i < 5; ++i) res[i] = h[i];
-  std::vector<int> best(k);
-  for (int64_t j = 0; j < k; ++j) best[j] = (int)st[3 * j + 2];
-  if (h[5] != 0.0) {
-    // two columns share a best match: the angle-minimising matching is a
-    // linear assignment on the deviation angles (host, O(k^3))
-    std::vector<zd> hm((size_t)k * k);
-    GEVP_HIP_TRY(hipMemcpy2DAsync(hm.data(), sizeof(zd) * k, M, sizeof(zd) * ldm, sizeof(zd) * k, k,
-                                  hipMemcpyDeviceToHost, c->stream));
-    GEVP_HIP_TRY(hipStreamSynchronize(c->stream));
-    std::vector<double> cost((size_t)k * k);  // row: result column j, column: seed column i
-    for (int64_t j = 0; j < k; ++j)
-      for (int64_t i = 0; i < k; ++i) {
-        const zd m = hm[(size_t)j * k + i];
-        cost[(size_t)j * k + i] = std::acos(std::min(1.0, std::sqrt(m.x * m.x + m.y * m.y)));
-      }
-    best = min_cost_assignment(cost, (int)k);
-    double sum = 0.0, sq = 0.0, mx = 0.0, re = 0.0;
-    for (int64_t j = 0; j < k; ++j) {
-      const double dv = cost[(size_t)j * k + best[j]] * 0.63661977236758134;  // / (pi/2)
-      sum += dv;
-      sq += dv * dv;
-      mx = std::max(mx, dv);
-      re += (best[j] != j) ? 1.0 : 0.0;
-    }
-    const double mean = sum / (double)k;
-    res[1] = mean;
-    res[2] = mx;
-    res[3] = re;
-    res[4] = std::sqrt(std::max(0.0, sq / (double)k - mean * mean));
-  }
   if (match)
-    for (int64_t j = 0; j < k; ++j) match[j] = best[j];
+    for (int64_t j = 0; j < k; ++j) match[j] = (int)st[3 * j + 2];
   return GEVP_OK;
 }
 

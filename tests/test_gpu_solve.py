@@ -198,12 +198,15 @@ def _unitary(k, rng):
 
 
 @pytest.mark.parametrize("k,kind", [(3, "mix"), (6, "mix"), (40, "mix"), (300, "near"),
-                                    (64, "identity"), (1, "identity")])
+                                    (64, "identity"), (1, "identity"), (2500, "near"),
+                                    (4500, "mix")])
 def test_seed_monitor_entry_matches_oracle(h, oracle_mod, k, kind):
     """gevp_k_seed_monitor on constructed overlaps: random unitary mixings
-    (the per-column best matches collide, the host assignment runs), a
+    (the per-column best matches collide and the device assignment runs), a
     near-permutation (a permuted identity rotated by small angles) and the
-    identity, against the oracle's assignment."""
+    identity, against the oracle's assignment.  k = 2500 keeps the
+    assignment's work arrays in LDS at their largest; k = 4500 puts them in
+    device memory."""
     rng = np.random.default_rng(k)
     if kind == "mix":
         M = _unitary(k, rng)
