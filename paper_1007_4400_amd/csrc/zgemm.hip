@@ -3,12 +3,18 @@
 //   D = alpha op(A) op(B) + beta Cm + gamma diag(gcol) E
 //
 // op() is identity or conjugate transpose.  The complex product is formed
-// from four real products per 16 x 16 block:
-//   Re += Ar Br - Ai Bi,   Im += Ar Bi + Ai Br
-// on interleaved (re, im) operands, so no planar copy of the inputs exists.
+// from three real products per 16 x 16 block (Gauss's three-multiplication
+// form, as in the 3M complex GEMMs):
+//   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + Ai)(Br + Bi)
+//   Re = P1 - P2,  Im = P3 - P1 - P2
+// on interleaved (re, im) operands (the two sums are formed in registers from
+// the LDS slices), so no planar copy of the inputs exists.  Three MFMAs per
+// block and K step instead of four; the error of Im is bounded by the unit
+// roundoff times (|Ar| + |Ai|)(|Br| + |Bi|) instead of times |A||B|, a factor
+// of at most 2 in the normwise bounds.
 //
 // Tiling: a 256-thread work-group owns a 64 x 64 complex output tile; each of
-// its four waves owns 32 x 32 (2 x 2 MFMA blocks, 8 accumulators).  K is
+// its four waves owns 32 x 32 (2 x 2 MFMA blocks, 12 accumulators).  K is
 // walked in slices of 16 complex values staged through LDS (double buffered,
 // with the next slice's global loads in flight during the current slice's
 // MFMAs).  Rows of the LDS slices are padded by one element so that the
@@ -120,13 +126,14 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lg = lane >> 4;
 
-  d4 accR[2][2], accI[2][2];
+  d4 acc1[2][2], acc2[2][2], acc3[2][2];  // P1, P2, P3 of the three-product form
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      accR[i][j] = d4{0, 0, 0, 0};
-      accI[i][j] = d4{0, 0, 0, 0};
+      acc1[i][j] = d4{0, 0, 0, 0};
+      acc2[i][j] = d4{0, 0, 0, 0};
+      acc3[i][j] = d4{0, 0, 0, 0};
     }
 
   zd ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;  // next slice, in registers
@@ -209,31 +216,33 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kk = ks * 4 + lg;
       zd a[2], b[2];
+      double sa[2], sb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk][wr * 32 + i * 16 + l16];
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[cur][kk][wr * 32 + i * 16 + l16];
+        sa[i] = a[i].x + a[i].y;
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk][wc * 32 + j * 16 + l16];
-      // four independent accumulator sweeps keep the MFMA pipe busy
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, accR[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].y, accI[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) {
+        b[j] = Bs[cur][kk][wc * 32 + j * 16 + l16];
+        sb[j] = b[j].x + b[j].y;
+      }
+      // three independent accumulator sweeps keep the MFMA pipe busy
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, b[j].y, accR[i][j], 0, 0, 0);
+          acc1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, b[j].x, acc1[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, b[j].y, acc2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sb[j], acc3[i][j], 0, 0, 0);
     }
     if (t + 1 < t1) STORE_(cur ^ 1);
     __syncthreads();
@@ -245,6 +254,15 @@ __device__ __forceinline__ void zgemm_tile(const ZgemmParams& p) {
 #undef STB_
 #undef STORE_
 
+  // the complex result of the three products
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = acc1[i][j] - acc2[i][j];
+      accI[i][j] = acc3[i][j] - acc1[i][j] - acc2[i][j];
+    }
   // D layout of v_mfma_f64_16x16x4: lane l, register r -> row l/16 + 4r, col l%16
   if (p.splits > 1) {  // raw partial tile, [col][row] within the tile
     zd* pt = p.part + ((int64_t)kc * p.tiles + tile) * (BM * BN);
@@ -325,7 +343,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_sk(ZgemmParams p) {
   const int row0 = tm * SM, col0 = tn * SN;
   const int l16 = lane & 15, lg = lane >> 4;
   const int bm = TALL ? wave : 0, bn = TALL ? 0 : wave;  // this wave's 16 x 16 block
-  d4 accR = d4{0, 0, 0, 0}, accI = d4{0, 0, 0, 0};
+  d4 acc1 = d4{0, 0, 0, 0}, acc2 = d4{0, 0, 0, 0}, acc3 = d4{0, 0, 0, 0};  // three-product form
   constexpr int LA = SM * KT / NTHR, LB = SN * KT / NTHR;  // loads per thread and slice
   zd ra[LA], rb[LB];
   // thread -> (m, k) of op(A) and (k, n) of op(B), the stored layout's fast
@@ -385,14 +403,14 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_sk(ZgemmParams p) {
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kk = ks * 4 + lg;
       const zd a = As[cur][kk][bm * 16 + l16], b = Bs[cur][kk][bn * 16 + l16];
-      accR = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, accI, 0, 0, 0);
-      accR = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accR, 0, 0, 0);
-      accI = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, accI, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, acc3, 0, 0, 0);
     }
     if (t + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
+  const d4 accR = acc1 - acc2, accI = acc3 - acc1 - acc2;
   const int col = col0 + bn * 16 + l16;
   if (col >= p.N) return;
   const bool useC = (p.Cm != nullptr) && (p.beta != 0.0);
