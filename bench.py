@@ -585,6 +585,10 @@ def _roofline_gemm(infos):
         "kernel_ms_per_step": ms / max(len(infos), 1),
         "algorithmic_flops_per_unit": "8 flops per complex multiply-add: 8 m n k for a dense product, "
                                       "half where only one triangle of the output or of op(A) is involved",
+        # the kernels form a complex product from three real products (Gauss),
+        # so they execute 6 of the 8 algorithmic flops of a complex multiply-add
+        "executed_per_algorithmic": 0.75,
+        "executed_frac": achieved * 0.75 / peak,
     }
 
 

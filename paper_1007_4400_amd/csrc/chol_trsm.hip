@@ -392,14 +392,16 @@ gevp_status copy_ct(gevp_ctx* c, int64_t m, int64_t k, const zd* in, int64_t ldi
 // the panel stream may factor that panel, then to the rest of the lower
 // triangle, which overlaps the factorisation.
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
-                       int* info_dev, hipEvent_t midpoint) {
+                       int* info_dev, hipEvent_t midpoint, zd* R, int64_t ldr, int64_t m) {
   constexpr int64_t PW = 6 * NB;  // measured at n = 8192: 30 ms; 128: 31, 256: 32, 512: 33
   if (n <= 0) {
     if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
     return GEVP_OK;
   }
+  const bool rhs = R != nullptr && m > 0;
   if (n <= NB) {
     GEVP_TRY(potrf_leaf(c, n, M, ldm, Dinv, ldi, info_dev, 0));
+    if (rhs) GEVP_TRY(trsm_left_lower_n(c, n, m, M, ldm, Dinv, ldi, R, ldr));
     if (midpoint) GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));
   } else {
     const int64_t half = ((n + NB - 1) / NB / 2) * NB;  // first row of the second half
@@ -458,6 +460,15 @@ gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int
           GEVP_TRY(launch_zgemm(c, 0, 0, rest2, rest2, pw, -1.0, Lp + pw1, ldm, LpH + pw1 * ldm,
                                 ldm, 1.0, A3, ldm, 0.0, nullptr, 0, nullptr, A3, ldm, nullptr, 1));
         }
+      }
+      if (rhs) {
+        // block row of the forward substitution: R_p <- L_pp^{-1} R_p (every
+        // earlier panel's update of these rows is queued before it on this
+        // stream), then the rows below: R_rest -= L_rest,p R_p
+        GEVP_TRY(trsm_left_lower_n(c, pw, m, M + p0 + p0 * ldm, ldm, Dinv + p0, ldi, R + p0, ldr));
+        if (rest > 0)
+          GEVP_TRY(launch_zgemm(c, 0, 0, rest, m, pw, -1.0, Lp, ldm, R + p0, ldr, 1.0, R + pend, ldr,
+                                0.0, nullptr, 0, nullptr, R + pend, ldr));
       }
       if (midpoint && !mid_done && pend >= half) {
         GEVP_HIP_TRY(hipEventRecord(midpoint, c->stream));

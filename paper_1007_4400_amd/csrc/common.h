@@ -146,8 +146,14 @@ gevp_status launch_zgemm(gevp_ctx* c, int opA, int opB, int64_t m, int64_t n, in
 // (device int) receives the first failing pivot (1-based) or stays 0.  If
 // given, `midpoint` is recorded on c->stream once half the block columns
 // are queued (from there on the factorisation leaves most compute units idle).
+// If R is given (n x m, ld ldr), it is overwritten by L^{-1} R, the forward
+// substitution carried along panel by panel: each block row of R is solved
+// with its panel's diagonal block as soon as that panel is factored and
+// updated with the panel below it, work that overlaps the factorisation of
+// the next panel.
 gevp_status chol_lower(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, zd* Dinv, int64_t ldi,
-                       int* info_dev, hipEvent_t midpoint = nullptr);
+                       int* info_dev, hipEvent_t midpoint = nullptr, zd* R = nullptr,
+                       int64_t ldr = 0, int64_t m = 0);
 // R <- L^{-1} R (R n x m) ;  R <- L^{-H} R ;  R <- R L^{-H} (R m x n)
 // lhu = 1: the strictly upper triangle of L holds L^H (see launch_mirror_lower),
 // and the off-diagonal products read those blocks as stored instead of

@@ -4,10 +4,10 @@
 // One solve (the paper's fast iteration, section 2, seeded by the previous
 // iteration's eigenvectors):
 //   stage    A, B lower triangles -> full Hermitian copies; NaN/Inf scan
-//   chol     B = L L^H (blocked, lookahead on a panel stream); L^H X0 for a
+//   chol     B = L L^H (blocked, lookahead on a panel stream) with the left
+//            solve W = L^{-1} A carried along panel by panel; L^H X0 for a
 //            seeded solve, then L^H copied into L's upper triangle
-//   reduce   C = L^{-1} A L^{-H} (left solve, then the lower triangle of the
-//            right solve, mirrored)
+//   reduce   C = W L^{-H} (the lower triangle of the right solve, mirrored)
 //   bounds   Lanczos on C (filter interval), on A and B (norm estimates)
 //   seed     Y0 = [L^H X0, random], or random for a cold start; a full seed's
 //            first projection X0^H A X0 and its eigensolve run on a second
@@ -739,9 +739,12 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
   }
 
   // ---------------- Cholesky of B
+  // (with the first half of the reduction, W = L^{-1} A, carried along the
+  // factorisation: C starts as a copy of A)
   tm.start();
   GEVP_TRY(launch_copy2d(c, n, n, Bf, n, L, n));
-  GEVP_TRY(chol_lower(c, n, L, n, Dinv, n, flags + 1, spec ? evs.mid : nullptr));
+  GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
+  GEVP_TRY(chol_lower(c, n, L, n, Dinv, n, flags + 1, spec ? evs.mid : nullptr, C, n, n));
   tm.stop(info, GEVP_STAGE_CHOL);
   if (spec) {  // second stream, from the Cholesky's midpoint on
     GEVP_HIP_TRY(hipStreamWaitEvent(ax->stream, evs.mid, 0));
@@ -780,9 +783,8 @@ gevp_status gevp_solve(gevp_handle h, const gevp_opts* opts, int64_t n, const vo
 
   // ---------------- reduction to standard form
   tm.start();
-  GEVP_TRY(launch_copy2d(c, n, n, Af, n, C, n));
-  GEVP_TRY(trsm_left_lower_n(c, n, n, L, n, Dinv, n, C, n));
-  // C = W L^{-H} is Hermitian: only its lower triangle is formed, then mirrored
+  // C = W L^{-H} (W = L^{-1} A, formed with the factorisation) is Hermitian:
+  // only its lower triangle is formed, then mirrored
   GEVP_TRY(trsm_right_lower_c_lowerpart(c, n, L, n, Dinv, n, C, n, 1));
   GEVP_TRY(launch_mirror_lower(c, n, C, n, C, n, flags + 3));
   if (lp && bf16) GEVP_TRY(launch_split_rows_bf16(c, n, C, n, Clp));

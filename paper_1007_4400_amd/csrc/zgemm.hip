@@ -326,8 +326,8 @@ __global__ __launch_bounds__(NTHR, 2) void k_zgemm_cc(ZgemmParams p) { zgemm_til
 // and 64-wide updates of the triangular solves and the panel products of the
 // Cholesky factorisation.  With 64 x 64 tiles such a product has one tile per
 // 64 columns (or rows), so 15 work-groups for a 64 x 948 result, and each of
-// their waves runs a chain of 16 MFMAs per 4 K; here each of the four waves
-// owns one 16 x 16 block (4 MFMAs per 4 K), so the work-groups are four times
+// their waves runs a chain of 12 MFMAs per 4 K; here each of the four waves
+// owns one 16 x 16 block (3 MFMAs per 4 K), so the work-groups are four times
 // as many and their chains four times shorter.  A tile still spans every row
 // (TALL) or every column (wide) of the result, so a base case that writes its
 // right operand in place (TALL) or its left operand in place (wide) reads its
