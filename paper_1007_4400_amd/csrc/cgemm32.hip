@@ -8,8 +8,9 @@
 // P the previous one (D may alias P) and R the FP32 residual block.  With
 // beta_j = 0 the G term is not read, so the kernel also serves general
 // products D = alpha A G + gamma P (A of m rows, G of k rows).  Same tiling,
-// LDS staging and XCD-aware tile order as the FP64 kernel; the accumulators
-// are FP32.
+// LDS staging, XCD-aware tile order and three-real-product complex form
+// (P1 = Ar Gr, P2 = Ai Gi, P3 = (Ar + Ai)(Gr + Gi); Re = P1 - P2,
+// Im = P3 - P1 - P2) as the FP64 kernel; the accumulators are FP32.
 #include "common.h"
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -53,13 +54,14 @@ __global__ __launch_bounds__(NTHR, 2) void k_cgemm32_filter(CgemmParams p) {
   const int wr = wave >> 1, wc = wave & 1;
   const int l16 = lane & 15, lg = lane >> 4;
 
-  f4 accR[2][2], accI[2][2];
+  f4 acc1[2][2], acc2[2][2], acc3[2][2];  // P1, P2, P3 of the three-product form
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      accR[i][j] = f4{0, 0, 0, 0};
-      accI[i][j] = f4{0, 0, 0, 0};
+      acc1[i][j] = f4{0, 0, 0, 0};
+      acc2[i][j] = f4{0, 0, 0, 0};
+      acc3[i][j] = f4{0, 0, 0, 0};
     }
   zf ra[4], rb[4];
   auto load = [&](int k0) {
@@ -97,34 +99,44 @@ __global__ __launch_bounds__(NTHR, 2) void k_cgemm32_filter(CgemmParams p) {
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kk = ks * 4 + lg;
       zf a[2], b[2];
+      float sa[2], sb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk][wr * 32 + i * 16 + l16];
+      for (int i = 0; i < 2; ++i) {
+        a[i] = As[cur][kk][wr * 32 + i * 16 + l16];
+        sa[i] = a[i].x + a[i].y;
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk][wc * 32 + j * 16 + l16];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, accR[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].y, accI[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) {
+        b[j] = Bs[cur][kk][wc * 32 + j * 16 + l16];
+        sb[j] = b[j].x + b[j].y;
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i].y, b[j].y, accR[i][j], 0, 0, 0);
+          acc1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, acc1[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].x, accI[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].y, acc2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[i], sb[j], acc3[i][j], 0, 0, 0);
     }
     if (t + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
+  f4 accR[2][2], accI[2][2];  // the complex result of the three products
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = acc1[i][j] - acc2[i][j];
+      accI[i][j] = acc3[i][j] - acc1[i][j] - acc2[i][j];
+    }
   // D layout of v_mfma_f32_16x16x4f32: lane l, register r -> row 4 (l/16) + r, col l%16
 #pragma unroll
   for (int i = 0; i < 2; ++i)
