@@ -14,9 +14,10 @@
 //     pivoting), one thread per eigenvalue, recurrences in registers; members
 //     of numerically degenerate clusters are then made orthonormal by
 //     modified Gram-Schmidt.
-//  4. Z = U Z_T by applying the reflectors in reverse order, in compact-WY
-//     blocks of 16 (one kernel forms every block's triangular factor, one
-//     applies the blocks to column slabs of Z held in LDS).
+//  4. Z = U Z_T with U = I - V T V^H for all reflectors at once: T^{-1} is
+//     diag(1/tau) plus the strict upper triangle of V^H V, so Z <- Z - V (T
+//     (V^H Z)) is a Gram product, a triangular solve and two products on the
+//     FP64 matrix cores.
 #include <cfloat>
 
 #include "common.h"
@@ -501,194 +502,6 @@ __global__ __launch_bounds__(256) void k_zt_to_complex(const double* Zt, int n, 
   }
 }
 
-// Z <- G_0 G_1 ... G_{n-2} Z in compact-WY blocks of WYB reflectors: block k
-// (reflectors s0 = WYB k ..) is G_{s0} ... G_{s0+b-1} = I - V T V^H with T
-// upper triangular (forward accumulation: T_ii = tau_i, T(0:i-1, i) =
-// -tau_i T(0:i-1, 0:i-1) V(:, 0:i-1)^H v_i), and the blocks are applied last
-// to first, Z <- Z - V (T (V^H Z)).  k_wy_factors forms every block's T (one
-// work-group per block); k_apply_wy keeps `cols` columns of Z in LDS per
-// work-group and, per block, (1) stages the block's reflectors 64 rows at a
-// time in LDS, where each wave accumulates V^H z for its columns, one row per
-// lane, (2) forms u = T w, (3) subtracts V u row by row.  Two dependent
-// passes per 16 reflectors instead of one barrier-separated step per
-// reflector.
-constexpr int WYB = 16;  // reflectors per block
-
-__global__ __launch_bounds__(256) void k_wy_factors(int n, const zd* V, int64_t ldv, const zd* tau,
-                                                    zd* Tg) {
-  __shared__ zd G[WYB][WYB];  // G[i][j] = v_i^H v_j, i < j
-  __shared__ zd T[WYB][WYB];  // T[r][c]
-  const int k = blockIdx.x, s0 = k * WYB;
-  const int nref = n - 1, b = (nref - s0 < WYB) ? nref - s0 : WYB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // Gram entries over the later reflector's support (rows >= s0 + j + 1)
-  for (int pidx = wave; pidx < WYB * WYB; pidx += 4) {
-    const int i = pidx / WYB, j = pidx % WYB;
-    if (!(i < j && j < b)) continue;
-    const zd* vi = V + (int64_t)(s0 + i) * ldv;
-    const zd* vj = V + (int64_t)(s0 + j) * ldv;
-    double sr = 0.0, si = 0.0;
-    for (int r = s0 + j + 1 + lane; r < n; r += 64) {
-      const zd a = vi[r], c = vj[r];  // conj(a) c
-      sr += a.x * c.x + a.y * c.y;
-      si += a.x * c.y - a.y * c.x;
-    }
-    sr = wsum(sr);
-    si = wsum(si);
-    if (lane == 0) G[i][j] = make_double2(sr, si);
-  }
-  if (tid < WYB * WYB) T[tid % WYB][tid / WYB] = make_double2(0.0, 0.0);
-  __syncthreads();
-  for (int i = 0; i < b; ++i) {
-    const zd ti = tau[s0 + i];
-    zd acc = make_double2(0.0, 0.0);
-    if (tid < i) {  // row tid of T(0:i-1, 0:i-1) G(0:i-1, i), T upper triangular
-      for (int m = tid; m < i; ++m) {
-        const zd t = cmul(T[tid][m], G[m][i]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-    }
-    __syncthreads();
-    if (tid < i) {
-      const zd v = cmul(ti, acc);
-      T[tid][i] = make_double2(-v.x, -v.y);
-    }
-    if (tid == i) T[i][i] = ti;
-    __syncthreads();
-  }
-  if (tid < WYB * WYB) Tg[(int64_t)k * WYB * WYB + tid] = T[tid % WYB][tid / WYB];  // column-major
-}
-
-constexpr int WYR = 64;       // rows of a staged reflector chunk
-constexpr int WYS = WYB + 1;  // LDS row stride of a chunk (odd: lanes on distinct banks)
-__global__ __launch_bounds__(256) void k_apply_wy(int n, int cols, zd* Z, int64_t ldz, const zd* V,
-                                                  int64_t ldv, const zd* Tg) {
-  extern __shared__ zd sm3[];
-  zd* sz = sm3;                       // cols x n
-  zd* vb = sm3 + (size_t)cols * n;    // 2 x WYR x WYS, [row][j]
-  zd* wv = vb + 2 * WYR * WYS;        // cols x WYB: w = V^H z
-  zd* uv = wv + cols * WYB;           // cols x WYB
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = blockIdx.x * cols;
-  const int nc = (n - c0 < cols) ? n - c0 : cols;
-  for (int q = 0; q < cols; ++q)
-    for (int i = tid; i < n; i += 256)
-      sz[(size_t)q * n + i] = (q < nc) ? Z[i + (int64_t)(c0 + q) * ldz] : make_double2(0.0, 0.0);
-  const int nref = n - 1, nblk = (nref + WYB - 1) / WYB;
-  __syncthreads();
-  for (int k = nblk - 1; k >= 0; --k) {
-    const int s0 = k * WYB, b = (nref - s0 < WYB) ? nref - s0 : WYB;
-    const int r0 = s0 + 1;  // first row any reflector of the block touches
-    // (1) w = V^H z: chunks of WYR rows staged in LDS (double buffered); wave
-    // w accumulates the columns w, w + 4, ... one row per lane
-    zd acc[2][WYB];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int j = 0; j < WYB; ++j) acc[q][j] = make_double2(0.0, 0.0);
-    const int nch = (n - r0 + WYR - 1) / WYR;
-    // a chunk's entries go global -> registers before the current chunk's
-    // products and registers -> LDS after them, so the loads are in flight
-    // while the current chunk is used
-    constexpr int PQ = WYR * WYB / 256;
-    zd pre[PQ];
-    auto load_chunk = [&](int ch) {
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        const int e = tid + 256 * q, rr = e % WYR, j = e / WYR, r = r0 + ch * WYR + rr;
-        pre[q] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
-      }
-    };
-    auto store_chunk = [&](zd* buf) {
-#pragma unroll
-      for (int q = 0; q < PQ; ++q) {
-        const int e = tid + 256 * q;
-        buf[(e % WYR) * WYS + e / WYR] = pre[q];
-      }
-    };
-    if (nch > 0) {
-      load_chunk(0);
-      store_chunk(vb);
-    }
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-      zd* cur = vb + (ch & 1) * WYR * WYS;
-      if (ch + 1 < nch) load_chunk(ch + 1);
-      const int r = r0 + ch * WYR + lane;
-      if (r < n) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int c = wave + 4 * q;
-          if (c < cols) {
-            const zd z = sz[(size_t)c * n + r];
-#pragma unroll
-            for (int j = 0; j < WYB; ++j) {  // conj(v) z
-              const zd v = cur[lane * WYS + j];
-              acc[q][j].x += v.x * z.x + v.y * z.y;
-              acc[q][j].y += v.x * z.y - v.y * z.x;
-            }
-          }
-        }
-      }
-      if (ch + 1 < nch) store_chunk(vb + ((ch + 1) & 1) * WYR * WYS);
-      __syncthreads();  // the other buffer is complete, this one is free
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = wave + 4 * q;
-#pragma unroll
-      for (int j = 0; j < WYB; ++j) {
-        const double xr = wsum(acc[q][j].x), xi = wsum(acc[q][j].y);
-        if (lane == 0 && c < cols) wv[c * WYB + j] = make_double2(xr, xi);
-      }
-    }
-    __syncthreads();
-    // (2) u = T w (T upper triangular, column-major)
-    const zd* T = Tg + (int64_t)k * WYB * WYB;
-    if (tid < cols * WYB) {
-      const int c = tid / WYB, i = tid % WYB;
-      zd u = make_double2(0.0, 0.0);
-      for (int m = i; m < b; ++m) {
-        const zd t = cmul(T[i + m * WYB], wv[c * WYB + m]);
-        u.x += t.x;
-        u.y += t.y;
-      }
-      uv[c * WYB + i] = u;
-    }
-    __syncthreads();
-    // (3) z <- z - V u, one thread per row, the next row's reflector entries
-    // loaded while the current row is updated
-    zd v[WYB], vn[WYB];
-    auto load_row = [&](int r, zd* dst) {
-#pragma unroll
-      for (int j = 0; j < WYB; ++j)
-        dst[j] = (r < n && j < b) ? V[r + (int64_t)(s0 + j) * ldv] : make_double2(0.0, 0.0);
-    };
-    load_row(r0 + tid, v);
-    for (int r = r0 + tid; r < n; r += 256) {
-      load_row(r + 256, vn);
-      for (int c = 0; c < cols; ++c) {
-        zd d = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < WYB; ++j) {
-          const zd t = cmul(v[j], uv[c * WYB + j]);
-          d.x += t.x;
-          d.y += t.y;
-        }
-        zd& z = sz[(size_t)c * n + r];
-        z.x -= d.x;
-        z.y -= d.y;
-      }
-#pragma unroll
-      for (int j = 0; j < WYB; ++j) v[j] = vn[j];
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < nc; ++q)
-    for (int i = tid; i < n; i += 256) Z[i + (int64_t)(c0 + q) * ldz] = sz[(size_t)q * n + i];
-}
-
 __global__ void k_tri_norm(const double* d, const double* e, int n, double* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double m = 0.0;
@@ -697,10 +510,6 @@ __global__ void k_tri_norm(const double* d, const double* e, int n, double* out)
   out[0] = m;
 }
 }  // namespace
-
-// work-groups of a tridiagonalisation step: one wave per trailing column
-// while n - 1 <= 4 G, at most one work-group per compute unit
-constexpr int64_t WY_LDS = 163840;     // LDS budget of the compact-WY application (bytes)
 
 // work-groups of the tridiagonalisation: one column per wave as far as the
 // order allows, and at most HT, since the next step's block reduction reads
@@ -741,6 +550,32 @@ gevp_status tridiag_eig(gevp_ctx* c, int64_t n64, const double* d, const double*
   return GEVP_OK;
 }
 
+// Back-transformation Z <- Q Z, Q = G_0 G_1 ... G_{k-1} = I - V T V^H with the
+// k = n - 1 reflectors G_i = I - tau_i v_i v_i^H as the columns of V.  For the
+// forward accumulation (T_ii = tau_i, T(0:i-1, i) = -tau_i T(0:i-1, 0:i-1)
+// V(:, 0:i-1)^H v_i) the inverse of T is diag(1/tau) + striu(V^H V) (the UT
+// transform), so with L = T^{-H} = diag(conj(1/tau)) + stril(V^H V):
+//   S = V^H Z,   S <- L^{-H} S (= T S),   Z <- Z - V S,
+// a Gram product, a triangular solve and two products on the FP64 matrix
+// cores.  A reflector with tau = 0 is the identity: its column of V is
+// cleared and its diagonal entry of L set to 1, which leaves it out.
+__global__ __launch_bounds__(256) void k_ut_clear(int n, int k, zd* V, int64_t ldv, const zd* tau) {
+  const int i = blockIdx.x;
+  if (i >= k) return;
+  const zd t = tau[i];
+  if (t.x != 0.0 || t.y != 0.0) return;
+  for (int r = threadIdx.x; r < n; r += 256) V[r + (int64_t)i * ldv] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_ut_diag(int k, zd* L, int64_t ldl, const zd* tau) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= k) return;
+  const zd t = tau[i];
+  const double dd = t.x * t.x + t.y * t.y;
+  // conj(1 / t) = t / |t|^2
+  L[i + (int64_t)i * ldl] = (dd == 0.0) ? make_double2(1.0, 0.0) : make_double2(t.x / dd, t.y / dd);
+}
+
 size_t heev_work_bytes(int64_t n) {
   const int G = trd_groups(n);
   size_t b = 0;
@@ -751,7 +586,8 @@ size_t heev_work_bytes(int64_t n) {
   b += ws_round(sizeof(zd) * 2 * G);          // pp
   b += ws_round(sizeof(double) * n * n);      // Zt
   b += tridiag_eig_work_bytes(n);
-  b += ws_round(sizeof(zd) * WYB * WYB * ((n + WYB - 1) / WYB));  // WY factors
+  b += 2 * ws_round(sizeof(zd) * n * n);     // L = T^{-H}, S
+  b += ws_round(sizeof(zd) * n * 64);         // inverses of L's diagonal blocks
   return b;
 }
 
@@ -817,7 +653,8 @@ gevp_status hetrd_launches(gevp_ctx* c, const TrdArgs& a, int G, size_t sh3) {
 gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* theta, zd* Z,
                        int64_t ldz, void* work) {
   if (n64 <= 0) return GEVP_OK;
-  if (n64 > 2048) return GEVP_ERR_INVALID;  // v_s and one column of Z must fit 64 KB of LDS
+  // the reflector step keeps at most QMAX rows per thread and three n-vectors in LDS
+  if (n64 > (int64_t)QMAX * HT) return GEVP_ERR_INVALID;
   const int n = (int)n64;
   const int G = trd_groups(n);
   char* w = (char*)work;
@@ -840,15 +677,15 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   a.G = G;
   double* Zt = (double*)take(sizeof(double) * n * n);
   void* tw = take(tridiag_eig_work_bytes(n));
-  zd* wyT = (zd*)take(sizeof(zd) * WYB * WYB * ((n + WYB - 1) / WYB));
+  zd* Lut = (zd*)take(sizeof(zd) * n * n);
+  zd* Sut = (zd*)take(sizeof(zd) * n * n);
+  zd* Dut = (zd*)take(sizeof(zd) * n * 64);
 
   const size_t shv = sizeof(zd) * (size_t)n;
   const size_t sh3 = 3 * shv;  // v_s, w_{s-1}, v_{s-1}
   static const bool attr = [&]() {
     (void)hipFuncSetAttribute((const void*)k_hetrd_step, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(3 * sizeof(zd) * 2048));
-    (void)hipFuncSetAttribute((const void*)k_apply_wy, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)WY_LDS);
     return true;
   }();
   (void)attr;
@@ -865,19 +702,20 @@ gevp_status heev_small(gevp_ctx* c, int64_t n64, zd* H, int64_t ldh, double* the
   hipLaunchKernelGGL(k_zt_to_complex, dim3(tb, tb), dim3(256), 0, c->stream, Zt, n, Z, ldz);
   GEVP_HIP_TRY(hipGetLastError());
   if (n > 1) {
-    // columns per work-group: as many as fit WY_LDS next to the two reflector
-    // chunks and the w / u vectors, at most 8 (two per wave)
-    const int64_t fixed = (int64_t)sizeof(zd) * (2 * WYR * WYS);
-    int cols = (int)((WY_LDS - fixed) / ((int64_t)shv + 2 * (int64_t)sizeof(zd) * WYB));
-    if (cols > 8) cols = 8;
-    if (cols < 1) return GEVP_ERR_INVALID;  // n > 2048 is not supported here
-    const size_t lds = (size_t)fixed + (size_t)cols * (shv + 2 * sizeof(zd) * WYB);
-    const int nblk = (n - 1 + WYB - 1) / WYB;
-    hipLaunchKernelGGL(k_wy_factors, dim3(nblk), dim3(256), 0, c->stream, n, a.V, a.ldv, a.tau, wyT);
+    const int k = n - 1;
+    hipLaunchKernelGGL(k_ut_clear, dim3((unsigned)k), dim3(256), 0, c->stream, n, k, a.V, a.ldv, a.tau);
     GEVP_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_apply_wy, dim3((n + cols - 1) / cols), dim3(256), lds, c->stream, n, cols,
-                       Z, ldz, a.V, a.ldv, wyT);
+    GEVP_TRY(launch_zgemm(c, 1, 0, k, k, n, 1.0, a.V, a.ldv, a.V, a.ldv, 0.0, nullptr, 0, 0.0, nullptr,
+                          0, nullptr, Lut, k, nullptr, 1));  // lower triangle of V^H V
+    hipLaunchKernelGGL(k_ut_diag, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, c->stream, k, Lut, k,
+                       a.tau);
     GEVP_HIP_TRY(hipGetLastError());
+    GEVP_TRY(diag_block_inverses(c, k, Lut, k, Dut, k));
+    GEVP_TRY(launch_zgemm(c, 1, 0, k, n, n, 1.0, a.V, a.ldv, Z, ldz, 0.0, nullptr, 0, 0.0, nullptr, 0,
+                          nullptr, Sut, k));
+    GEVP_TRY(trsm_left_lower_c(c, k, n, Lut, k, Dut, k, Sut, k, 0));
+    GEVP_TRY(launch_zgemm(c, 0, 0, n, n, k, -1.0, a.V, a.ldv, Sut, k, 1.0, Z, ldz, 0.0, nullptr, 0,
+                          nullptr, Z, ldz));
   }
   return GEVP_OK;
 }

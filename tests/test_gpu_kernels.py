@@ -241,6 +241,37 @@ def test_heev_replayed_sequence(h):
     h2.close()
 
 
+@pytest.mark.parametrize("kind", ["diagonal", "real_tridiagonal", "blocks"])
+def test_heev_identity_reflectors(h, kind):
+    """Matrices whose tridiagonalisation meets identity reflectors (tau = 0:
+    nothing below the subdiagonal and a real subdiagonal entry): a real
+    diagonal, a real tridiagonal, and a block-diagonal matrix of dense complex
+    blocks and 1 x 1 blocks.  The back-transformation must leave those
+    reflectors out; eigenpairs against numpy's."""
+    n = 200
+    rng = np.random.default_rng(5)
+    if kind == "diagonal":
+        H = np.diag(rng.standard_normal(n)).astype(complex)
+    elif kind == "real_tridiagonal":
+        H = np.diag(rng.standard_normal(n)) + np.diag(rng.standard_normal(n - 1), 1)
+        H = (H + np.triu(H, 1).T).astype(complex)
+    else:
+        H = np.zeros((n, n), dtype=complex)
+        i = 0
+        for b in (37, 1, 1, 64, 1, 50, 1, 45):
+            G = _cn(rng, b, b)
+            H[i:i + b, i:i + b] = 0.5 * (G + G.conj().T)
+            i += b
+        assert i == n
+    th, Z = h.heev(_dev(H))
+    th, Z = _np(th), _np(Z)
+    lam = np.linalg.eigvalsh(H)
+    nrm = max(1.0, np.max(np.abs(lam)))
+    assert np.max(np.abs(th - lam)) <= 1e-13 * nrm * np.sqrt(n)
+    assert np.max(np.abs(H @ Z - Z * th[None, :])) <= 1e-12 * nrm * np.sqrt(n)
+    assert np.max(np.abs(Z.conj().T @ Z - np.eye(n))) <= 1e-10
+
+
 @pytest.mark.parametrize("n", [40, 300])
 def test_heev_degenerate(h, oracle_mod, n):
     # repeated eigenvalues: an invariant subspace, not unique vectors
