@@ -395,6 +395,14 @@ gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t 
                                int64_t ldd, const double* alpha, const double* beta,
                                const double* gamma, const double* delta);
 
+/* y = M x for an n x n Hermitian M stored in full (device complex128,
+ * column-major, ld ldm >= n; only the 64 x 64 tiles on and below the diagonal
+ * are read), x and y device vectors of n complex128 (y must not overlap M or
+ * x).  The matrix-vector product of the Lanczos spectral bounds that set the
+ * Chebyshev filter's interval (section 3: the filter damps the unwanted part
+ * of the spectrum, whose ends the bounds estimate).  Asynchronous. */
+gevp_status gevp_k_hemv(gevp_handle h, int64_t n, const void* M, int64_t ldm, const void* x, void* y);
+
 /* In-place Cholesky of the lower triangle of the n x n Hermitian M (upper
  * triangle zeroed).  Synchronous; returns GEVP_ERR_NOT_HPD with *pivot
  * (1-based) on failure. */

@@ -250,7 +250,11 @@ gevp_status seed_monitor_stats(gevp_ctx* c, int64_t k, const zd* M, int64_t ldm,
 gevp_status launch_gather_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                                const int* perm, zd* D, int64_t ldd);
 gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* X, int64_t ldx);
-gevp_status launch_hemv_cols(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y);
+// y = M x for a Hermitian M stored in full (only the tiles on and below the
+// diagonal are read); work >= hemv_work_bytes(n) (partial vectors)
+size_t hemv_work_bytes(int64_t n);
+gevp_status launch_hemv(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y,
+                        void* work);
 gevp_status launch_add_diag(gevp_ctx* c, int64_t n, zd* M, int64_t ldm, const double* shift);
 gevp_status launch_scale_cols(gevp_ctx* c, int64_t rows, int64_t cols, const zd* S, int64_t lds,
                               const double* w, zd* D, int64_t ldd);

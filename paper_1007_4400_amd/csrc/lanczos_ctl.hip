@@ -56,29 +56,59 @@ __device__ double bsum1024(double v, double* sh) {
 }
 
 // w = M v_j (given); alpha_j = Re(v_j^H w); w -= alpha_j v_j + beta_{j-1} v_{j-1};
-// beta_j = ||w||; v_{j+1} = w / beta_j
+// beta_j = ||w||; v_{j+1} = w / beta_j.  Up to LV * 1024 entries are held in
+// registers (all loads of a chunk in flight at once); longer vectors go
+// through in chunks, re-reading them per pass.
+constexpr int LV = 8;
 __global__ __launch_bounds__(1024) void k_lanczos_vec(int64_t n, const zd* vprev, const zd* vcur,
                                                       const zd* w, zd* vnext, double* alpha,
                                                       double* beta, int j) {
   __shared__ double sh[16];
+  const int64_t t = threadIdx.x, chunk = 1024 * LV;
+  const bool one = n <= chunk;  // uniform
+  zd vv[LV], ww[LV], pv[LV];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int64_t i = i0 + t + 1024 * u;
+      const bool in = i < n;
+      vv[u] = in ? vcur[i] : make_double2(0.0, 0.0);
+      ww[u] = in ? w[i] : make_double2(0.0, 0.0);
+      pv[u] = (in && j > 0) ? vprev[i] : make_double2(0.0, 0.0);
+    }
+  };
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) s += vcur[i].x * w[i].x + vcur[i].y * w[i].y;
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    load(i0);
+#pragma unroll
+    for (int u = 0; u < LV; ++u) s += vv[u].x * ww[u].x + vv[u].y * ww[u].y;
+  }
   const double a = bsum1024(s, sh);
   const double bp = (j > 0) ? beta[j - 1] : 0.0;
+  zd rr[LV];
   double q = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    double rx = w[i].x - a * vcur[i].x, ry = w[i].y - a * vcur[i].y;
-    if (j > 0) {
-      rx -= bp * vprev[i].x;
-      ry -= bp * vprev[i].y;
+  for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+    if (!one) load(i0);
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      rr[u] = make_double2(ww[u].x - a * vv[u].x - bp * pv[u].x, ww[u].y - a * vv[u].y - bp * pv[u].y);
+      q += rr[u].x * rr[u].x + rr[u].y * rr[u].y;
+      const int64_t i = i0 + t + 1024 * u;
+      if (!one && i < n) vnext[i] = rr[u];
     }
-    vnext[i] = make_double2(rx, ry);
-    q += rx * rx + ry * ry;
   }
   const double b = sqrt(bsum1024(q, sh));
   const double inv = (b > 0.0) ? 1.0 / b : 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) vnext[i] = make_double2(vnext[i].x * inv, vnext[i].y * inv);
-  if (threadIdx.x == 0) {
+  if (one) {
+#pragma unroll
+    for (int u = 0; u < LV; ++u) {
+      const int64_t i = t + 1024 * u;
+      if (i < n) vnext[i] = make_double2(rr[u].x * inv, rr[u].y * inv);
+    }
+  } else {
+    for (int64_t i = t; i < n; i += 1024) vnext[i] = make_double2(vnext[i].x * inv, vnext[i].y * inv);
+  }
+  if (t == 0) {
     alpha[j] = a;
     beta[j] = b;
   }
@@ -301,7 +331,7 @@ size_t lanczos_work_bytes(int64_t n, int steps) {
   if (steps > 64) steps = 64;
   return ws_round(sizeof(zd) * n * 4) + 2 * ws_round(sizeof(double) * (steps + 1)) +
          ws_round(sizeof(double) * 64) + ws_round(sizeof(double) * 64 * 64) +
-         tridiag_eig_work_bytes(64);
+         tridiag_eig_work_bytes(64) + hemv_work_bytes(n);
 }
 
 gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int steps,
@@ -321,6 +351,8 @@ gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int
   double* Zt = (double*)w;  // eigenvectors of the tridiagonal, row-major
   w += ws_round(sizeof(double) * 64 * 64);
   void* tw = w;
+  w += tridiag_eig_work_bytes(64);
+  void* hw = w;  // partial vectors of the matrix-vector products
   zd* buf[3] = {V, V + n, V + 2 * n};
   zd* wv = V + 3 * n;
   GEVP_TRY(launch_randn(c, n, 1, buf[0], n, 0, seed));
@@ -330,7 +362,7 @@ gevp_status lanczos_bounds(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, int
     zd* vc = buf[j % 3];
     zd* vp = buf[(j + 2) % 3];
     zd* vn = buf[(j + 1) % 3];
-    GEVP_TRY(launch_hemv_cols(c, n, M, ldm, vc, wv));
+    GEVP_TRY(launch_hemv(c, n, M, ldm, vc, wv, hw));
     hipLaunchKernelGGL(k_lanczos_vec, dim3(1), dim3(1024), 0, c->stream, n, vp, vc, wv, vn, alpha,
                        beta, j);
     GEVP_HIP_TRY(hipGetLastError());

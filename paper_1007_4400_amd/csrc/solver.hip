@@ -1425,6 +1425,14 @@ gevp_status gevp_k_filter_gemm(gevp_handle h, int precision, int64_t n, int64_t 
                                gamma, delta);
 }
 
+gevp_status gevp_k_hemv(gevp_handle h, int64_t n, const void* M, int64_t ldm, const void* x, void* y) {
+  if (!h || n < 1 || !M || ldm < n || !x || !y) return GEVP_ERR_INVALID;
+  GEVP_HIP_TRY(hipSetDevice(h->device));
+  GEVP_TRY(ws_reserve(h, hemv_work_bytes(n) + 256));
+  void* w = ws_take(h, hemv_work_bytes(n));
+  return launch_hemv(h, n, (const zd*)M, ldm, (const zd*)x, (zd*)y, w);
+}
+
 gevp_status gevp_k_potrf(gevp_handle h, int64_t n, void* M, int64_t ldm, int64_t* pivot) {
   if (!h || n < 1 || !M || ldm < n) return GEVP_ERR_INVALID;
   GEVP_HIP_TRY(hipSetDevice(h->device));

@@ -557,23 +557,128 @@ __global__ __launch_bounds__(256) void k_phase_normalize(int64_t rows, zd* X, in
   }
 }
 
-// y_i = sum_j conj(M(j, i)) x_j, which is (M x)_i for Hermitian M: one wave
-// per output entry reads column i contiguously.
-__global__ __launch_bounds__(256) void k_hemv_cols(int64_t n, const zd* M, int64_t ldm, const zd* x,
-                                                   zd* y) {
-  const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const zd* col = M + i * ldm;
-  double sr = 0.0, si = 0.0;
-  for (int64_t j = lane; j < n; j += 64) {
-    const zd a = col[j], b = x[j];
-    sr += a.x * b.x + a.y * b.y;
-    si += a.x * b.y - a.y * b.x;
+// y = M x for a Hermitian M stored in full, reading only the 64 x 64 tiles on
+// and below the diagonal: the tile (I, J), I > J, gives y_I += T x_J and
+// y_J += T^H x_I, a diagonal tile y_I += T x_I.  One work-group per tile
+// (lane = row, each wave 16 columns, loads first) writes its two partial
+// 64-vectors; k_hemv_reduce sums, for every block I, the partials of the
+// tiles in block row I and block column I.  Half the bytes of a column-by-
+// column product.
+constexpr int HV = 64;  // tile order
+__device__ __forceinline__ int64_t hv_pair(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
+
+__global__ __launch_bounds__(256) void k_hemv_tiles(int64_t n, const zd* M, int64_t ldm, const zd* x,
+                                                    zd* P1, zd* P2) {
+  __shared__ zd xs[2][HV];
+  __shared__ zd ys[4][HV];
+  const int64_t p = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > p) --I;  // correct the rounding of the root
+  while ((I + 1) * (I + 2) / 2 <= p) ++I;
+  const int64_t J = p - I * (I + 1) / 2;
+  const int64_t r0 = I * HV, c0 = J * HV;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // every global load of the tile in flight before the first is used: the
+  // matrix entries (indices clamped into the matrix, out-of-range entries
+  // zeroed after the load) and the two slices of x
+  const int64_t row = r0 + lane, rowc = min(row, n - 1);
+  zd a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t col = c0 + wave * 16 + q;
+    a[q] = M[rowc + min(col, n - 1) * ldm];
   }
-  sr = wave_sum(sr);
-  si = wave_sum(si);
-  if (lane == 0) y[i] = make_double2(sr, si);
+  const zd xj = x[min(c0 + lane, n - 1)], xi = x[min(r0 + lane, n - 1)];
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (row >= n || c0 + wave * 16 + q >= n) a[q] = make_double2(0.0, 0.0);
+  if (tid < HV) {
+    xs[0][tid] = (c0 + tid < n) ? xj : make_double2(0.0, 0.0);  // x_J
+    xs[1][tid] = (r0 + tid < n) ? xi : make_double2(0.0, 0.0);  // x_I
+  }
+  __syncthreads();
+  // y_I partial: the lane's row over the wave's 16 columns
+  double yr = 0.0, yi = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const zd v = xs[0][wave * 16 + q];
+    yr += a[q].x * v.x - a[q].y * v.y;
+    yi += a[q].x * v.y + a[q].y * v.x;
+  }
+  ys[wave][lane] = make_double2(yr, yi);
+  if (I != J) {
+    // y_J partial for the wave's 16 columns: sum over the 64 rows of
+    // conj(T(r, c)) x_I(r), a reduce-scatter over the lanes (after the four
+    // halving steps lane l holds column (l >> 2) summed over 16 lanes)
+    const zd xi = xs[1][lane];
+    double vr[16], vi[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      vr[q] = a[q].x * xi.x + a[q].y * xi.y;
+      vi[q] = a[q].x * xi.y - a[q].y * xi.x;
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int o = 32 >> st, m = 16 >> st, h = m >> 1;
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q < h) {
+          const double sr = up ? vr[q] : vr[q + h], si = up ? vi[q] : vi[q + h];
+          const double kr = up ? vr[q + h] : vr[q], ki = up ? vi[q + h] : vi[q];
+          vr[q] = kr + __shfl_xor(sr, o, 64);
+          vi[q] = ki + __shfl_xor(si, o, 64);
+        }
+      }
+    }
+    double tr = vr[0], ti = vi[0];
+    tr += __shfl_xor(tr, 2, 64);
+    ti += __shfl_xor(ti, 2, 64);
+    tr += __shfl_xor(tr, 1, 64);
+    ti += __shfl_xor(ti, 1, 64);
+    if ((lane & 3) == 0) P2[p * HV + wave * 16 + (lane >> 2)] = make_double2(tr, ti);
+  }
+  __syncthreads();
+  if (tid < HV) {
+    zd t = ys[0][tid];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      t.x += ys[w][tid].x;
+      t.y += ys[w][tid].y;
+    }
+    P1[p * HV + tid] = t;
+  }
+}
+
+// y_I = sum over the partials of block row I (tiles (I, J), J <= I) and of
+// block column I (tiles (K, I), K > I): nbk terms per row, split over four
+// thread groups, each with eight loads in flight.
+__global__ __launch_bounds__(256) void k_hemv_reduce(int64_t n, int64_t nbk, const zd* P1, const zd* P2,
+                                                     zd* y) {
+  __shared__ zd part[4][HV];
+  const int64_t I = blockIdx.x;
+  const int r = threadIdx.x & (HV - 1), g = threadIdx.x >> 6;
+  double sr = 0.0, si = 0.0;
+  for (int64_t k0 = g; k0 < nbk; k0 += 4 * 8) {
+    zd v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = min(k0 + 4 * u, nbk - 1);  // clamped: every load valid
+      v[u] = (k <= I) ? P1[hv_pair(I, k) * HV + r] : P2[hv_pair(k, I) * HV + r];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + 4 * u < nbk) {
+        sr += v[u].x;
+        si += v[u].y;
+      }
+  }
+  part[g][r] = make_double2(sr, si);
+  __syncthreads();
+  if (g == 0 && I * HV + r < n) {
+    const zd a = part[0][r], b = part[1][r], c = part[2][r], d = part[3][r];
+    y[I * HV + r] = make_double2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
+  }
 }
 
 __global__ void k_add_diag(int64_t n, zd* M, int64_t ldm, const double* shift) {
@@ -755,10 +860,20 @@ gevp_status launch_phase_normalize(gevp_ctx* c, int64_t rows, int64_t cols, zd* 
   return GEVP_OK;
 }
 
-gevp_status launch_hemv_cols(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y) {
+size_t hemv_work_bytes(int64_t n) {
+  const int64_t nbk = (n + HV - 1) / HV;
+  return 2 * ws_round(sizeof(zd) * HV * (size_t)(nbk * (nbk + 1) / 2));
+}
+
+gevp_status launch_hemv(gevp_ctx* c, int64_t n, const zd* M, int64_t ldm, const zd* x, zd* y,
+                        void* work) {
   if (n <= 0) return GEVP_OK;
-  hipLaunchKernelGGL(k_hemv_cols, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, n, M, ldm,
-                     x, y);
+  const int64_t nbk = (n + HV - 1) / HV, pairs = nbk * (nbk + 1) / 2;
+  zd* P1 = (zd*)work;
+  zd* P2 = (zd*)((char*)work + ws_round(sizeof(zd) * HV * (size_t)pairs));
+  hipLaunchKernelGGL(k_hemv_tiles, dim3((unsigned)pairs), dim3(256), 0, c->stream, n, M, ldm, x, P1, P2);
+  GEVP_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_hemv_reduce, dim3((unsigned)nbk), dim3(256), 0, c->stream, n, nbk, P1, P2, y);
   GEVP_HIP_TRY(hipGetLastError());
   return GEVP_OK;
 }

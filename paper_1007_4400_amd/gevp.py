@@ -146,6 +146,8 @@ def load():
     lib.gevp_k_zgemm_tri.restype = I
     lib.gevp_k_filter_gemm.argtypes = [P, I, L, L, P, L, P, L, P, L, P, L, P, L, P, P, P, P]
     lib.gevp_k_filter_gemm.restype = I
+    lib.gevp_k_hemv.argtypes = [P, L, P, L, P, P]
+    lib.gevp_k_hemv.restype = I
     lib.gevp_k_potrf.argtypes = [P, L, P, L, ctypes.POINTER(L)]
     lib.gevp_k_potrf.restype = I
     lib.gevp_k_trsm.argtypes = [P, C, C, L, L, P, L, P, L]
@@ -574,6 +576,19 @@ class Handle:
         if s != GEVP_OK:
             raise GevpError(s, "gevp_k_filter_gemm")
         return D
+
+    def hemv(self, M, x):
+        """y = M x for a Hermitian M stored in full (gevp_k_hemv)."""
+        M = _check_mat(M, "M", self.device, square=True)
+        n = M.shape[0]
+        x = _check_vec(x, "x", self.device, n, dtype=torch.complex128)[:n]
+        x = x.resolve_conj().resolve_neg().contiguous()
+        y = torch.empty_like(x)
+        self._stream()
+        s = self.lib.gevp_k_hemv(self.h, n, _ptr(M), _ld(M), _ptr(x), _ptr(y))
+        if s != GEVP_OK:
+            raise GevpError(s, "gevp_k_hemv")
+        return y
 
     def potrf(self, M):
         """In-place lower Cholesky on a column-major copy; returns (L, pivot)."""

@@ -241,6 +241,33 @@ def test_heev_replayed_sequence(h):
     h2.close()
 
 
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 130, 1000, 2049])
+def test_hemv_lower_tiles(h, n):
+    """gevp_k_hemv (the Lanczos bounds' matrix-vector product) against a host
+    product: y = H x for a random Hermitian H whose tiles strictly above the
+    diagonal 64 x 64 blocks are overwritten with NaN (they must not be read),
+    ragged orders included, and once with a padded leading dimension."""
+    from paper_1007_4400_amd import gevp
+
+    rng = np.random.default_rng(n)
+    G = _cn(rng, n, n)
+    H = 0.5 * (G + G.conj().T)
+    x = _cn(rng, n, 1)[:, 0]
+    ref = H @ x
+    M = H.copy()
+    for I in range((n + 63) // 64):
+        for J in range(I + 1, (n + 63) // 64):
+            M[I * 64:(I + 1) * 64, J * 64:(J + 1) * 64] = np.nan
+    for pad in (0, 3) if n in (65, 1000) else (0,):
+        Md = gevp.empty_colmajor(n + pad, n, device="cuda")
+        Md.copy_(torch.from_numpy(np.vstack([M, np.zeros((pad, n), dtype=complex)])))
+        y = h.hemv(Md[:n], torch.from_numpy(x).to("cuda"))
+        yh = _np(y)
+        assert np.all(np.isfinite(yh))
+        err = np.max(np.abs(yh - ref)) / max(1.0, np.max(np.abs(ref)))
+        assert err <= 1e-13 * max(1.0, np.sqrt(n)), (pad, err)
+
+
 @pytest.mark.parametrize("kind", ["diagonal", "real_tridiagonal", "blocks"])
 def test_heev_identity_reflectors(h, kind):
     """Matrices whose tridiagonalisation meets identity reflectors (tau = 0:
