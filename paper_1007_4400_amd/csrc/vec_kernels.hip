@@ -1,7 +1,8 @@
 // Bandwidth-bound helper kernels: input mirroring and scans, transposes,
 // column norms and residual norms (wave64 reductions), column gathers,
 // counter-based random fill, phase normalisation, Hermitian matrix-vector
-// products for the Lanczos bounds.
+// products for the Lanczos bounds; and the seed monitor's statistics with
+// its angle-minimising matching (one work-group).
 #include <algorithm>
 #include <cmath>
 #include <vector>
