@@ -227,6 +227,68 @@ def rocprof_summary(db_path, kernel_substr="k_cgemm_bf16x3_filter", region="time
     return "\n".join(lines)
 
 
+def rocprof_breakdown(db_path, region="timed", families=("k_zgemm", "k_cgemm_bf16x3_filter")):
+    """Kernel totals inside the roctx range `region` of a --kernel-trace
+    database (every stream), the FP64 GEMM launches by work-groups per launch,
+    and, for each kernel family, the wall time during which at least one of
+    its kernels runs (the union of its launch intervals) next to its summed
+    kernel time: with several streams their ratio is the family's average
+    concurrency."""
+    import sqlite3
+    from collections import defaultdict
+
+    cur = sqlite3.connect(db_path).cursor()
+    reg = _regions(cur)
+    if region not in reg:
+        return f"no roctx range '{region}' in {db_path}"
+    w0, w1 = reg[region]
+    rows = cur.execute("select name, grid_x / workgroup_x, start, end from kernels "
+                       "where start >= ? and end <= ? order by start", (w0, w1)).fetchall()
+
+    def short(name):
+        return name.split("::")[1].split("(")[0] if "::" in name else name[:40]
+
+    def union(iv):
+        tot, cs, ce = 0, None, None
+        for s, e in sorted(iv):
+            if ce is None or s > ce:
+                if ce is not None:
+                    tot += ce - cs
+                cs, ce = s, e
+            else:
+                ce = max(ce, e)
+        return tot + (ce - cs if ce is not None else 0)
+
+    lines = [f"roctx range '{region}': {(w1 - w0) / 1e6:.1f} ms; {len(rows)} kernels inside it, "
+             f"busy (any kernel running) {union([(s, e) for _, _, s, e in rows]) / 1e6:.1f} ms",
+             "kernel totals inside it (all streams):"]
+    agg = defaultdict(lambda: [0, 0])
+    for name, _, s, e in rows:
+        agg[short(name)][0] += 1
+        agg[short(name)][1] += e - s
+    for k, (n, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:25]:
+        lines.append(f"  {k:32s} n={n:6d} total={t / 1e6:9.2f} ms avg={t / n / 1e6:.4f} ms")
+    lines.append("FP64 GEMM launches by work-groups per launch:")
+    agg2 = defaultdict(lambda: [0, 0])
+    for name, g, s, e in rows:
+        if "k_zgemm" not in name:
+            continue
+        b = ("<64" if g < 64 else "<256" if g < 256 else "<1024" if g < 1024 else "<4096" if g < 4096
+             else ">=4096")
+        agg2[(short(name), b)][0] += 1
+        agg2[(short(name), b)][1] += e - s
+    for (k, b), (n, t) in sorted(agg2.items(), key=lambda x: -x[1][1]):
+        lines.append(f"  {k:24s} grid {b:7s} n={n:6d} total={t / 1e6:8.2f} ms avg={t / n / 1e6:.4f} ms")
+    for fam in families:
+        iv = [(s, e) for name, _, s, e in rows if fam in name]
+        if iv:
+            u, t = union(iv), sum(e - s for s, e in iv)
+            lines.append(f"family {fam}: {len(iv)} launches, summed kernel time {t / 1e6:.1f} ms, "
+                         f"wall time with one or more running {u / 1e6:.1f} ms "
+                         f"({u / (w1 - w0):.1%} of the range), average concurrency {t / max(u, 1):.2f}")
+    return "\n".join(lines)
+
+
 def run_batched(args):
     """32 independent k-point pencils of uneven size (n ~ U[1500, 3000],
     nev = round(0.1 n), per-problem spectrum shift), 8 SCF steps each; one
@@ -268,10 +330,14 @@ def run_batched(args):
             log(f"autotuned: {tuning}")
         torch.cuda.synchronize()
         h.set_profiling(2 if k > 0 else 0)  # events around every filter launch of the timed steps
+        if k == 1:
+            _mark_push("timed")  # the batched solves of steps 1..7, for a profiler's trace
         ts = time.perf_counter()
         out = h.solve_batched(probs, tol=args.tol, opts=opts)
         torch.cuda.synchronize()
         dt = time.perf_counter() - ts
+        if k == 7:
+            _mark_pop()
         h.set_profiling(0)
         if k > 0:
             for o in out:
@@ -978,6 +1044,9 @@ def main():
                     help="batched: keep --streams and split-K by the cost model instead of autotuning")
     ap.add_argument("--rocprof-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
     ap.add_argument("--summary-kernel", default=None, help="kernel name for --rocprof-summary")
+    ap.add_argument("--rocprof-breakdown", metavar="DB",
+                    help="kernel totals and family concurrency inside the 'timed' range of a "
+                         "rocprofv3 kernel-trace database, and exit")
     ap.add_argument("--host-qr", action="store_true",
                     help="factor the generator's Gaussian matrix on the host (for counter runs)")
     ap.add_argument("--pmc-last", type=int, default=0,
@@ -992,6 +1061,9 @@ def main():
     if args.rocprof_summary:
         print(rocprof_summary(args.rocprof_summary, args.summary_kernel or FILTER_KERNELS[args.precision],
                               pmc_last=args.pmc_last))
+        return
+    if args.rocprof_breakdown:
+        print(rocprof_breakdown(args.rocprof_breakdown))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus above 1 is not supported "
