@@ -279,6 +279,23 @@ def rocprof_breakdown(db_path, region="timed", families=("k_zgemm", "k_cgemm_bf1
         agg2[(short(name), b)][1] += e - s
     for (k, b), (n, t) in sorted(agg2.items(), key=lambda x: -x[1][1]):
         lines.append(f"  {k:24s} grid {b:7s} n={n:6d} total={t / 1e6:8.2f} ms avg={t / n / 1e6:.4f} ms")
+    # idle gaps (no kernel on any stream), the largest with the kernels around them
+    gaps, last_end, last_name = [], None, None
+    for name, _, st, en in rows:
+        if last_end is not None and st > last_end:
+            gaps.append((st - last_end, short(last_name), short(name)))
+        if last_end is None or en > last_end:
+            last_end, last_name = en, name
+    if gaps:
+        tot = sum(g[0] for g in gaps)
+        lines.append(f"idle gaps: {len(gaps)}, {tot / 1e6:.1f} ms in total; the largest "
+                     f"(after -> before):")
+        by_pair = defaultdict(lambda: [0, 0])
+        for d, a, b in gaps:
+            by_pair[(a, b)][0] += 1
+            by_pair[(a, b)][1] += d
+        for (a, b), (k, d) in sorted(by_pair.items(), key=lambda x: -x[1][1])[:12]:
+            lines.append(f"  {a:28s} -> {b:28s} n={k:5d} total={d / 1e6:7.2f} ms")
     for fam in families:
         iv = [(s, e) for name, _, s, e in rows if fam in name]
         if iv:

@@ -43,6 +43,9 @@ def test_breakdown_totals_and_concurrency(tmp_path):
     assert "busy (any kernel running) 0.6 ms" in out
     assert "k_zgemm<0>                       n=     2 total=     0.50 ms" in out
     assert "grid <256    n=     1" in out and "grid >=4096  n=     1" in out
+    # one idle gap, 0.5 -> 0.6 ms, between the filter and the GEMM
+    assert "idle gaps: 1, 0.1 ms in total" in out
+    assert "k_cgemm_bf16x3_filter        -> k_zgemm<0>" in out
     # filter: summed 0.5 ms over a union of 0.4 ms -> concurrency 1.25
     assert ("family k_cgemm_bf16x3_filter: 2 launches, summed kernel time 0.5 ms, wall time with one "
             "or more running 0.4 ms (40.0% of the range), average concurrency 1.25") in out
