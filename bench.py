@@ -100,14 +100,15 @@ KERNEL_SOURCES = {"k_cgemm_bf16x3_filter": "paper_1007_4400_amd/csrc/cgemm_bf16.
                   "k_upd_apply": "paper_1007_4400_amd/csrc/update.hip"}
 
 
-def committed_traffic(kernel, workload="n8192_nev820_seq12"):
+def committed_traffic(kernel, workload="n8192_nev820_seq12", root=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<kernel>_<workload>_hbm_counters.txt), or None when there is
-    none or the kernel's source has changed since the counters were taken
-    (the summary records the source's SHA-256)."""
+    (profiles/<kernel>_<workload>_hbm_counters.txt under `root`, the
+    repository by default), or None when there is none or the kernel's source
+    has changed since the counters were taken (the summary records the
+    source's SHA-256)."""
     import hashlib
 
-    here = os.path.dirname(os.path.abspath(__file__))
+    here = root or os.path.dirname(os.path.abspath(__file__))
     prof = os.path.join(here, "profiles", f"{kernel}_{workload}_hbm_counters.txt")
     src = KERNEL_SOURCES.get(kernel)
     if not src or not os.path.exists(prof):
